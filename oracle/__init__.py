@@ -1,0 +1,310 @@
+"""CPU FP64 oracle for the steric-constraint step (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may use this package; the product library never does.  It
+shares no code with the HIP library.  The arithmetic lives in
+``rodlcp_oracle.c`` (plain sequential C, double precision); this file only
+marshals numpy arrays.  ``crosscheck.py`` adds dense cross-check solvers for
+tiny systems.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rodlcp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+IMG_ZERO = 0x888
+FLAG_CUTOFF, FLAG_PARALLEL, FLAG_DEGENERATE = 1, 2, 4
+OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC", "-shared",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = C.CDLL(_LIB)
+            P = C.c_void_p
+            I64 = C.c_int64
+            D = C.c_double
+            lib.ora_img_pack.argtypes = [C.c_int, C.c_int, C.c_int]
+            lib.ora_img_pack.restype = C.c_int
+            lib.ora_rotation.argtypes = [P, P]
+            lib.ora_directors.argtypes = [I64, P, P]
+            lib.ora_psi_times.argtypes = [P, P, P]
+            lib.ora_mobility_coeffs.argtypes = [D, D, D, P]
+            lib.ora_mobility_block.argtypes = [P, D, D, D, P]
+            lib.ora_apply_mobility.argtypes = [I64, P, P, D, D, D, P, P]
+            lib.ora_closest_flat.argtypes = [P, P, D, P, P, D, P]
+            for fn in (lib.ora_pairs_brute, lib.ora_pairs_cells):
+                fn.argtypes = [I64, P, P, P, D, P, D, D, I64, P, P, P, P]
+                fn.restype = I64
+            lib.ora_assemble.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P]
+            lib.ora_dense_D.argtypes = [I64, P, I64, P, P, P, P, P]
+            lib.ora_apply_Mc.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P]
+            lib.ora_velocity.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P]
+            lib.ora_bbpgd.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, D, I64, P, P, P]
+            lib.ora_bbpgd.restype = C.c_int
+            lib.ora_integrate.argtypes = [I64, P, D, P, P, P, P]
+            _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _len_args(length, n):
+    """(len array or None, uniform length)."""
+    if length is None:
+        raise ValueError("length required")
+    if np.isscalar(length):
+        return None, float(length)
+    arr = _f64(length)
+    if arr.shape != (n,):
+        raise ValueError("length shape")
+    return arr, 0.0
+
+
+def _box3(box) -> np.ndarray:
+    b = np.asarray(box, dtype=np.float64).reshape(-1)
+    return _f64(np.repeat(b, 3) if b.size == 1 else b)
+
+
+# --- geometry ----------------------------------------------------------------
+
+def img_pack(nx: int, ny: int, nz: int) -> int:
+    return int(_load().ora_img_pack(nx, ny, nz))
+
+
+def img_unpack(img) -> np.ndarray:
+    img = np.asarray(img, dtype=np.int64)
+    return np.stack([((img >> 8) & 15) - 8, ((img >> 4) & 15) - 8, (img & 15) - 8], axis=-1)
+
+
+def rotation(quat) -> np.ndarray:
+    q = _f64(quat)
+    R = np.empty(9)
+    _load().ora_rotation(_p(q), _p(R))
+    return R.reshape(3, 3)
+
+
+def directors(quat) -> np.ndarray:
+    q = _f64(quat)
+    n = q.shape[0]
+    d = np.empty((n, 3))
+    _load().ora_directors(n, _p(q), _p(d))
+    return d
+
+
+def psi_times(quat, omega) -> np.ndarray:
+    q, w = _f64(quat), _f64(omega)
+    out = np.empty(4)
+    _load().ora_psi_times(_p(q), _p(w), _p(out))
+    return out
+
+
+def mobility_coeffs(L: float, diam: float, eta: float) -> np.ndarray:
+    c = np.empty(4)
+    _load().ora_mobility_coeffs(L, diam, eta, _p(c))
+    return c
+
+
+def mobility_block(d, L: float, diam: float, eta: float) -> np.ndarray:
+    dd = _f64(d)
+    M = np.empty(36)
+    _load().ora_mobility_block(_p(dd), L, diam, eta, _p(M))
+    return M.reshape(6, 6)
+
+
+def apply_mobility(dir_, length, diam, eta, F) -> np.ndarray:
+    d = _f64(dir_)
+    n = d.shape[0]
+    la, l0 = _len_args(length, n)
+    Fa = _f64(F)
+    U = np.empty((n, 6))
+    _load().ora_apply_mobility(n, _p(d), _p(la), l0, diam, eta, _p(Fa), _p(U))
+    return U
+
+
+def closest(xi, di, Li, xj, dj, Lj):
+    """Closest points of two rod axes: (s, t, dist, e[3], flags)."""
+    out = np.empty(7)
+    a = [_f64(v) for v in (xi, di, xj, dj)]
+    _load().ora_closest_flat(_p(a[0]), _p(a[1]), float(Li), _p(a[2]), _p(a[3]), float(Lj), _p(out))
+    return out[0], out[1], out[2], out[3:6].copy(), int(out[6])
+
+
+@dataclass
+class Pairs:
+    pi: np.ndarray
+    pj: np.ndarray
+    img: np.ndarray
+    flags: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.pi.shape[0])
+
+
+def pairs(x, dir_, length, box, diam, cutoff, method: str = "auto") -> Pairs:
+    """Canonical near-contact pair list; 'brute' is the definition, 'cells'
+    an independent uniform-grid search (used for large n)."""
+    xa, d = _f64(x), _f64(dir_)
+    n = xa.shape[0]
+    la, l0 = _len_args(length, n)
+    b = _box3(box)
+    lib = _load()
+    if method == "auto":
+        method = "brute" if n <= 3000 else "cells"
+    fn = lib.ora_pairs_brute if method == "brute" else lib.ora_pairs_cells
+    cap = 16 * n + 64
+    while True:
+        pi = np.empty(cap, np.int32)
+        pj = np.empty(cap, np.int32)
+        img = np.empty(cap, np.int32)
+        fl = np.empty(cap, np.uint8)
+        cnt = fn(n, _p(xa), _p(d), _p(la), l0, _p(b), diam, cutoff, cap, _p(pi), _p(pj), _p(img), _p(fl))
+        if cnt <= cap:
+            return Pairs(pi[:cnt].copy(), pj[:cnt].copy(), img[:cnt].copy(), fl[:cnt].copy())
+        cap = int(cnt)
+
+
+@dataclass
+class Constraints:
+    phi: np.ndarray   # [nc]
+    e: np.ndarray     # [nc, 3]
+    arm: np.ndarray   # [nc, 2]
+    q: np.ndarray     # [nc]
+
+
+def assemble(x, dir_, length, box, diam, eta, dt, pr: Pairs, F) -> Constraints:
+    xa, d, Fa = _f64(x), _f64(dir_), _f64(F)
+    n = xa.shape[0]
+    la, l0 = _len_args(length, n)
+    b = _box3(box)
+    nc = pr.n
+    phi, q = np.empty(nc), np.empty(nc)
+    e, arm = np.empty((nc, 3)), np.empty((nc, 2))
+    pi, pj, img = _i32(pr.pi), _i32(pr.pj), _i32(pr.img)
+    _load().ora_assemble(n, _p(xa), _p(d), _p(la), l0, _p(b), diam, eta, dt, nc, _p(pi), _p(pj), _p(img),
+                         _p(Fa), _p(phi), _p(e), _p(arm), _p(q))
+    return Constraints(phi, e, arm, q)
+
+
+def dense_D(dir_, pr: Pairs, cs: Constraints) -> np.ndarray:
+    d = _f64(dir_)
+    n, nc = d.shape[0], pr.n
+    D = np.empty((6 * n, nc))
+    _load().ora_dense_D(n, _p(d), nc, _p(_i32(pr.pi)), _p(_i32(pr.pj)), _p(_f64(cs.e)), _p(_f64(cs.arm)), _p(D))
+    return D
+
+
+def apply_Mc(dir_, length, diam, eta, pr: Pairs, cs: Constraints, gamma, add_q: bool = True) -> np.ndarray:
+    d = _f64(dir_)
+    n, nc = d.shape[0], pr.n
+    la, l0 = _len_args(length, n)
+    g = _f64(gamma)
+    w = np.empty(nc)
+    q = _f64(cs.q) if add_q else None
+    _load().ora_apply_Mc(n, _p(d), _p(la), l0, diam, eta, nc, _p(_i32(pr.pi)), _p(_i32(pr.pj)),
+                         _p(_f64(cs.e)), _p(_f64(cs.arm)), _p(q), _p(g), _p(w))
+    return w
+
+
+def velocity(dir_, length, diam, eta, pr: Pairs, cs: Constraints, gamma, F) -> np.ndarray:
+    d = _f64(dir_)
+    n, nc = d.shape[0], pr.n
+    la, l0 = _len_args(length, n)
+    U = np.empty((n, 6))
+    _load().ora_velocity(n, _p(d), _p(la), l0, diam, eta, nc, _p(_i32(pr.pi)), _p(_i32(pr.pj)),
+                         _p(_f64(cs.e)), _p(_f64(cs.arm)), _p(_f64(gamma)), _p(_f64(F)), _p(U))
+    return U
+
+
+@dataclass
+class SolveResult:
+    gamma: np.ndarray
+    g: np.ndarray
+    iterations: int
+    residual: float
+    alpha0: float
+    status: int
+
+
+def bbpgd(dir_, length, diam, eta, pr: Pairs, cs: Constraints, tol=1e-8, max_iter=100_000,
+          gamma0=None) -> SolveResult:
+    d = _f64(dir_)
+    n, nc = d.shape[0], pr.n
+    la, l0 = _len_args(length, n)
+    gamma = np.zeros(nc) if gamma0 is None else _f64(gamma0).copy()
+    g = np.empty(nc)
+    info = np.zeros(3)
+    st = _load().ora_bbpgd(n, _p(d), _p(la), l0, diam, eta, nc, _p(_i32(pr.pi)), _p(_i32(pr.pj)),
+                           _p(_f64(cs.e)), _p(_f64(cs.arm)), _p(_f64(cs.q)), tol, int(max_iter),
+                           _p(gamma), _p(g), _p(info))
+    return SolveResult(gamma, g, int(info[0]), float(info[1]), float(info[2]), int(st))
+
+
+def integrate(box, dt, U, x, quat, xu=None):
+    """In place: x, quat (and xu if given) advance by one step."""
+    b = _box3(box)
+    n = x.shape[0]
+    for a in (U, x, quat) + ((xu,) if xu is not None else ()):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().ora_integrate(n, _p(b), float(dt), _p(U), _p(x), _p(xu), _p(quat))
+
+
+# --- one whole step ------------------------------------------------------------
+
+@dataclass
+class StepResult:
+    dir: np.ndarray
+    pairs: Pairs
+    cons: Constraints
+    solve: SolveResult
+    U: np.ndarray
+
+
+def step_solve(sys, tol=None, max_iter=100_000, pair_method="auto") -> StepResult:
+    """Directors, pairs, constraint geometry, BBPGD and U for one rod system
+    (an object with x, quat, length, force, box, diam, cutoff, eta, dt)."""
+    tol = 1e-8 if tol is None else tol
+    d = directors(sys.quat)
+    L = sys.uniform_length if sys.uniform_length is not None else sys.length
+    pr = pairs(sys.x, d, L, sys.box, sys.diam, sys.cutoff, method=pair_method)
+    cs = assemble(sys.x, d, L, sys.box, sys.diam, sys.eta, sys.dt, pr, sys.force)
+    sr = bbpgd(d, L, sys.diam, sys.eta, pr, cs, tol=tol, max_iter=max_iter)
+    U = velocity(d, L, sys.diam, sys.eta, pr, cs, sr.gamma, sys.force)
+    return StepResult(d, pr, cs, sr, U)

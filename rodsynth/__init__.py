@@ -1,0 +1,170 @@
+"""Seeded synthetic rod suspensions.
+
+This module only draws inputs: rod centres, orientations (as unit
+quaternions), lengths and external forces/torques, plus the periodic box that
+a target volume fraction implies.  It holds none of the method's arithmetic
+(no directors, mobilities, distances or solver steps), so both the CPU oracle
+and the HIP library can be fed from it without sharing any code.
+
+The workloads follow the paper's filament suspensions (Section "Results":
+viscosity 0.01 pN s/um^2, timestep 1e-4 s; filament diameter 25 nm) at the
+sizes of the benchmark configurations below.  Units are um, s and pN.
+
+Draw order for one system: centres, orientations, lengths, forces, each from
+``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+ETA = 0.01          # pN s / um^2  (Section "Results")
+DT = 1.0e-4         # s
+DIAM = 0.025        # um, filament diameter
+CUTOFF = 0.05       # um, pair-search threshold on the surface gap
+TOL = 1.0e-8        # complementarity residual
+
+
+@dataclasses.dataclass
+class RodSystem:
+    """One periodic suspension.  Arrays are float64, row-major, host memory."""
+    x: np.ndarray            # [n, 3] centres, inside [0, box)
+    quat: np.ndarray         # [n, 4] unit quaternions [s, px, py, pz]
+    length: np.ndarray       # [n] rod lengths
+    force: np.ndarray        # [n, 6] external force (3) and torque (3)
+    box: float
+    diam: float = DIAM
+    cutoff: float = CUTOFF
+    eta: float = ETA
+    dt: float = DT
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def uniform_length(self) -> Optional[float]:
+        """The common length when all rods are equal, else None."""
+        if self.n and np.all(self.length == self.length[0]):
+            return float(self.length[0])
+        return None
+
+
+def spherocylinder_volume(length: np.ndarray, diam: float) -> np.ndarray:
+    """Volume of a cylinder of the given length capped by two hemispheres."""
+    return math.pi * diam * diam * length / 4.0 + math.pi * diam ** 3 / 6.0
+
+
+def box_for_volume_fraction(length: np.ndarray, diam: float, phi: float) -> float:
+    return float((spherocylinder_volume(length, diam).sum() / phi) ** (1.0 / 3.0))
+
+
+def _isotropic_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Haar-uniform rotations: a normalised 4-D Gaussian.  The rotated body
+    axis is then uniform on the sphere."""
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return q
+
+
+def _vmf_quaternions(rng: np.random.Generator, n: int, kappa: float) -> np.ndarray:
+    """Rotations whose image of the body z axis follows a von Mises-Fisher law
+    about z with concentration kappa, with a uniform twist about the rod's own
+    axis.  cos(polar angle) is drawn by the inverse CDF of Wood (1994)."""
+    u = rng.random(n)
+    w = 1.0 + np.log(u + (1.0 - u) * np.exp(-2.0 * kappa)) / kappa
+    w = np.clip(w, -1.0, 1.0)
+    phi = rng.random(n) * 2.0 * math.pi
+    twist = rng.random(n) * 2.0 * math.pi
+    beta = np.arccos(w)
+    # tilt: rotation by beta about the horizontal axis (-sin phi, cos phi, 0),
+    # twist: rotation by `twist` about z; composed as tilt * twist.
+    c1, s1 = np.cos(beta / 2), np.sin(beta / 2)
+    ax, ay = -np.sin(phi), np.cos(phi)
+    c2, s2 = np.cos(twist / 2), np.sin(twist / 2)
+    q = np.empty((n, 4))
+    q[:, 0] = c1 * c2
+    q[:, 1] = s1 * ax * c2 + s1 * ay * s2
+    q[:, 2] = s1 * ay * c2 - s1 * ax * s2
+    q[:, 3] = c1 * s2
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return q
+
+
+def make_system(n: int, *, seed: int, box: Optional[float] = None,
+                phi: Optional[float] = None, length=1.0,
+                orientation: str = "isotropic", kappa: float = 20.0,
+                diam: float = DIAM, cutoff: float = CUTOFF, eta: float = ETA,
+                dt: float = DT, force_scale: float = 1.0, name: str = "") -> RodSystem:
+    """Draw one suspension.  ``length`` is a number or a (lo, hi) uniform
+    range; give either ``box`` or the volume fraction ``phi``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # lengths are needed for the box before centres are placed, but are drawn
+    # from their own stream so the documented draw order of the main stream
+    # (centres, orientations, forces) does not depend on the length law.
+    lrng = np.random.Generator(np.random.PCG64([seed, 1]))
+    if isinstance(length, (tuple, list)):
+        lens = lrng.uniform(length[0], length[1], n)
+    else:
+        lens = np.full(n, float(length))
+    if box is None:
+        if phi is None:
+            raise ValueError("give box or phi")
+        box = box_for_volume_fraction(lens, diam, phi)
+    x = rng.random((n, 3)) * box
+    x = np.where(x >= box, 0.0, x)
+    if orientation == "isotropic":
+        quat = _isotropic_quaternions(rng, n)
+    elif orientation == "vmf":
+        quat = _vmf_quaternions(rng, n, kappa)
+    else:
+        raise ValueError(orientation)
+    force = rng.standard_normal((n, 6)) * force_scale
+    return RodSystem(x=np.ascontiguousarray(x), quat=np.ascontiguousarray(quat),
+                     length=lens, force=np.ascontiguousarray(force), box=float(box),
+                     diam=diam, cutoff=cutoff, eta=eta, dt=dt, name=name)
+
+
+# --- the benchmark workloads -------------------------------------------------
+
+def cfg_small(seed: int = 0) -> RodSystem:
+    """1,000 rods of length 1 in a periodic cube of side 4, isotropic."""
+    return make_system(1000, seed=seed, box=4.0, orientation="isotropic",
+                       name="rods1k_box4_iso")
+
+
+def cfg_paper_scale(seed: int = 0, n: int = 100_000) -> RodSystem:
+    """100,000 rods of length 1, volume fraction 0.05, nematic (vMF kappa=20
+    about z).  ``n`` may be lowered for a scaled-down copy at the same
+    density."""
+    return make_system(n, seed=seed, phi=0.05, orientation="vmf", kappa=20.0,
+                       name=f"rods{n // 1000}k_phi0.05_vmf20")
+
+
+def cfg_precision(seed: int = 0, n: int = 400_000) -> RodSystem:
+    """400,000 rods, lengths uniform in [0.5, 1.5], volume fraction 0.08,
+    isotropic."""
+    return make_system(n, seed=seed, phi=0.08, length=(0.5, 1.5),
+                       orientation="isotropic", name=f"rods{n // 1000}k_phi0.08_iso_L0.5-1.5")
+
+
+def cfg_batched(seed: int = 0, systems: int = 256, n_lo: int = 200,
+                n_hi: int = 20_000) -> List[RodSystem]:
+    """Independent periodic systems, rod counts log-uniform in [n_lo, n_hi],
+    volume fractions uniform in [0.02, 0.1], isotropic."""
+    rng = np.random.Generator(np.random.PCG64([seed, 7]))
+    counts = np.floor(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), systems))).astype(int)
+    phis = rng.uniform(0.02, 0.1, systems)
+    return [make_system(int(c), seed=seed * 100_003 + k, phi=float(p),
+                        orientation="isotropic", name=f"batch{k}")
+            for k, (c, p) in enumerate(zip(counts, phis))]
+
+
+def cfg_rollout(seed: int = 0, n: int = 50_000) -> RodSystem:
+    """50,000 rods of length 1, volume fraction 0.05, isotropic."""
+    return make_system(n, seed=seed, phi=0.05, orientation="isotropic",
+                       name=f"rods{n // 1000}k_phi0.05_iso")
