@@ -1,0 +1,186 @@
+#!/usr/bin/env python
+"""Throughput of the steric-constraint step on one MI355X.
+
+One step = one whole pass of the hot path on the 100,000-rod suspension
+(length 1, diameter 0.025, volume fraction 0.05, nematic: von Mises-Fisher
+kappa = 20 about z; external forces and torques N(0,1); dt = 1e-4; pair
+threshold 0.05 on the surface gap): directors, pair search, constraint
+geometry, the BBPGD solve to residual 1e-8 and the Euler update.  Every step
+starts from the same resident configuration (a device copy inside the timed
+region), so each step does the same work.
+
+Prints one JSON line: BBPGD iterations per second over the timed steps (the
+whole step is timed, pair search included), LCP solves per second, the
+roofline of the dominant solver kernel from HIP events sampled during the
+timed steps, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BBPGD iters/sec and LCP solves/sec at 100k rods; HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bbpgd_rods100k.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f) for f in ("rl_solver.hip",)]
+
+
+def kernel_bytes(n: int, nc: int) -> dict:
+    """Algorithmic bytes per launch: every array element the kernel must touch
+    once (FP64 values, int32 indices).
+    rod kernel:        per rod pptr+qptr 8, dir 24, V write 48       -> 80 n
+                       per constraint gamma 8, g 8, e 24, arm 16, qidx 4 -> 60 nc
+    constraint kernel: per constraint pi+pj 8, e 24, arm 16, q 8,
+                       gamma r/w 16, g r/w 16                        -> 88 nc
+                       per rod V read 48                             -> 48 n"""
+    return {"rod": 80 * n + 60 * nc, "con": 88 * nc + 48 * n}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(sysm, iters: int) -> dict:
+    import numpy as np  # noqa: F401
+
+    import oracle
+    d = oracle.directors(sysm.quat)
+    t0 = time.perf_counter()
+    pr = oracle.pairs(sysm.x, d, 1.0, sysm.box, sysm.diam, sysm.cutoff)
+    cs = oracle.assemble(sysm.x, d, 1.0, sysm.box, sysm.diam, sysm.eta, sysm.dt, pr, sysm.force)
+    t1 = time.perf_counter()
+    r = oracle.bbpgd(d, 1.0, sysm.diam, sysm.eta, pr, cs, tol=1e-8, max_iter=iters)
+    t2 = time.perf_counter()
+    # the start costs two products (g0 and the Cauchy step), like two iterations
+    per_iter = (t2 - t1) / (r.iterations + 2)
+    return {"value": 1.0 / per_iter, "unit": "BBPGD iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{r.iterations} BBPGD iterations (+2 start products) of the sequential FP64 C oracle on the "
+                      f"same {sysm.n}-rod system ({pr.n} constraints); pair search + assembly took "
+                      f"{t1 - t0:.2f} s and are not in the rate",
+            "pairs_assembly_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rods", type=int, default=100_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--profile-every", type=int, default=8, help="sample kernel events every k-th iteration")
+    ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations timed for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2109_08206_amd as rl
+    import rodsynth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    s = rodsynth.cfg_paper_scale(args.seed, n=args.rods)
+    x0 = torch.as_tensor(s.x, device=dev)
+    q0 = torch.as_tensor(s.quat, device=dev)
+    F = torch.as_tensor(s.force, device=dev)
+    x, q = torch.empty_like(x0), torch.empty_like(q0)
+    U = torch.empty((s.n, 6), dtype=torch.float64, device=dev)
+    slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8, max_iter=200_000)
+
+    def one_step():
+        x.copy_(x0)
+        q.copy_(q0)
+        return slv.step(x, q, 1.0, F=F, U=U)
+
+    for _ in range(args.warmup):
+        one_step()
+    slv.profile_enable(args.profile_every)
+    slv.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, npairs, res, status = 0, 0, 0.0, 0
+    for _ in range(args.steps):
+        _, info, npairs = one_step()
+        iters += info.iterations
+        res = max(res, info.residual)
+        status = max(status, info.status)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = slv.profile_read()
+    slv.profile_enable(0)
+
+    elapsed = t1 - t0
+    kb = kernel_bytes(s.n, npairs)
+    avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
+           "con": prof["con_ms"] / max(1, prof["con_launches"])}
+    names = {"rod": "k_rod<2,true>", "con": "k_con<2>"}
+    dom = max(avg, key=avg.get)
+    achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
+    traffic = measured_traffic(dom)
+    per_iter_bytes = kb["rod"] + kb["con"]
+    out = {
+        "metric": METRIC,
+        "value": iters / elapsed,
+        "unit": "BBPGD iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{s.n} rods L=1 d=0.025 phi=0.05 nematic vMF kappa=20, one whole step to "
+                               f"residual 1e-8 (pairs + geometry + BBPGD + update)",
+                   "rods": s.n, "constraints": npairs, "box": round(s.box, 4), "seed": args.seed},
+        "lcp_solves_per_s": args.steps / elapsed,
+        "iters_per_solve": iters / args.steps,
+        "max_residual": res,
+        "status": status,
+        "solver_alg_gbps": per_iter_bytes * iters / elapsed / 1e9,
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "alg_bytes_per_launch": kb[dom], "avg_launch_us": 1e3 * avg[dom]},
+        "kernels": {names[k]: {"avg_us": 1e3 * avg[k], "alg_bytes": kb[k],
+                               "alg_gbps": kb[k] / (avg[k] * 1e-3) / 1e9 if avg[k] > 0 else 0.0,
+                               "samples": prof[f"{k}_launches"]} for k in ("rod", "con")},
+    }
+    slv.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,186 @@
+/*
+ * rodlcp — steric-constraint step for rigid spherocylinder filaments on one
+ * AMD MI355X (gfx950) GPU.
+ *
+ * The method is the constraint-based collision handling of Yan et al.,
+ * "Towards the cellular-scale simulation of motor-driven cytoskeletal
+ * assemblies" (arXiv 2109.08206), unilateral (collision) constraints only:
+ *
+ *   * each rod has a centre x and a unit quaternion theta; velocities and
+ *     forces are 6-vectors per rod, U = M F with a block-diagonal mobility
+ *     (Section 3 "Filament dynamics"; Appendix "Filament dynamics");
+ *   * near-contact pairs are the rod pairs whose surface gap phi is below a
+ *     threshold (Appendix "Implementation");
+ *   * the force on a pair acts along the unit normal e at the closest points,
+ *     F_u = D_u gamma_u (eq. dmap, the column D_PQ of Appendix "Symmetry of
+ *     the geometrically constrained optimization problem");
+ *   * one linearised implicit Euler step (eq. constrainedeom_euler,
+ *     eq. linearconstraints) reduces to the complementarity problem
+ *     gamma >= 0, w = Mc gamma + q >= 0, gamma.w = 0, with Mc = D^T M D and
+ *     q = phi/h + D^T M F_ext (eq. blockdef, blocks A and B; eq. cqpdef),
+ *     solved by Barzilai-Borwein projected gradient descent (Section
+ *     "Instantiation in a massively parallel computing environment").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: um, s, pN.  All arrays are DEVICE pointers in the caller's
+ * allocation (e.g. torch tensors), row-major, double precision unless noted;
+ * the library never frees them and never keeps them past the call.  The
+ * library owns only its handle's workspace.  Work is enqueued on the
+ * handle's stream (rl_set_stream); entry points that return host values
+ * (counts, rl_solve_info) synchronise that stream before returning.
+ *
+ *   x[n][3]      rod centres, each coordinate inside [0, box)
+ *   quat[n][4]   unit quaternions [s, px, py, pz]; the rod axis is body z
+ *   dir[n][3]    unit directors R(theta) e_z
+ *   len[n]       rod lengths; or len == NULL and every rod has length len0
+ *   F[n][6]      external force (3) and torque (3) per rod
+ *   U[n][6]      translational (3) and angular (3) velocity per rod
+ *   pi, pj[nc]   int32 rod indices of each constraint, pi <= pj, sorted so
+ *                that pi is non-decreasing (canonical order below)
+ *   img[nc]      int32 packed periodic shift n of rod pj: rod pj is taken at
+ *                x_pj + n*box; img = ((nx+8)<<8) | ((ny+8)<<4) | (nz+8),
+ *                |n| <= 7, zero shift = 0x888; packed values order like
+ *                (nx, ny, nz) lexicographically
+ *   flags[nc]    uint8 bit 0: |phi - cutoff| <= 1e-9; bit 1: axes within
+ *                1e-10 of parallel (1 - (di.dj)^2 <= 1e-10); bit 2: axes
+ *                closer than 1e-12 (normal taken from di x dj)
+ *   phi[nc]      surface gap = axis distance - diam
+ *   e[nc][3]     unit normal at the closest points, pointing from rod pj
+ *                (imaged) to rod pi; gamma > 0 pushes them apart
+ *   arm[nc][2]   (s_i, s_j): arclength of the closest point on each axis
+ *                from its centre, |s| <= L/2; lever arm y = s * dir
+ *   q[nc]        phi/h + D^T M F
+ *   gamma[nc]    constraint force magnitudes (pN)
+ *
+ * Canonical pair order: ascending (pi, pj, img); a rod may pair with its own
+ * periodic image (pi == pj) only with a lexicographically positive shift.
+ *
+ * Return codes: 0 OK; > 0 warnings (outputs valid, solve not converged);
+ * < 0 errors (outputs undefined).  rl_status_str() names them and
+ * rl_last_error() gives the message of the last error on the calling thread.
+ */
+#ifndef RODLCP_H
+#define RODLCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RL_OK 0
+#define RL_NOT_CONVERGED 1  /* max_iter reached; gamma, U are the last iterate */
+#define RL_STAGNATED 2      /* BB step made no progress (gamma unchanged) above tol */
+#define RL_ERR_ARG (-1)     /* bad argument: NULL pointer, size, layout or value */
+#define RL_ERR_CAPACITY (-2)/* pair capacity too small; required count written */
+#define RL_ERR_NONFINITE (-3) /* NaN/Inf met in inputs or iterates */
+#define RL_ERR_HIP (-4)     /* a HIP runtime call failed */
+#define RL_ERR_NOMEM (-5)   /* workspace allocation failed */
+
+#define RL_FP64 0           /* all solver arithmetic in double precision */
+#define RL_FP32_MIXED 1     /* single-precision products, double reductions */
+
+typedef struct rl_ctx *rl_handle;
+
+typedef struct {
+    double box[3];      /* periodic box edges, > 0 (every system is periodic) */
+    double diam;        /* rod diameter, > 0 */
+    double cutoff;      /* keep pairs with phi < cutoff (strict), >= 0 */
+    double eta;         /* fluid viscosity, > 0 (pN s / um^2) */
+    double dt;          /* time step h, > 0 */
+    double tol;         /* BBPGD stops when max_c |min(gamma_c, w_c)| <= tol */
+    int64_t max_iter;   /* BBPGD iteration cap, >= 0 */
+    int32_t precision;  /* RL_FP64 or RL_FP32_MIXED */
+    int32_t check_every;/* iterations between host checks of the stop flag; 0 = default */
+} rl_params;
+
+typedef struct {
+    int64_t iterations; /* BBPGD iterations taken (products Mc*gamma in the loop) */
+    double residual;    /* max_c |min(gamma_c, w_c)| at exit */
+    double alpha0;      /* initial step length */
+    int32_t status;     /* RL_OK, RL_NOT_CONVERGED or RL_STAGNATED */
+    int32_t reserved;
+} rl_solve_info;
+
+/* Handle lifecycle.  rl_create copies *prm (validated: RL_ERR_ARG on a bad
+ * value) and binds the device that is current on the calling thread.  The
+ * default stream is the null stream. */
+int rl_create(rl_handle *h, const rl_params *prm);
+int rl_destroy(rl_handle h);
+int rl_set_params(rl_handle h, const rl_params *prm);
+int rl_get_params(rl_handle h, rl_params *prm);
+/* hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
+int rl_set_stream(rl_handle h, void *hip_stream);
+/* Pre-size the workspace for up to max_rods rods and max_pairs constraints
+ * so that later calls of that size allocate nothing. */
+int rl_reserve(rl_handle h, int64_t max_rods, int64_t max_pairs);
+const char *rl_status_str(int status);
+const char *rl_last_error(void);
+
+/* Directors dir = R(theta) e_z (Appendix "Filament dynamics": rotation
+ * matrix of the unit quaternion; the rod axis is body z). */
+int rl_directors(rl_handle h, int64_t n, const double *quat, double *dir);
+
+/* Near-contact pairs (Appendix "Implementation": only pairs whose minimal
+ * distance is below the threshold enter the solver; here phi < cutoff on
+ * the surface gap).  Writes the canonical list into pi, pj, img, flags
+ * (each of length capacity) and the count into *n_pairs (host).  If the
+ * count exceeds capacity nothing is written to the lists, *n_pairs holds
+ * the required count and RL_ERR_CAPACITY is returned.  RL_ERR_ARG if a
+ * centre lies outside [0, box) or box < (reach of two rods)/7 in any
+ * direction; RL_ERR_NONFINITE on NaN/Inf in x or dir.  Synchronises. */
+int rl_build_pairs(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                   int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs);
+
+/* Constraint geometry and right-hand side for a pair list (eq. blockdef,
+ * block A: q = phi/h + D^T M F; the column of D for pair (P, Q) =
+ * (pi, pj) is [e; y_P x e; -e; -(y_Q x e)], Appendix "Symmetry ...").
+ * Writes phi, e, arm, q.  F may be NULL (no external load).  RL_ERR_ARG if
+ * a pair index is outside [0, n).  Synchronises (index validation). */
+int rl_assemble_D(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                  int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
+                  double *phi, double *e, double *arm, double *q);
+
+/* w = Mc gamma + q with Mc = D^T M D applied matrix-free (the gradient of
+ * the QP of eq. cqpdef).  q may be NULL (then w = Mc gamma).  gamma is
+ * used as given (no projection).  RL_ERR_ARG if pi is not sorted or an
+ * index is out of range.  Synchronises (index validation). */
+int rl_apply_M(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+               const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+               const double *gamma, double *w);
+
+/* Solve the complementarity problem of eq. cqpdef (unilateral block) by
+ * BBPGD and return the velocities U = M (D gamma + F) (eq.
+ * constrainedeom_euler).  gamma is the start on entry (negative entries are
+ * clipped to 0; zeros = cold start) and the solution on exit.  F may be NULL
+ * (zero external load).  *info (host) receives iterations, residual and
+ * status.  Returns info->status (>= 0) or an error.  Synchronises. */
+int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                 const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                 const double *F, double *gamma, double *U, rl_solve_info *info);
+
+/* One whole timestep: directors, pairs, geometry, solve, then the
+ * linearised Euler update x += h U_t (wrapped into the box) and
+ * theta += h Psi(theta) Omega, renormalised (eq. constrainedeom_euler,
+ * first line; Psi of Appendix "Filament dynamics").  x and quat are updated
+ * in place; U (may be NULL) receives the velocities; *n_pairs (host, may be
+ * NULL) the constraint count.  Pair and constraint storage is the handle's.
+ * Synchronises. */
+int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
+            double *U, rl_solve_info *info, int64_t *n_pairs);
+
+/* Kernel timing with HIP events on the handle's stream, for measurement.
+ * With every > 0, every every-th BBPGD iteration of later solves records
+ * events around its rod kernel and its constraint kernel (iterations after
+ * convergence are not counted); every = 0 turns it off.  rl_profile_read
+ * writes {rod_ms_total, rod_launches, constraint_ms_total,
+ * constraint_launches} to out[4] (host) and resets the totals. */
+int rl_profile_enable(rl_handle h, int every);
+int rl_profile_read(rl_handle h, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RODLCP_H */

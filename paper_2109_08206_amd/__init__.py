@@ -1,0 +1,293 @@
+"""Python binding of librodlcp, the gfx950 HIP library for the steric-
+constraint step of rigid filaments (Yan et al., arXiv 2109.08206).
+
+Argument marshalling only: every step runs in the HIP kernels behind the
+C-ABI declared in ``include/rodlcp.h``.  Tensors must be CUDA (HIP) tensors,
+contiguous, float64 (int32 / uint8 for index and flag lists).  Work goes on
+``torch.cuda.current_stream()``.  There is no CPU fallback: without the built
+library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from dataclasses import dataclass
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librodlcp.so")
+
+OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
+ERR_ARG, ERR_CAPACITY, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = -1, -2, -3, -4, -5
+FP64, FP32_MIXED = 0, 1
+IMG_ZERO = 0x888
+
+_lib = None
+_lock = threading.Lock()
+
+
+class RodLCPError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("box", C.c_double * 3), ("diam", C.c_double), ("cutoff", C.c_double), ("eta", C.c_double),
+                ("dt", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("residual", C.c_double), ("alpha0", C.c_double),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
+SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
+           "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
+           "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read")
+
+
+def load(path: Optional[str] = None) -> C.CDLL:
+    """Load the built library (never builds, never falls back)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(f"librodlcp.so not built ({p}); run paper_2109_08206_amd/build.py")
+        lib = C.CDLL(p)
+        P, I64, D, I32 = C.c_void_p, C.c_int64, C.c_double, C.c_int32
+        H = C.c_void_p
+        sig = {
+            "rl_create": ([C.POINTER(H), C.POINTER(Params)], C.c_int),
+            "rl_destroy": ([H], C.c_int),
+            "rl_set_params": ([H, C.POINTER(Params)], C.c_int),
+            "rl_get_params": ([H, C.POINTER(Params)], C.c_int),
+            "rl_set_stream": ([H, P], C.c_int),
+            "rl_reserve": ([H, I64, I64], C.c_int),
+            "rl_status_str": ([C.c_int], C.c_char_p),
+            "rl_last_error": ([], C.c_char_p),
+            "rl_directors": ([H, I64, P, P], C.c_int),
+            "rl_build_pairs": ([H, I64, P, P, P, D, I64, P, P, P, P, C.POINTER(C.c_int64)], C.c_int),
+            "rl_assemble_D": ([H, I64, P, P, P, D, I64, P, P, P, P, P, P, P, P], C.c_int),
+            "rl_apply_M": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P], C.c_int),
+            "rl_solve_lcp": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)], C.c_int),
+            "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64)], C.c_int),
+            "rl_profile_enable": ([H, C.c_int], C.c_int),
+            "rl_profile_read": ([H, C.POINTER(C.c_double)], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype=None, shape=None, name="array"):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name}: expected a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _len_args(length, n):
+    """(len tensor or None, uniform length)."""
+    torch = _torch()
+    if isinstance(length, torch.Tensor):
+        return _ptr(length, torch.float64, (n,), "len"), 0.0
+    return None, float(length)
+
+
+@dataclass
+class SolveResult:
+    iterations: int
+    residual: float
+    alpha0: float
+    status: int
+
+
+class Solver:
+    """One library handle: parameters, stream and workspace."""
+
+    def __init__(self, box, diam=0.025, cutoff=0.05, eta=0.01, dt=1e-4, tol=1e-8, max_iter=100_000,
+                 precision=FP64, check_every=0):
+        self.lib = load()
+        self._h = C.c_void_p()
+        self.params = Params()
+        self.set_params(box=box, diam=diam, cutoff=cutoff, eta=eta, dt=dt, tol=tol, max_iter=max_iter,
+                        precision=precision, check_every=check_every, _create=True)
+
+    # -- lifecycle ------------------------------------------------------------
+    def set_params(self, _create=False, **kw):
+        p = self.params
+        box = kw.pop("box", None)
+        if box is not None:
+            b = [float(box)] * 3 if not hasattr(box, "__len__") else [float(v) for v in box]
+            p.box[:] = b
+        for k, v in kw.items():
+            setattr(p, k, v)
+        if _create:
+            self._check(self.lib.rl_create(C.byref(self._h), C.byref(p)), "rl_create")
+        else:
+            self._check(self.lib.rl_set_params(self._h, C.byref(p)), "rl_set_params")
+
+    def close(self):
+        if self._h:
+            self.lib.rl_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, where):
+        if rc < 0:
+            raise RodLCPError(rc, where, self.lib.rl_last_error().decode())
+        return rc
+
+    def _stream(self):
+        torch = _torch()
+        self.lib.rl_set_stream(self._h, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+    def profile_enable(self, every: int):
+        self._check(self.lib.rl_profile_enable(self._h, int(every)), "rl_profile_enable")
+
+    def profile_read(self):
+        """{'rod_ms', 'rod_launches', 'con_ms', 'con_launches'} since the last read."""
+        out = (C.c_double * 4)()
+        self._check(self.lib.rl_profile_read(self._h, out), "rl_profile_read")
+        return {"rod_ms": out[0], "rod_launches": int(out[1]), "con_ms": out[2], "con_launches": int(out[3])}
+
+    def reserve(self, max_rods, max_pairs):
+        self._check(self.lib.rl_reserve(self._h, int(max_rods), int(max_pairs)), "rl_reserve")
+
+    # -- entry points -----------------------------------------------------------
+    def directors(self, quat, out=None):
+        torch = _torch()
+        n = quat.shape[0]
+        out = torch.empty((n, 3), dtype=torch.float64, device=quat.device) if out is None else out
+        self._stream()
+        self._check(self.lib.rl_directors(self._h, n, _ptr(quat, torch.float64, (n, 4), "quat"),
+                                          _ptr(out, torch.float64, (n, 3), "dir")), "rl_directors")
+        return out
+
+    def build_pairs(self, x, dir_, length, capacity=None):
+        """Returns (pi, pj, img, flags), each trimmed to the pair count."""
+        torch = _torch()
+        n = x.shape[0]
+        la, l0 = _len_args(length, n)
+        cap = int(capacity) if capacity is not None else 16 * n + 64
+        for _ in range(2):
+            dev = x.device
+            pi = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            pj = torch.empty_like(pi)
+            img = torch.empty_like(pi)
+            fl = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+            cnt = C.c_int64(0)
+            self._stream()
+            rc = self.lib.rl_build_pairs(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
+                                         _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, cap,
+                                         _ptr(pi), _ptr(pj), _ptr(img), _ptr(fl), C.byref(cnt))
+            if rc == ERR_CAPACITY and capacity is None:
+                cap = int(cnt.value)
+                continue
+            self._check(rc, "rl_build_pairs")
+            k = int(cnt.value)
+            return pi[:k], pj[:k], img[:k], fl[:k]
+        raise RodLCPError(ERR_CAPACITY, "rl_build_pairs", "capacity")
+
+    def assemble_D(self, x, dir_, length, pi, pj, img, F):
+        torch = _torch()
+        n, nc = x.shape[0], pi.shape[0]
+        la, l0 = _len_args(length, n)
+        dev = x.device
+        phi = torch.empty(nc, dtype=torch.float64, device=dev)
+        e = torch.empty((nc, 3), dtype=torch.float64, device=dev)
+        arm = torch.empty((nc, 2), dtype=torch.float64, device=dev)
+        q = torch.empty(nc, dtype=torch.float64, device=dev)
+        self._stream()
+        self._check(self.lib.rl_assemble_D(
+            self._h, n, _ptr(x, torch.float64, (n, 3), "x"), _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, nc,
+            _ptr(pi, torch.int32, (nc,), "pi"), _ptr(pj, torch.int32, (nc,), "pj"),
+            _ptr(img, torch.int32, (nc,), "img"), _ptr(F, torch.float64, (n, 6), "F"),
+            _ptr(phi), _ptr(e), _ptr(arm), _ptr(q)), "rl_assemble_D")
+        return phi, e, arm, q
+
+    def apply_M(self, dir_, length, pi, pj, e, arm, q, gamma, out=None):
+        torch = _torch()
+        n, nc = dir_.shape[0], pi.shape[0]
+        la, l0 = _len_args(length, n)
+        w = torch.empty(nc, dtype=torch.float64, device=dir_.device) if out is None else out
+        self._stream()
+        self._check(self.lib.rl_apply_M(
+            self._h, n, _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, nc, _ptr(pi, torch.int32, (nc,), "pi"),
+            _ptr(pj, torch.int32, (nc,), "pj"), _ptr(e, torch.float64, (nc, 3), "e"),
+            _ptr(arm, torch.float64, (nc, 2), "arm"), _ptr(q, torch.float64, (nc,), "q"),
+            _ptr(gamma, torch.float64, (nc,), "gamma"), _ptr(w, torch.float64, (nc,), "w")), "rl_apply_M")
+        return w
+
+    def solve_lcp(self, dir_, length, pi, pj, e, arm, q, F=None, gamma=None, U=None):
+        """Returns (gamma, U, SolveResult); gamma is updated in place if given."""
+        torch = _torch()
+        n, nc = dir_.shape[0], pi.shape[0]
+        la, l0 = _len_args(length, n)
+        dev = dir_.device
+        gamma = torch.zeros(nc, dtype=torch.float64, device=dev) if gamma is None else gamma
+        U = torch.empty((n, 6), dtype=torch.float64, device=dev) if U is None else U
+        info = SolveInfo()
+        self._stream()
+        rc = self.lib.rl_solve_lcp(
+            self._h, n, _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, nc, _ptr(pi, torch.int32, (nc,), "pi"),
+            _ptr(pj, torch.int32, (nc,), "pj"), _ptr(e, torch.float64, (nc, 3), "e"),
+            _ptr(arm, torch.float64, (nc, 2), "arm"), _ptr(q, torch.float64, (nc,), "q"),
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
+            _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
+        self._check(rc, "rl_solve_lcp")
+        return gamma, U, SolveResult(int(info.iterations), float(info.residual), float(info.alpha0),
+                                     int(info.status))
+
+    def step(self, x, quat, length, F=None, U=None):
+        """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs)."""
+        torch = _torch()
+        n = x.shape[0]
+        la, l0 = _len_args(length, n)
+        U = torch.empty((n, 6), dtype=torch.float64, device=x.device) if U is None else U
+        info = SolveInfo()
+        npairs = C.c_int64(0)
+        self._stream()
+        rc = self.lib.rl_step(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
+                              _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
+                              _ptr(F, torch.float64, (n, 6), "F"), _ptr(U, torch.float64, (n, 6), "U"),
+                              C.byref(info), C.byref(npairs))
+        self._check(rc, "rl_step")
+        return U, SolveResult(int(info.iterations), float(info.residual), float(info.alpha0),
+                              int(info.status)), int(npairs.value)
+
+
+def status_str(status: int) -> str:
+    return load().rl_status_str(int(status)).decode()

@@ -1,0 +1,353 @@
+// C-ABI entry points of librodlcp: argument checks, handle and workspace
+// management, and the order of kernel launches of each call.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "rl_internal.hpp"
+
+namespace rl {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+void *ws_get(rl_ctx *h, int s, size_t bytes, int *err)
+{
+    if (s < 0 || s >= kWsCount) {
+        set_error("internal: workspace slot %d out of range", s);
+        *err = RL_ERR_ARG;
+        return nullptr;
+    }
+    if (bytes == 0) bytes = 8;
+    if (h->cap[s] >= bytes) return h->buf[s];
+    if (h->buf[s]) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->buf[s]);
+        h->buf[s] = nullptr;
+        h->cap[s] = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    want = (want + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("workspace allocation of %zu bytes failed", want);
+        *err = RL_ERR_NOMEM;
+        return nullptr;
+    }
+    h->buf[s] = p;
+    h->cap[s] = want;
+    return p;
+}
+
+static int check_params(const rl_params *p)
+{
+    if (!p) {
+        set_error("params is NULL");
+        return RL_ERR_ARG;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!(p->box[a] > 0.0) || !std::isfinite(p->box[a])) {
+            set_error("box edges must be finite and > 0");
+            return RL_ERR_ARG;
+        }
+    if (!(p->diam > 0.0) || !(p->cutoff >= 0.0) || !(p->eta > 0.0) || !(p->dt > 0.0) || !(p->tol >= 0.0) ||
+        !std::isfinite(p->diam) || !std::isfinite(p->cutoff) || !std::isfinite(p->eta) || !std::isfinite(p->dt)) {
+        set_error("need diam > 0, cutoff >= 0, eta > 0, dt > 0, tol >= 0");
+        return RL_ERR_ARG;
+    }
+    if (p->max_iter < 0 || p->check_every < 0) {
+        set_error("max_iter and check_every must be >= 0");
+        return RL_ERR_ARG;
+    }
+    if (p->precision != RL_FP64 && p->precision != RL_FP32_MIXED) {
+        set_error("unknown precision %d", p->precision);
+        return RL_ERR_ARG;
+    }
+    return RL_OK;
+}
+
+}  // namespace rl
+
+using namespace rl;
+
+#define RL_CHECK_HANDLE(h)                      \
+    do {                                        \
+        if (!(h)) {                             \
+            set_error("handle is NULL");        \
+            return RL_ERR_ARG;                  \
+        }                                       \
+        RL_HIP(hipSetDevice((h)->device));      \
+    } while (0)
+
+#define RL_REQUIRE(cond, msg)     \
+    do {                          \
+        if (!(cond)) {            \
+            set_error("%s", msg); \
+            return RL_ERR_ARG;    \
+        }                         \
+    } while (0)
+
+extern "C" {
+
+const char *rl_status_str(int status)
+{
+    switch (status) {
+    case RL_OK: return "ok";
+    case RL_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case RL_STAGNATED: return "stagnated (no progress above tolerance)";
+    case RL_ERR_ARG: return "invalid argument";
+    case RL_ERR_CAPACITY: return "pair capacity too small";
+    case RL_ERR_NONFINITE: return "non-finite value";
+    case RL_ERR_HIP: return "HIP runtime error";
+    case RL_ERR_NOMEM: return "out of device memory";
+    default: return "unknown status";
+    }
+}
+
+const char *rl_last_error(void) { return g_last_error; }
+
+int rl_create(rl_handle *out, const rl_params *prm)
+{
+    if (!out) {
+        set_error("rl_create: out is NULL");
+        return RL_ERR_ARG;
+    }
+    *out = nullptr;
+    int rc = check_params(prm);
+    if (rc) return rc;
+    rl_ctx *h = new (std::nothrow) rl_ctx();
+    if (!h) return RL_ERR_NOMEM;
+    h->prm = *prm;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        set_error("rl_create: no HIP device");
+        return RL_ERR_HIP;
+    }
+    if (hipMalloc(&h->state, sizeof(SolverState)) != hipSuccess ||
+        hipMalloc(&h->flag_dev, sizeof(int) * 4) != hipSuccess ||
+        hipHostMalloc(&h->state_host, sizeof(SolverState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&h->host_scratch, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess) {
+        set_error("rl_create: allocation failed");
+        rl_destroy(h);
+        return RL_ERR_NOMEM;
+    }
+    memset(h->state_host, 0, sizeof(SolverState));
+    *out = h;
+    return RL_OK;
+}
+
+int rl_destroy(rl_handle h)
+{
+    if (!h) return RL_OK;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (int v = 0; v < rl_ctx::kMaxEv; ++v)
+        for (int k = 0; k < 3; ++k)
+            if (h->ev[v][k]) (void)hipEventDestroy(h->ev[v][k]);
+    for (int s = 0; s < rl_ctx::kSlots; ++s)
+        if (h->buf[s]) (void)hipFree(h->buf[s]);
+    if (h->state) (void)hipFree(h->state);
+    if (h->flag_dev) (void)hipFree(h->flag_dev);
+    if (h->state_host) (void)hipHostFree(h->state_host);
+    if (h->host_scratch) (void)hipHostFree(h->host_scratch);
+    delete h;
+    return RL_OK;
+}
+
+int rl_set_params(rl_handle h, const rl_params *prm)
+{
+    if (!h) return RL_ERR_ARG;
+    int rc = check_params(prm);
+    if (rc) return rc;
+    h->prm = *prm;
+    return RL_OK;
+}
+
+int rl_get_params(rl_handle h, rl_params *prm)
+{
+    if (!h || !prm) return RL_ERR_ARG;
+    *prm = h->prm;
+    return RL_OK;
+}
+
+int rl_set_stream(rl_handle h, void *stream)
+{
+    if (!h) return RL_ERR_ARG;
+    h->stream = (hipStream_t)stream;
+    return RL_OK;
+}
+
+int rl_reserve(rl_handle h, int64_t max_rods, int64_t max_pairs)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(max_rods >= 0 && max_pairs >= 0 && max_pairs < 0x7fffffff, "rl_reserve: bad sizes");
+    int err = 0;
+    const int64_t n = max_rods > 0 ? max_rods : 1, nc = max_pairs > 0 ? max_pairs : 1;
+    const size_t sz[][2] = {
+        {kWsDir, sizeof(double) * 3 * n},  {kWsCoef, sizeof(double) * 3 * n},  {kWsV, sizeof(double) * 6 * n},
+        {kWsUnc, sizeof(double) * 6 * n},  {kWsPptr, sizeof(int) * (n + 1)},   {kWsQptr, sizeof(int) * (n + 1)},
+        {kWsQidx, sizeof(int) * nc},       {kWsQcnt, sizeof(int) * n},         {kWsG, sizeof(double) * nc},
+        {kWsPartial, sizeof(double) * 8 * kConGridMax},
+        {kWsCellOf, sizeof(int) * n},      {kWsSorted, sizeof(int) * n},       {kWsXs, sizeof(double) * 3 * n},
+        {kWsDs, sizeof(double) * 3 * n},   {kWsLs, sizeof(double) * n},        {kWsPcnt, sizeof(int) * n},
+        {kWsPoff, sizeof(int) * (n + 1)},  {kWsStepPi, sizeof(int) * nc},      {kWsStepPj, sizeof(int) * nc},
+        {kWsStepImg, sizeof(int) * nc},    {kWsStepFlags, (size_t)nc},                 {kWsStepPhi, sizeof(double) * nc},
+        {kWsStepE, sizeof(double) * 3 * nc}, {kWsStepArm, sizeof(double) * 2 * nc},
+        {kWsStepQ, sizeof(double) * nc},   {kWsStepGamma, sizeof(double) * nc}, {kWsStepU, sizeof(double) * 6 * n},
+        {kWsPP, sizeof(int) * 2 * nc},     {kWsGeo, sizeof(double) * 6 * nc},  {kWsSt, sizeof(double) * 2 * nc},
+        {kWsAlpha, sizeof(double) * 2},    {kWsQpos, sizeof(int) * nc},        {kWsQgeo, sizeof(double) * 4 * nc},
+        {kWsStq, sizeof(double) * 2 * nc},
+    };
+    for (auto &e : sz) {
+        ws_get(h, (int)e[0], e[1], &err);
+        if (err) return err;
+    }
+    return RL_OK;
+}
+
+int rl_directors(rl_handle h, int64_t n, const double *quat, double *dir)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0, "rl_directors: n < 0");
+    RL_REQUIRE(n == 0 || (quat && dir), "rl_directors: NULL array");
+    RL_HIP(launch_directors(h->stream, n, quat, dir));
+    return RL_OK;
+}
+
+int rl_build_pairs(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                   int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff, "rl_build_pairs: bad n");
+    RL_REQUIRE(capacity >= 0, "rl_build_pairs: capacity < 0");
+    RL_REQUIRE(n == 0 || (x && dir), "rl_build_pairs: NULL x or dir");
+    RL_REQUIRE(capacity == 0 || (pi && pj && img && flags), "rl_build_pairs: NULL output list");
+    return build_pairs_impl(h, n, x, dir, len, len0, capacity, pi, pj, img, flags, n_pairs);
+}
+
+int rl_assemble_D(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                  int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
+                  double *phi, double *e, double *arm, double *q)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && nc >= 0 && nc < 0x7fffffff, "rl_assemble_D: bad sizes");
+    RL_REQUIRE(nc == 0 || (x && dir && pi && pj && img && phi && e && arm && q), "rl_assemble_D: NULL array");
+    RL_REQUIRE(len || len0 > 0.0, "rl_assemble_D: len0 must be > 0 when len is NULL");
+    return assemble_impl(h, n, x, dir, len, len0, nc, pi, pj, img, F, phi, e, arm, q);
+}
+
+int rl_apply_M(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+               const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+               const double *gamma, double *w)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && nc >= 0 && nc < 0x7fffffff, "rl_apply_M: bad sizes");
+    RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && gamma && w), "rl_apply_M: NULL array");
+    RL_REQUIRE(len || len0 > 0.0, "rl_apply_M: len0 must be > 0 when len is NULL");
+    SolveArgs a;
+    int rc = prepare_solve(h, n, dir, len, len0, nc, pi, pj, e, arm, q, const_cast<double *>(gamma), &a);
+    if (rc) return rc;
+    rc = apply_impl(h, a, w);
+    if (rc) return rc;
+    RL_HIP(hipStreamSynchronize(h->stream));
+    return RL_OK;
+}
+
+int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                 const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                 const double *F, double *gamma, double *U, rl_solve_info *info)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && nc >= 0 && nc < 0x7fffffff, "rl_solve_lcp: bad sizes");
+    RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && q && gamma), "rl_solve_lcp: NULL array");
+    RL_REQUIRE(n == 0 || dir || !U, "rl_solve_lcp: NULL dir");
+    RL_REQUIRE(len || len0 > 0.0, "rl_solve_lcp: len0 must be > 0 when len is NULL");
+    SolveArgs a;
+    int rc = prepare_solve(h, n, dir, len, len0, nc, pi, pj, e, arm, q, gamma, &a);
+    if (rc) return rc;
+    return solve_impl(h, a, F, U, gamma, info);
+}
+
+int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
+            double *U, rl_solve_info *info, int64_t *n_pairs)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff, "rl_step: bad n");
+    RL_REQUIRE(n == 0 || (x && quat), "rl_step: NULL x or quat");
+    RL_REQUIRE(len || len0 > 0.0, "rl_step: len0 must be > 0 when len is NULL");
+    if (n == 0) {
+        if (n_pairs) *n_pairs = 0;
+        if (info) *info = rl_solve_info{0, 0.0, 0.0, RL_OK, 0};
+        return RL_OK;
+    }
+    int err = 0;
+    double *dir = (double *)ws_get(h, kWsDir, sizeof(double) * 3 * n, &err);
+    if (err) return err;
+    RL_HIP(launch_directors(h->stream, n, quat, dir));
+    // pairs with the rods renumbered in cell order: the solver then reads
+    // neighbouring rods and constraints from neighbouring memory
+    int64_t np = 0;
+    const int *perm = nullptr;
+    const double *xs = nullptr, *ds = nullptr, *ls = nullptr;
+    int rc = build_pairs_sorted(h, n, x, dir, len, len0, &np, &perm, &xs, &ds, &ls);
+    if (rc) return rc;
+    if (n_pairs) *n_pairs = np;
+    const int64_t nb = np > 0 ? np : 1;
+    double *phi = (double *)ws_get(h, kWsStepPhi, sizeof(double) * nb, &err);
+    double *e = (double *)ws_get(h, kWsStepE, sizeof(double) * 3 * nb, &err);
+    double *arm = (double *)ws_get(h, kWsStepArm, sizeof(double) * 2 * nb, &err);
+    double *q = (double *)ws_get(h, kWsStepQ, sizeof(double) * nb, &err);
+    double *gamma = (double *)ws_get(h, kWsStepGamma, sizeof(double) * nb, &err);
+    double *Fs = F ? (double *)ws_get(h, kWsFs, sizeof(double) * 6 * n, &err) : nullptr;
+    double *Uw = U ? U : (double *)ws_get(h, kWsStepU, sizeof(double) * 6 * n, &err);
+    if (err) return err;
+    if (F) RL_HIP(launch_gather6(h->stream, n, perm, F, Fs));
+    const double *lsv = len ? ls : nullptr;
+    const int32_t *pi = (const int32_t *)h->buf[kWsStepPi], *pj = (const int32_t *)h->buf[kWsStepPj];
+    const int32_t *img = (const int32_t *)h->buf[kWsStepImg];
+    rc = assemble_impl(h, n, xs, ds, lsv, len0, np, pi, pj, img, Fs, phi, e, arm, q);
+    if (rc) return rc;
+    RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, h->stream));
+    SolveArgs a;
+    rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a);
+    if (rc) return rc;
+    rc = solve_impl(h, a, F, Uw, gamma, info, perm);
+    if (rc < 0) return rc;
+    const int rc2 = integrate_impl(h, n, Uw, x, quat);
+    if (rc2) return rc2;
+    RL_HIP(hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+int rl_profile_enable(rl_handle h, int every)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(every >= 0, "rl_profile_enable: every < 0");
+    h->prof_every = every;
+    return RL_OK;
+}
+
+int rl_profile_read(rl_handle h, double *out)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(out != nullptr, "rl_profile_read: NULL out");
+    out[0] = h->prof_ms[0];
+    out[1] = h->prof_cnt[0];
+    out[2] = h->prof_ms[1];
+    out[3] = h->prof_cnt[1];
+    h->prof_ms[0] = h->prof_ms[1] = 0.0;
+    h->prof_cnt[0] = h->prof_cnt[1] = 0.0;
+    return RL_OK;
+}
+
+}  // extern "C"

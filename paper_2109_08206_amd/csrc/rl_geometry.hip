@@ -1,0 +1,701 @@
+// Rod geometry on gfx950: directors, per-rod mobility, closest points of rod
+// axes, the uniform-grid pair search and the constraint geometry.
+//
+// Method: Yan et al., arXiv 2109.08206.  Directors come from the unit
+// quaternion of each rod (Appendix "Filament dynamics"); pairs are the rods
+// whose surface gap is below the threshold (Appendix "Implementation");
+// the constraint column of a pair uses the closest points and the unit
+// normal between them (Appendix "Symmetry of the geometrically constrained
+// optimization problem", D_PQ and r = x_P + y_P - x_Q - y_Q); q follows
+// eq. (blockdef), block A.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "rl_internal.hpp"
+
+namespace rl {
+
+// ---------------------------------------------------------------------------
+// small vector helpers
+// ---------------------------------------------------------------------------
+struct V3 {
+    double x, y, z;
+};
+__device__ __forceinline__ V3 v3(double a, double b, double c) { return V3{a, b, c}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator*(double s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b)
+{
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 load3(const double *p) { return v3(p[0], p[1], p[2]); }
+__device__ __forceinline__ void store3(double *p, V3 a)
+{
+    p[0] = a.x;
+    p[1] = a.y;
+    p[2] = a.z;
+}
+__device__ __forceinline__ double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ---------------------------------------------------------------------------
+// directors: third column of R(theta) = (s^2 - p.p) I + 2 p p^T + 2 s [p]x
+// ---------------------------------------------------------------------------
+__global__ void k_directors(int64_t n, const double *__restrict__ quat, double *__restrict__ dir)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 a = *reinterpret_cast<const double2 *>(quat + 4 * i);
+    const double2 b = *reinterpret_cast<const double2 *>(quat + 4 * i + 2);
+    const double s = a.x, px = a.y, py = b.x, pz = b.y;
+    dir[3 * i + 0] = 2.0 * (px * pz + s * py);
+    dir[3 * i + 1] = 2.0 * (py * pz - s * px);
+    dir[3 * i + 2] = s * s - px * px - py * py + pz * pz;
+}
+
+hipError_t launch_directors(hipStream_t st, int64_t n, const double *quat, double *dir)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_directors, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, quat, dir);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// slender-body mobility of a rod of length L (perpendicular drag
+// 4 pi eta L / log(2L/d) as in Section 3; parallel drag half of it;
+// rotational drag pi eta L^3 / (3 log(2L/d)))
+// ---------------------------------------------------------------------------
+__host__ __device__ inline Mob mobility_of(double L, double diam, double eta)
+{
+    const double lg = log(2.0 * L / diam);
+    Mob m;
+    m.aperp = lg / (4.0 * M_PI * eta * L);
+    m.apar = 2.0 * m.aperp;
+    m.rperp = 3.0 * lg / (M_PI * eta * L * L * L);
+    return m;
+}
+
+Mob mobility_host(double L, double diam, double eta) { return mobility_of(L, diam, eta); }
+
+__global__ void k_mobility_coeffs(int64_t n, const double *__restrict__ len, double diam, double eta,
+                                  double *__restrict__ coef)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Mob m = mobility_of(len[i], diam, eta);
+    coef[3 * i + 0] = m.apar;
+    coef[3 * i + 1] = m.aperp;
+    coef[3 * i + 2] = m.rperp;
+}
+
+hipError_t launch_mobility_coeffs(hipStream_t st, int64_t n, const double *len, double diam, double eta, double *coef)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mobility_coeffs, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, len,
+                       diam, eta, coef);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Closest points of two rod axes xi + s di (|s| <= hi) and xj + t dj
+// (|t| <= hj), xj already imaged.  The squared distance is a convex
+// quadratic in (s, t): take the stationary s with t free and clamp it, the
+// best t for that s, and if t leaves its range clamp it and take the best s
+// again (clamped normal equations for segment pairs, Lumelsky 1985).  For
+// parallel axes (1 - b^2 <= 1e-14) the contact is the midpoint of the
+// overlap of the two parameter ranges, else the best end-point candidate.
+// ---------------------------------------------------------------------------
+struct Contact {
+    double s, t, dist;
+    V3 e;
+    unsigned flags;
+};
+
+__device__ Contact closest_point(V3 xi, V3 di, double hi, V3 xj, V3 dj, double hj)
+{
+    const V3 r0 = xi - xj;
+    const double b = dot(di, dj);
+    const double c = dot(di, r0);
+    const double f = dot(dj, r0);
+    const double den = 1.0 - b * b;
+    Contact out;
+    out.flags = den <= kBandPar ? 2u : 0u;
+    double s, t;
+    if (den > kEpsPar) {
+        s = clampd((b * f - c) / den, -hi, hi);
+        t = b * s + f;
+        if (t < -hj) {
+            t = -hj;
+            s = clampd(b * t - c, -hi, hi);
+        } else if (t > hj) {
+            t = hj;
+            s = clampd(b * t - c, -hi, hi);
+        }
+    } else {
+        const double sg = b >= 0.0 ? 1.0 : -1.0;
+        double lo = (-hj - f) * sg, up = (hj - f) * sg;
+        if (lo > up) {
+            const double tmp = lo;
+            lo = up;
+            up = tmp;
+        }
+        lo = lo > -hi ? lo : -hi;
+        up = up < hi ? up : hi;
+        if (lo <= up) {
+            s = 0.5 * (lo + up);
+            t = clampd(b * s + f, -hj, hj);
+        } else {
+            double best = INFINITY;
+            s = 0.0;
+            t = 0.0;
+            for (int k = 0; k < 4; ++k) {
+                double sk, tk;
+                if (k < 2) {
+                    sk = k == 0 ? -hi : hi;
+                    tk = clampd(b * sk + f, -hj, hj);
+                } else {
+                    tk = k == 2 ? -hj : hj;
+                    sk = clampd(b * tk - c, -hi, hi);
+                }
+                const V3 rk = r0 + sk * di - tk * dj;
+                const double d2 = dot(rk, rk);
+                if (d2 < best) {
+                    best = d2;
+                    s = sk;
+                    t = tk;
+                }
+            }
+        }
+    }
+    const V3 r = r0 + s * di - t * dj;
+    const double dist = sqrt(dot(r, r));
+    out.s = s;
+    out.t = t;
+    out.dist = dist;
+    if (dist >= kDegenDist) {
+        out.e = v3(r.x / dist, r.y / dist, r.z / dist);
+    } else {
+        out.flags |= 4u;
+        V3 nrm = cross(di, dj);
+        double nn = sqrt(dot(nrm, nrm));
+        if (nn < 1e-12) {
+            // collinear axes: normal to di and the coordinate axis least aligned with it
+            const double ax = fabs(di.x), ay = fabs(di.y), az = fabs(di.z);
+            int k = 0;
+            double best = ax;
+            if (ay < best) {
+                k = 1;
+                best = ay;
+            }
+            if (az < best) k = 2;
+            const V3 ek = v3(k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0);
+            nrm = cross(di, ek);
+            nn = sqrt(dot(nrm, nrm));
+        }
+        const double sg = dot(nrm, r0) >= 0.0 ? 1.0 : -1.0;
+        out.e = v3(sg * nrm.x / nn, sg * nrm.y / nn, sg * nrm.z / nn);
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Pair search.  Cells of edge >= reach (max length + diam + cutoff) on a
+// periodic grid; rods are binned by centre and copied in cell order so that
+// the lanes of a wave, which hold rods of the same cell, read the same
+// neighbour-cell entries together.  The stencil offset u of a cell maps to
+// the wrapped cell u mod nc and the shift floor(u / nc) of the neighbour.
+// ---------------------------------------------------------------------------
+struct GridDev {
+    int nc[3];
+    int S[3];
+    double cell[3];
+    double box[3];
+};
+
+__device__ __forceinline__ int cell_coord(double x, double cell, int nc)
+{
+    int k = (int)floor(x / cell);
+    return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+}
+
+__global__ void k_bin(int64_t n, const double *__restrict__ x, const double *__restrict__ dir, GridDev g,
+                      int *__restrict__ cell_of, int *__restrict__ cell_cnt, int *__restrict__ err)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const V3 xi = load3(x + 3 * i), di = load3(dir + 3 * i);
+    const double xs[3] = {xi.x, xi.y, xi.z};
+    bool finite = isfinite(xi.x) && isfinite(xi.y) && isfinite(xi.z) && isfinite(di.x) && isfinite(di.y) &&
+                  isfinite(di.z);
+    if (!finite) {
+        // keep the cell counts consistent with the scatter that follows
+        atomicOr(err, 1);
+        cell_of[i] = 0;
+        atomicAdd(cell_cnt, 1);
+        return;
+    }
+    int kc[3];
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) {
+        inside = inside && xs[a] >= 0.0 && xs[a] < g.box[a];
+        kc[a] = cell_coord(xs[a], g.cell[a], g.nc[a]);
+    }
+    if (!inside) atomicOr(err, 2);
+    const int id = (kc[0] * g.nc[1] + kc[1]) * g.nc[2] + kc[2];
+    cell_of[i] = id;
+    atomicAdd(cell_cnt + id, 1);
+}
+
+// exclusive scan of m int32 counts into m+1 offsets, one workgroup of 1024
+__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int64_t m, int *__restrict__ out,
+                                               int64_t *__restrict__ total)
+{
+    __shared__ long long part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (m + 1023) / 1024;
+    const int64_t beg = tid * chunk;
+    const int64_t end = beg + chunk < m ? beg + chunk : m;
+    long long s = 0;
+    for (int64_t k = beg; k < end; ++k) s += in[k];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        long long v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    long long run = part[tid] - s;
+    for (int64_t k = beg; k < end; ++k) {
+        out[k] = (int)run;
+        run += in[k];
+    }
+    if (tid == 1023) {
+        out[m] = (int)part[1023];
+        if (total) *total = part[1023];
+    }
+}
+
+hipError_t launch_scan(hipStream_t st, const int *in, int64_t m, int *out, int64_t *total)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, in, m, out, total);
+    return hipGetLastError();
+}
+
+__global__ void k_scatter(int64_t n, const double *__restrict__ x, const double *__restrict__ dir,
+                          const double *__restrict__ len, double len0, const int *__restrict__ cell_of,
+                          const int *__restrict__ cell_start, int *__restrict__ cell_cur, int *__restrict__ sorted,
+                          double *__restrict__ xs, double *__restrict__ ds, double *__restrict__ ls)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell_of[i];
+    const int slot = cell_start[c] + atomicAdd(cell_cur + c, 1);
+    sorted[slot] = (int)i;
+    store3(xs + 3 * (int64_t)slot, load3(x + 3 * i));
+    store3(ds + 3 * (int64_t)slot, load3(dir + 3 * i));
+    ls[slot] = len ? len[i] : len0;
+}
+
+__device__ __forceinline__ bool lex_positive(int a, int b, int c)
+{
+    return a > 0 || (a == 0 && (b > 0 || (b == 0 && c > 0)));
+}
+
+// One lane per rod (in cell order t).  INTERNAL: rods are numbered by their
+// cell-order slot; otherwise by the caller's index sorted[t].  A pair is
+// listed by its smaller rod number (self-images: positive shifts only).
+template <bool FILL, bool INTERNAL>
+__global__ void k_pairs(int64_t n, GridDev g, double diam, double cutoff, const int *__restrict__ sorted,
+                        const double *__restrict__ xs, const double *__restrict__ ds, const double *__restrict__ ls,
+                        const int *__restrict__ cell_start, int *__restrict__ pcnt, const int *__restrict__ poff,
+                        int32_t *__restrict__ pi, int32_t *__restrict__ pj, int32_t *__restrict__ img,
+                        uint8_t *__restrict__ flags)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = INTERNAL ? (int)t : sorted[t];
+    const V3 xi = load3(xs + 3 * t), di = load3(ds + 3 * t);
+    const double Li = ls[t];
+    const int kx = cell_coord(xi.x, g.cell[0], g.nc[0]);
+    const int ky = cell_coord(xi.y, g.cell[1], g.nc[1]);
+    const int kz = cell_coord(xi.z, g.cell[2], g.nc[2]);
+    int cnt = 0;
+    const int base = FILL ? poff[i] : 0;
+    for (int ox = -g.S[0]; ox <= g.S[0]; ++ox) {
+        const int ux = kx + ox;
+        const int wx = ((ux % g.nc[0]) + g.nc[0]) % g.nc[0];
+        const int sx = (ux - wx) / g.nc[0];
+        for (int oy = -g.S[1]; oy <= g.S[1]; ++oy) {
+            const int uy = ky + oy;
+            const int wy = ((uy % g.nc[1]) + g.nc[1]) % g.nc[1];
+            const int sy = (uy - wy) / g.nc[1];
+            for (int oz = -g.S[2]; oz <= g.S[2]; ++oz) {
+                const int uz = kz + oz;
+                const int wz = ((uz % g.nc[2]) + g.nc[2]) % g.nc[2];
+                const int sz = (uz - wz) / g.nc[2];
+                const bool selfok = lex_positive(sx, sy, sz);
+                const V3 shift = v3(sx * g.box[0], sy * g.box[1], sz * g.box[2]);
+                const int w = (wx * g.nc[1] + wy) * g.nc[2] + wz;
+                const int qb = cell_start[w], qe = cell_start[w + 1];
+                for (int q = qb; q < qe; ++q) {
+                    const int j = INTERNAL ? q : sorted[q];
+                    if (j < i || (j == i && !selfok)) continue;
+                    const V3 xj = load3(xs + 3 * (int64_t)q) + shift;
+                    const V3 r0 = xi - xj;
+                    const double Lj = ls[q];
+                    const double reach = 0.5 * (Li + Lj) + diam + cutoff;
+                    if (dot(r0, r0) >= reach * reach) continue;
+                    const Contact c = closest_point(xi, di, 0.5 * Li, xj, load3(ds + 3 * (int64_t)q), 0.5 * Lj);
+                    const double phi = c.dist - diam;
+                    if (!(phi < cutoff)) continue;
+                    if (FILL) {
+                        const int o = base + cnt;
+                        pi[o] = i;
+                        pj[o] = j;
+                        img[o] = ((sx + 8) << 8) | ((sy + 8) << 4) | (sz + 8);
+                        flags[o] = (uint8_t)(c.flags | (fabs(phi - cutoff) <= kCutoffBand ? 1u : 0u));
+                    }
+                    ++cnt;
+                }
+            }
+        }
+    }
+    if (!FILL) pcnt[i] = cnt;
+}
+
+// copies of centres, directors, lengths (and forces) in cell order
+__global__ void k_gather_rods(int64_t n, const int *__restrict__ perm, const double *__restrict__ x,
+                              const double *__restrict__ dir, const double *__restrict__ len, double len0,
+                              double *__restrict__ xs, double *__restrict__ ds, double *__restrict__ ls)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = perm[t];
+    store3(xs + 3 * t, load3(x + 3 * i));
+    store3(ds + 3 * t, load3(dir + 3 * i));
+    ls[t] = len ? len[i] : len0;
+}
+
+// order each rod's pairs by (pj, img): short insertion sort per rod
+__global__ void k_sort_pairs(int64_t n, const int *__restrict__ poff, int32_t *__restrict__ pj,
+                             int32_t *__restrict__ img, uint8_t *__restrict__ flags)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = poff[i], e = poff[i + 1];
+    for (int k = b + 1; k < e; ++k) {
+        const int32_t kj = pj[k], ki = img[k];
+        const uint8_t kf = flags[k];
+        const long long key = ((long long)kj << 12) | ki;
+        int m = k - 1;
+        while (m >= b && (((long long)pj[m] << 12) | img[m]) > key) {
+            pj[m + 1] = pj[m];
+            img[m + 1] = img[m];
+            flags[m + 1] = flags[m];
+            --m;
+        }
+        pj[m + 1] = kj;
+        img[m + 1] = ki;
+        flags[m + 1] = kf;
+    }
+}
+
+__global__ void k_len_max(int64_t n, const double *__restrict__ len, unsigned long long *__restrict__ out,
+                          int *__restrict__ err)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double L = len[i];
+    if (!(L > 0.0) || !isfinite(L)) {
+        atomicOr(err, 4);
+        return;
+    }
+    // positive doubles order like their bit patterns
+    atomicMax(out, (unsigned long long)__double_as_longlong(L));
+}
+
+static inline unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+__global__ void k_gather6(int64_t n, const int *__restrict__ perm, const double *__restrict__ src,
+                          double *__restrict__ dst)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t i = perm[t];
+    for (int a = 0; a < 6; ++a) dst[6 * t + a] = src[6 * i + a];
+}
+
+hipError_t launch_gather6(hipStream_t st, int64_t n, const int *perm, const double *src, double *dst)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather6, dim3(grid_of(n)), dim3(kBlock), 0, st, n, perm, src, dst);
+    return hipGetLastError();
+}
+
+// Shared body of the two pair searches.  internal = false: canonical list
+// in the caller's rod numbering; internal = true: rods renumbered in cell
+// order (stable by caller index), h's workspace keeps the order and copies.
+static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                      bool internal, int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags,
+                      int64_t *n_pairs)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    int werr = 0;
+    if (n_pairs) *n_pairs = 0;
+    if (n == 0) return RL_OK;
+    // longest rod
+    double Lmax = len0;
+    RL_HIP(hipMemsetAsync(h->flag_dev, 0, sizeof(int) * 4, st));
+    if (len) {
+        auto *lm = (unsigned long long *)ws_get(h, kWsLenMax, sizeof(unsigned long long), &werr);
+        if (werr) return werr;
+        RL_HIP(hipMemsetAsync(lm, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_len_max, dim3(grid_of(n)), dim3(kBlock), 0, st, n, len, lm, h->flag_dev);
+        RL_HIP(hipGetLastError());
+        RL_HIP(hipMemcpyAsync(h->host_scratch, lm, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipMemcpyAsync(h->host_scratch + 1, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipStreamSynchronize(st));
+        if (((int *)(h->host_scratch + 1))[0] & 4) {
+            set_error("pair search: rod lengths must be finite and > 0");
+            return RL_ERR_ARG;
+        }
+        unsigned long long bits = (unsigned long long)h->host_scratch[0];
+        std::memcpy(&Lmax, &bits, sizeof(double));
+    } else if (!(len0 > 0.0)) {
+        set_error("pair search: len0 must be > 0");
+        return RL_ERR_ARG;
+    }
+    const double reach = Lmax + p.diam + p.cutoff;
+    GridDev g;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        int nca = (int)floor(p.box[a] / reach);
+        if (nca < 1) nca = 1;
+        if (nca > 1024) nca = 1024;
+        g.nc[a] = nca;
+        g.cell[a] = p.box[a] / nca;
+        g.S[a] = (int)ceil(reach / g.cell[a]);
+        g.box[a] = p.box[a];
+        if (g.S[a] > 7) {
+            set_error("pair search: box edge %g too small for rod reach %g (needs box >= reach/7)", p.box[a], reach);
+            return RL_ERR_ARG;
+        }
+        ncell *= nca;
+    }
+    if (ncell > (1 << 26)) {
+        set_error("pair search: too many cells (%lld)", (long long)ncell);
+        return RL_ERR_ARG;
+    }
+    int *cell_of = (int *)ws_get(h, kWsCellOf, sizeof(int) * n, &werr);
+    int *cell_cnt = (int *)ws_get(h, kWsCellCnt, sizeof(int) * ncell, &werr);
+    int *cell_start = (int *)ws_get(h, kWsCellStart, sizeof(int) * (ncell + 1), &werr);
+    int *cell_cur = (int *)ws_get(h, kWsCellCur, sizeof(int) * ncell, &werr);
+    int *sorted = (int *)ws_get(h, kWsSorted, sizeof(int) * n, &werr);
+    int *cell_key = internal ? (int *)ws_get(h, kWsCellKey, sizeof(int) * n, &werr) : nullptr;
+    double *xs = (double *)ws_get(h, kWsXs, sizeof(double) * 3 * n, &werr);
+    double *ds = (double *)ws_get(h, kWsDs, sizeof(double) * 3 * n, &werr);
+    double *ls = (double *)ws_get(h, kWsLs, sizeof(double) * n, &werr);
+    int *pcnt = (int *)ws_get(h, kWsPcnt, sizeof(int) * n, &werr);
+    int *poff = (int *)ws_get(h, kWsPoff, sizeof(int) * (n + 1), &werr);
+    int64_t *tot = (int64_t *)ws_get(h, kWsScan, sizeof(int64_t) * 2, &werr);
+    if (werr) return werr;
+
+    RL_HIP(hipMemsetAsync(cell_cnt, 0, sizeof(int) * ncell, st));
+    hipLaunchKernelGGL(k_bin, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, g, cell_of, cell_cnt, h->flag_dev);
+    RL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cell_cnt, ncell, cell_start, (int64_t *)nullptr);
+    RL_HIP(hipGetLastError());
+    if (internal) {
+        int bits = 1;
+        while ((1LL << bits) < ncell) ++bits;
+        int rc = stable_sort_by_key(h, n, cell_of, bits, cell_key, sorted);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_gather_rods, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)sorted, x, dir, len,
+                           len0, xs, ds, ls);
+    } else {
+        RL_HIP(hipMemsetAsync(cell_cur, 0, sizeof(int) * ncell, st));
+        hipLaunchKernelGGL(k_scatter, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, len, len0, cell_of,
+                           cell_start, cell_cur, sorted, xs, ds, ls);
+    }
+    RL_HIP(hipGetLastError());
+    if (internal)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, true>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g, p.diam,
+                           p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
+                           (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, false>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g,
+                           p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr,
+                           (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
+    RL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pcnt, n, poff, tot);
+    RL_HIP(hipGetLastError());
+    RL_HIP(hipMemcpyAsync(h->host_scratch, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipMemcpyAsync(h->host_scratch + 1, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipStreamSynchronize(st));
+    const int64_t total = h->host_scratch[0];
+    const int ferr = ((int *)(h->host_scratch + 1))[0];
+    if (ferr & 1) {
+        set_error("pair search: non-finite centre or director");
+        return RL_ERR_NONFINITE;
+    }
+    if (ferr & 2) {
+        set_error("pair search: a centre lies outside [0, box)");
+        return RL_ERR_ARG;
+    }
+    if (n_pairs) *n_pairs = total;
+    if (total > capacity) {
+        set_error("pair search: %lld pairs exceed capacity %lld", (long long)total, (long long)capacity);
+        return RL_ERR_CAPACITY;
+    }
+    if (total > 0x7fffffffLL) {
+        set_error("pair search: pair count overflows int32");
+        return RL_ERR_CAPACITY;
+    }
+    if (total == 0) return RL_OK;
+    if (internal)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, true>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g, p.diam,
+                           p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, false>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g,
+                           p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img,
+                           flags);
+    RL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sort_pairs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)poff, pj, img, flags);
+    RL_HIP(hipGetLastError());
+    return RL_OK;
+}
+
+int build_pairs_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                     int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs)
+{
+    return pairs_core(h, n, x, dir, len, len0, false, capacity, pi, pj, img, flags, n_pairs);
+}
+
+int build_pairs_sorted(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                       int64_t *n_pairs, const int **perm, const double **xs, const double **ds, const double **ls)
+{
+    int err = 0;
+    int64_t cap = (int64_t)(h->cap[kWsStepPi] / sizeof(int32_t));
+    int64_t np = 0;
+    int rc = RL_ERR_CAPACITY;
+    for (int attempt = 0; attempt < 2 && rc == RL_ERR_CAPACITY; ++attempt) {
+        if (cap > 0 && (h->cap[kWsStepPj] < sizeof(int32_t) * cap || h->cap[kWsStepImg] < sizeof(int32_t) * cap ||
+                        h->cap[kWsStepFlags] < (size_t)cap))
+            cap = 0;
+        rc = pairs_core(h, n, x, dir, len, len0, true, cap, (int32_t *)h->buf[kWsStepPi],
+                        (int32_t *)h->buf[kWsStepPj], (int32_t *)h->buf[kWsStepImg], (uint8_t *)h->buf[kWsStepFlags],
+                        &np);
+        if (rc == RL_ERR_CAPACITY && np <= 0x7fffffffLL) {
+            cap = np + np / 4 + 64;
+            ws_get(h, kWsStepPi, sizeof(int32_t) * cap, &err);
+            ws_get(h, kWsStepPj, sizeof(int32_t) * cap, &err);
+            ws_get(h, kWsStepImg, sizeof(int32_t) * cap, &err);
+            ws_get(h, kWsStepFlags, (size_t)cap, &err);
+            if (err) return err;
+            cap = (int64_t)(h->cap[kWsStepPi] / sizeof(int32_t));
+        }
+    }
+    if (rc) return rc;
+    *n_pairs = np;
+    *perm = (const int *)h->buf[kWsSorted];
+    *xs = (const double *)h->buf[kWsXs];
+    *ds = (const double *)h->buf[kWsDs];
+    *ls = (const double *)h->buf[kWsLs];
+    return RL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Constraint geometry: phi, e, arm and q = phi/h + D^T M F per pair.
+// ---------------------------------------------------------------------------
+template <bool UNI>
+__global__ void k_unc(int64_t n, const double *__restrict__ dir, const double *__restrict__ len, Mob mob, double diam,
+                      double eta, const double *__restrict__ F, double *__restrict__ Unc)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Mob m = UNI ? mob : mobility_of(len[i], diam, eta);
+    const V3 d = load3(dir + 3 * i);
+    V3 f = v3(0, 0, 0), tq = v3(0, 0, 0);
+    if (F) {
+        f = load3(F + 6 * i);
+        tq = load3(F + 6 * i + 3);
+    }
+    const V3 u = m.aperp * f + ((m.apar - m.aperp) * dot(d, f)) * d;
+    const V3 w = m.rperp * tq;  // axial rotational mobility equals the normal one
+    store3(Unc + 6 * i, u);
+    store3(Unc + 6 * i + 3, w);
+}
+
+__global__ void k_assemble(int64_t nc, const double *__restrict__ x, const double *__restrict__ dir,
+                           const double *__restrict__ len, double len0, GridDev g, double diam, double dt,
+                           const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                           const int32_t *__restrict__ img, const double *__restrict__ Unc, double *__restrict__ phi,
+                           double *__restrict__ e, double *__restrict__ arm, double *__restrict__ q, int64_t n,
+                           int *__restrict__ err)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int i = pi[c], j = pj[c], im = img[c];
+    if (i < 0 || j < 0 || i >= n || j >= n) {
+        atomicOr(err, 8);
+        phi[c] = q[c] = arm[2 * c] = arm[2 * c + 1] = NAN;
+        store3(e + 3 * c, v3(NAN, NAN, NAN));
+        return;
+    }
+    const double sx = ((im >> 8) & 15) - 8, sy = ((im >> 4) & 15) - 8, sz = (im & 15) - 8;
+    const V3 xi = load3(x + 3 * (int64_t)i), di = load3(dir + 3 * (int64_t)i);
+    const V3 xj = load3(x + 3 * (int64_t)j) + v3(sx * g.box[0], sy * g.box[1], sz * g.box[2]);
+    const V3 dj = load3(dir + 3 * (int64_t)j);
+    const double Li = len ? len[i] : len0, Lj = len ? len[j] : len0;
+    const Contact ct = closest_point(xi, di, 0.5 * Li, xj, dj, 0.5 * Lj);
+    const double ph = ct.dist - diam;
+    phi[c] = ph;
+    store3(e + 3 * c, ct.e);
+    arm[2 * c] = ct.s;
+    arm[2 * c + 1] = ct.t;
+    // D^T U_nc: e.U_i + (s_i d_i x e).Omega_i - e.U_j - (t d_j x e).Omega_j
+    const V3 ui = load3(Unc + 6 * (int64_t)i), wi = load3(Unc + 6 * (int64_t)i + 3);
+    const V3 uj = load3(Unc + 6 * (int64_t)j), wj = load3(Unc + 6 * (int64_t)j + 3);
+    const double rate = dot(ct.e, ui) + dot(cross(ct.s * di, ct.e), wi) - dot(ct.e, uj) -
+                        dot(cross(ct.t * dj, ct.e), wj);
+    q[c] = ph / dt + rate;
+}
+
+int assemble_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                  int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
+                  double *phi, double *e, double *arm, double *q)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    int werr = 0;
+    if (nc == 0) return RL_OK;
+    double *Unc = (double *)ws_get(h, kWsUnc, sizeof(double) * 6 * (n > 0 ? n : 1), &werr);
+    if (werr) return werr;
+    const Mob mob = mobility_of(len ? 1.0 : len0, p.diam, p.eta);
+    if (len)
+        hipLaunchKernelGGL(k_unc<false>, dim3(grid_of(n)), dim3(kBlock), 0, st, n, dir, len, mob, p.diam, p.eta, F,
+                           Unc);
+    else
+        hipLaunchKernelGGL(k_unc<true>, dim3(grid_of(n)), dim3(kBlock), 0, st, n, dir, len, mob, p.diam, p.eta, F,
+                           Unc);
+    RL_HIP(hipGetLastError());
+    GridDev g{};
+    for (int a = 0; a < 3; ++a) g.box[a] = p.box[a];
+    RL_HIP(hipMemsetAsync(h->flag_dev, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_assemble, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, x, dir, len, len0, g, p.diam, p.dt,
+                       pi, pj, img, (const double *)Unc, phi, e, arm, q, n, h->flag_dev);
+    RL_HIP(hipGetLastError());
+    RL_HIP(hipMemcpyAsync(h->host_scratch, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipStreamSynchronize(st));
+    if (((int *)h->host_scratch)[0] & 8) {
+        set_error("rl_assemble_D: a pair index is outside [0, n)");
+        return RL_ERR_ARG;
+    }
+    return RL_OK;
+}
+
+}  // namespace rl

@@ -1,0 +1,164 @@
+// Internal declarations of the rodlcp HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/rodlcp.h"
+
+namespace rl {
+
+constexpr int kBlock = 256;              // threads per workgroup for the flat kernels
+constexpr int kWaves = kBlock / 64;      // wave64
+constexpr int kImgZero = 0x888;          // packed zero periodic shift
+constexpr double kEpsPar = 1e-14;        // below this 1 - (di.dj)^2 the axes are parallel
+constexpr double kBandPar = 1e-10;       // flag band for near-parallel axes
+constexpr double kDegenDist = 1e-12;     // axis distance below which the normal is di x dj
+constexpr double kCutoffBand = 1e-9;     // flag band around the pair threshold
+
+// Solver modes of the rod / constraint kernels.
+enum Mode : int {
+    kModeInit = 0,    // gamma' = max(0, gamma): w0 = Mc gamma0 + q
+    kModeAlpha0 = 1,  // gamma' = projected gradient: alpha0 = gh.gh / gh.Mc gh
+    kModeLoop = 2,    // gamma' = max(0, gamma - alpha g): one BBPGD iteration
+    kModeApply = 3,   // gamma' = gamma (no projection): w = Mc gamma (+ q)
+};
+
+// Device-resident solver state.  The loop kernels never write fields that
+// other workgroups of the same launch read: alpha and the stop latch are
+// published by workgroup 0 of the rod kernel and read by later launches.
+struct SolverState {
+    double alpha;          // step of iteration 0 (alpha0)
+    double alpha0, amin, amax;
+    double tol;
+    long long max_iter;
+    // results for the host, written once when the stop is decided
+    double res, ss, sy, yy;
+    long long iter;
+    int done, status;
+};
+
+// Per-rod mobility: a_par, a_perp (translation along / normal to the axis),
+// r_perp (rotation about a normal axis).  Axial rotation uses r_perp as well.
+struct Mob {
+    double apar, aperp, rperp;
+};
+
+// Host-side view of the mobility constants of a uniform-length system.
+Mob mobility_host(double L, double diam, double eta);
+
+constexpr int kRodBlock = 1024;  // rod kernel: 4 lanes per rod, 256 rods per workgroup
+constexpr int kRodLanes = 4;
+constexpr int kConBlock = 512;   // constraint kernel workgroup
+constexpr int kConGridMax = 512; // constraint kernel grid cap (grid-stride beyond)
+
+// Arguments shared by the solver kernels (passed by value).
+struct SolveArgs {
+    int64_t n, nc;
+    const double *dir;      // [n][3]
+    const double *coef;     // [n][3] per-rod mobility, or nullptr when uniform
+    Mob mob;                // uniform mobility
+    const int2 *pp;         // [nc] (pi, pj)
+    const int32_t *pptr;    // [n+1] first constraint with pi >= r
+    const int32_t *qptr;    // [n+1] Q-side incidence offsets
+    const int32_t *qidx;    // [nc] constraints with pj == r, ascending
+    const int32_t *qpos;    // [nc] position of constraint c in the Q-side list
+    const double *geo;      // [nc][6] (ex, ey, ez, s_i, s_j, q)
+    const double *qgeo;     // [nc][4] Q-side list order: (ex, ey, ez, s_j)
+    double2 *st;            // [nc] (gamma, g) of the current iterate
+    double2 *stq;           // [nc] the same in Q-side list order
+    double *V;              // [n][6] per rod: M_t F_c and Omega_c x dir
+    double *partial;        // [2][gcon][4] workgroup partials, by iteration parity
+    double *alpha_buf;      // [2] step length of iteration k at k & 1
+    int gcon;               // workgroups of the constraint kernel
+    SolverState *state;
+    double *out;            // kModeApply output
+};
+
+// --- kernels launchers (implemented in the .hip files) ----------------------
+hipError_t launch_directors(hipStream_t st, int64_t n, const double *quat, double *dir);
+hipError_t launch_mobility_coeffs(hipStream_t st, int64_t n, const double *len, double diam, double eta,
+                                  double *coef);
+
+struct PairGrid {
+    int nc[3];
+    double cell[3];
+    int S[3];
+    double box[3];
+    int64_t ncell;
+};
+
+}  // namespace rl
+
+// Opaque handle.
+struct rl_ctx {
+    rl_params prm;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // grow-only workspace slots
+    static constexpr int kSlots = 64;
+    void *buf[kSlots] = {};
+    size_t cap[kSlots] = {};
+    rl::SolverState *state = nullptr;       // device
+    rl::SolverState *state_host = nullptr;  // pinned
+    int *flag_dev = nullptr;                // device error flags
+    int64_t *host_scratch = nullptr;        // pinned, for small readbacks
+    // event sampling of the loop kernels
+    static constexpr int kMaxEv = 64;
+    int prof_every = 0;
+    hipEvent_t ev[kMaxEv][3] = {};
+    long long ev_iter[kMaxEv] = {};
+    double prof_ms[2] = {0.0, 0.0};
+    double prof_cnt[2] = {0.0, 0.0};
+};
+
+namespace rl {
+
+enum Slot : int {
+    kWsDir = 0, kWsCoef, kWsV, kWsUnc, kWsPptr, kWsQptr, kWsQidx, kWsQcnt, kWsG, kWsPartial,
+    kWsCellOf, kWsCellCnt, kWsCellStart, kWsCellCur, kWsSorted, kWsXs, kWsDs, kWsLs, kWsPcnt, kWsPoff,
+    kWsStepPi, kWsStepPj, kWsStepImg, kWsStepFlags, kWsStepPhi, kWsStepE, kWsStepArm, kWsStepQ, kWsStepGamma,
+    kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
+    kWsCount  // number of slots; must not exceed rl_ctx::kSlots
+};
+static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
+
+// Returns a device buffer of at least `bytes` in slot `s` (grow-only).
+void *ws_get(rl_ctx *h, int s, size_t bytes, int *err);
+
+void set_error(const char *fmt, ...);
+
+// Internal building blocks used by the C-ABI layer.
+int build_pairs_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                     int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs);
+hipError_t launch_gather6(hipStream_t st, int64_t n, const int *perm, const double *src, double *dst);
+int stable_sort_by_key(rl_ctx *h, int64_t n, const int *keys, int bits, int *keys_out, int *perm);
+// Pair list in the solver's own rod order (cell order).  On return *perm
+// (device, n) maps solver rod -> caller rod and xs/ds/ls hold the rods'
+// centres, directors and lengths in solver order (handle workspace).
+int build_pairs_sorted(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                       int64_t *n_pairs, const int **perm, const double **xs, const double **ds, const double **ls);
+int assemble_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                  int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
+                  double *phi, double *e, double *arm, double *q);
+int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                  const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                  double *gamma, SolveArgs *a);
+int apply_impl(rl_ctx *h, SolveArgs &a, double *w);
+int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamma_out, rl_solve_info *info,
+               const int *perm = nullptr);
+int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat);
+
+}  // namespace rl
+
+#define RL_HIP(call)                                                                               \
+    do {                                                                                           \
+        hipError_t _e = (call);                                                                    \
+        if (_e != hipSuccess) {                                                                    \
+            rl::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, __LINE__); \
+            return RL_ERR_HIP;                                                                     \
+        }                                                                                          \
+    } while (0)

@@ -1,0 +1,790 @@
+// BBPGD solve of the unilateral constraint problem on gfx950.
+//
+// The problem is min 1/2 gamma^T Mc gamma + q^T gamma, gamma >= 0, with
+// Mc = D^T M D (eq. cqpdef / suppcqpdef; eq. blockdef, block B).  Each
+// iteration needs one product Mc gamma, done matrix-free by two kernels:
+//
+//   rod kernel (four lanes per rod): the contact force D gamma' on the rod,
+//     summed over the constraints it takes part in (P side: contiguous range
+//     of the pi-sorted list; Q side: incidence list), and the mobility
+//     applied in registers.  It stores, per rod, V = M_t F_c and
+//     W = Omega_c x dir, so that the velocity of the axis point at arclength
+//     s is V + s W and the constraint side needs no director.
+//   constraint kernel (one lane per constraint, grid-stride): w = e.(V_i +
+//     s_i W_i - V_j - s_j W_j) + q, the projection, the BB dot products and
+//     the natural residual, reduced to one partial per workgroup.
+//
+// No workgroup ever waits for another inside a launch, so there are no
+// device-scope fences in the loop (each one flushes and invalidates the L2
+// of the issuing XCD).  Instead every workgroup of the next rod kernel sums
+// the previous iteration's partials itself, in a fixed order, and so reaches
+// the same step length and stop decision; workgroup 0 publishes them for the
+// constraint kernel and latches the stop.  Partials are double-buffered by
+// iteration parity.  All sums run in a fixed order (no floating-point
+// atomics), so results are bitwise repeatable.
+//
+// The BB iteration follows Barzilai & Borwein (1988) in its projected form
+// (Dai & Fletcher 2005): the paper names the method (Section "Instantiation
+// in a massively parallel computing environment"; Appendix
+// "Implementation") and leaves its details to earlier work.  Start:
+// g0 = Mc gamma0 + q; alpha0 = gh.gh / gh.Mc gh on the projected gradient gh.
+// Step k: gamma' = max(0, gamma - alpha g), g' = Mc gamma' + q, stop when
+// max |min(gamma', g')| <= tol; s = gamma' - gamma, y = g' - g; alpha =
+// s.s/s.y (k even) or s.y/y.y (k odd) when s.y > 0, clamped to
+// [1e-12, 1e12] * alpha0.
+#include <algorithm>
+#include <cmath>
+
+#include "rl_internal.hpp"
+
+namespace rl {
+
+static inline unsigned grid_of(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+static inline unsigned grid_of(int64_t n) { return grid_of(n, kBlock); }
+
+// ---------------------------------------------------------------------------
+// incidence structure and packing
+// ---------------------------------------------------------------------------
+// Checks 0 <= pi <= pj < n and pi non-decreasing; writes pptr[r] = first c
+// with pi[c] >= r (pptr[n] = nc).
+__global__ void k_check_pairs(int64_t n, int64_t nc, const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                              int32_t *__restrict__ pptr, int *__restrict__ err)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c > nc) return;
+    if (c == nc) {
+        // rods after the last constraint's pi (an invalid pi is reported by its own thread)
+        int64_t last = nc > 0 ? (int64_t)pi[nc - 1] : -1;
+        if (last < -1) last = -1;
+        for (int64_t r = last + 1; r <= n; ++r) pptr[r] = (int32_t)nc;
+        return;
+    }
+    const int64_t a = pi[c], b = pj[c];
+    if (a < 0 || b >= n || a > b) {
+        atomicOr(err, 1);
+        return;
+    }
+    int64_t prev = c > 0 ? (int64_t)pi[c - 1] : -1;
+    if (prev > a) {
+        atomicOr(err, 2);
+        return;
+    }
+    if (prev < -1) prev = -1;
+    for (int64_t r = prev + 1; r <= a; ++r) pptr[r] = (int32_t)c;
+}
+
+__global__ void k_qcount(int64_t nc, const int32_t *__restrict__ pj, int *__restrict__ qcnt)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    atomicAdd(qcnt + pj[c], 1);
+}
+
+__global__ void k_qfill(int64_t nc, const int32_t *__restrict__ pj, const int32_t *__restrict__ qptr,
+                        int *__restrict__ qcur, int32_t *__restrict__ qidx)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int r = pj[c];
+    qidx[qptr[r] + atomicAdd(qcur + r, 1)] = (int32_t)c;
+}
+
+// ascending constraint order inside each rod's Q-side list (fixes the
+// summation order of the rod kernel)
+__global__ void k_qsort(int64_t n, const int32_t *__restrict__ qptr, int32_t *__restrict__ qidx)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int b = qptr[r], e = qptr[r + 1];
+    for (int k = b + 1; k < e; ++k) {
+        const int32_t v = qidx[k];
+        int m = k - 1;
+        while (m >= b && qidx[m] > v) {
+            qidx[m + 1] = qidx[m];
+            --m;
+        }
+        qidx[m + 1] = v;
+    }
+}
+
+// constraint records: (pi, pj), (ex, ey, ez, s_i, s_j, q), (gamma, g = 0)
+__global__ void k_pack(int64_t nc, const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                       const double *__restrict__ e, const double *__restrict__ arm, const double *__restrict__ q,
+                       const double *__restrict__ gamma, int2 *__restrict__ pp, double *__restrict__ geo,
+                       double2 *__restrict__ st)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    pp[c] = make_int2(pi[c], pj[c]);
+    double2 *gd = reinterpret_cast<double2 *>(geo + 6 * c);
+    gd[0] = make_double2(e[3 * c], e[3 * c + 1]);
+    gd[1] = make_double2(e[3 * c + 2], arm[2 * c]);
+    gd[2] = make_double2(arm[2 * c + 1], q ? q[c] : 0.0);
+    st[c] = make_double2(gamma[c], 0.0);
+}
+
+// Q-side copies: qpos (inverse of qidx), the geometry a rod needs on its Q
+// side in list order, and the start iterate in list order
+__global__ void k_pack_q(int64_t nc, const int32_t *__restrict__ qidx, const double *__restrict__ geo,
+                         const double2 *__restrict__ st, int32_t *__restrict__ qpos, double *__restrict__ qgeo,
+                         double2 *__restrict__ stq)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nc) return;
+    const int c = qidx[k];
+    qpos[c] = (int32_t)k;
+    const double2 *gd = reinterpret_cast<const double2 *>(geo + 6 * (int64_t)c);
+    const double2 g0 = gd[0], g1 = gd[1], g2 = gd[2];
+    double2 *qd = reinterpret_cast<double2 *>(qgeo + 4 * k);
+    qd[0] = g0;
+    qd[1] = make_double2(g1.x, g2.x);
+    stq[k] = st[c];
+}
+
+__global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, double *__restrict__ gamma)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    gamma[c] = st[c].x;
+}
+
+hipError_t launch_scan(hipStream_t st, const int *in, int64_t m, int *out, int64_t *total);
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sums p[0..2] and takes the max of p[3] over the workgroup (fixed tree);
+// every thread receives the result.  lds holds NW x 4 doubles plus 4.
+template <int NW>
+__device__ __forceinline__ void block_reduce4_all(double p[4], double (*lds)[4])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    p[0] = wave_sum(p[0]);
+    p[1] = wave_sum(p[1]);
+    p[2] = wave_sum(p[2]);
+    p[3] = wave_max(p[3]);
+    if (lane == 0) {
+        lds[wid][0] = p[0];
+        lds[wid][1] = p[1];
+        lds[wid][2] = p[2];
+        lds[wid][3] = p[3];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NW; ++w) {
+            p[0] += lds[w][0];
+            p[1] += lds[w][1];
+            p[2] += lds[w][2];
+            p[3] = fmax(p[3], lds[w][3]);
+        }
+        lds[NW][0] = p[0];
+        lds[NW][1] = p[1];
+        lds[NW][2] = p[2];
+        lds[NW][3] = p[3];
+    }
+    __syncthreads();
+    p[0] = lds[NW][0];
+    p[1] = lds[NW][1];
+    p[2] = lds[NW][2];
+    p[3] = lds[NW][3];
+    __syncthreads();
+}
+
+// Totals of the gcon workgroup partials at `P`, identical in every workgroup.
+template <int NW>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ P, int gcon, double p[4], double (*lds)[4])
+{
+    p[0] = p[1] = p[2] = p[3] = 0.0;
+    for (int b = threadIdx.x; b < gcon; b += blockDim.x) {
+        const double2 *src = reinterpret_cast<const double2 *>(P + 4 * (int64_t)b);
+        const double2 u = src[0], v = src[1];
+        p[0] += u.x;
+        p[1] += u.y;
+        p[2] += v.x;
+        p[3] = fmax(p[3], v.y);
+    }
+    block_reduce4_all<NW>(p, lds);
+}
+
+// Stop test and step length for iteration k >= 1 from the totals of
+// iteration k-1 (s.s, s.y, y.y, residual); status RL_OK / NOT_CONVERGED /
+// STAGNATED / ERR_NONFINITE when stopping.
+struct Decision {
+    double alpha;
+    int stop, status;
+};
+
+__device__ __forceinline__ Decision decide(const SolveArgs &a, long long k, const double t[4])
+{
+    const SolverState *st = a.state;
+    Decision d{0.0, 0, RL_OK};
+    const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
+    if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
+        d.stop = 1;
+        d.status = RL_ERR_NONFINITE;
+    } else if (res <= st->tol) {
+        d.stop = 1;
+        d.status = RL_OK;
+    } else if (ss == 0.0) {
+        d.stop = 1;
+        d.status = RL_STAGNATED;
+    } else if (k >= st->max_iter) {
+        d.stop = 1;
+        d.status = RL_NOT_CONVERGED;
+    }
+    double al = a.alpha_buf[(k - 1) & 1];
+    if (sy > 0.0) {
+        al = ((k - 1) % 2 == 0) ? ss / sy : sy / yy;
+        al = al < st->amin ? st->amin : (al > st->amax ? st->amax : al);
+    }
+    d.alpha = al;
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// rod kernel
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ __forceinline__ double gamma_prime(double gam, double g, double alpha)
+{
+    if (MODE == kModeInit) return gam > 0.0 ? gam : 0.0;
+    if (MODE == kModeAlpha0) return (gam <= 0.0 && g > 0.0) ? 0.0 : g;
+    if (MODE == kModeLoop) {
+        const double v = fma(-alpha, g, gam);
+        return v > 0.0 ? v : 0.0;
+    }
+    return gam;
+}
+
+// Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
+// rod r, split over the four lanes of the rod and combined by a fixed tree.
+// The torque on the rod is dir x m.
+template <int MODE>
+__device__ __forceinline__ void rod_sums(const SolveArgs &a, int64_t r, bool active, int sub, double alpha,
+                                         double f[3], double m[3])
+{
+    f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
+    if (active) {
+        const int pb = a.pptr[r], pe = a.pptr[r + 1];
+        for (int c = pb + sub; c < pe; c += kRodLanes) {
+            const double2 sg = a.st[c];
+            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)c);
+            const double2 g0 = gd[0], g1 = gd[1];
+            const double gm = gamma_prime<MODE>(sg.x, sg.y, alpha);
+            const double gs = gm * g1.y;
+            f[0] += gm * g0.x;
+            f[1] += gm * g0.y;
+            f[2] += gm * g1.x;
+            m[0] += gs * g0.x;
+            m[1] += gs * g0.y;
+            m[2] += gs * g1.x;
+        }
+        const int qb = a.qptr[r], qe = a.qptr[r + 1];
+        for (int k = qb + sub; k < qe; k += kRodLanes) {
+            const double2 sg = a.stq[k];
+            const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)k);
+            const double2 g0 = gd[0], g1 = gd[1];
+            const double gm = gamma_prime<MODE>(sg.x, sg.y, alpha);
+            const double gs = gm * g1.y;
+            f[0] -= gm * g0.x;
+            f[1] -= gm * g0.y;
+            f[2] -= gm * g1.x;
+            m[0] -= gs * g0.x;
+            m[1] -= gs * g0.y;
+            m[2] -= gs * g1.x;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < kRodLanes; o <<= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[d] += __shfl_xor(f[d], o, 64);
+            m[d] += __shfl_xor(m[d], o, 64);
+        }
+    }
+}
+
+__device__ __forceinline__ void rod_mob(const SolveArgs &a, int64_t r, bool uni, double &apar, double &aperp,
+                                        double &rperp)
+{
+    if (uni) {
+        apar = a.mob.apar;
+        aperp = a.mob.aperp;
+        rperp = a.mob.rperp;
+    } else {
+        apar = a.coef[3 * r];
+        aperp = a.coef[3 * r + 1];
+        rperp = a.coef[3 * r + 2];
+    }
+}
+
+template <int MODE, bool UNI>
+__global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
+{
+    __shared__ double lds[kRodBlock / 64 + 1][4];
+    double alpha = 0.0;
+    if (MODE != kModeApply && a.state->done) return;
+    if (MODE == kModeLoop) {
+        if (k == 0) {
+            alpha = a.state->alpha;
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[0] = alpha;
+        } else {
+            double t[4];
+            sum_partials<kRodBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+            const Decision d = decide(a, k, t);
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                if (d.stop) {
+                    SolverState *st = a.state;
+                    st->iter = k;
+                    st->res = t[3];
+                    st->ss = t[0];
+                    st->sy = t[1];
+                    st->yy = t[2];
+                    st->status = d.status;
+                    st->done = 1;
+                } else {
+                    a.alpha_buf[k & 1] = d.alpha;
+                }
+            }
+            if (d.stop) return;
+            alpha = d.alpha;
+        }
+    }
+    const int sub = threadIdx.x & (kRodLanes - 1);
+    const int64_t r = (int64_t)blockIdx.x * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const bool active = r < a.n;
+    double f[3], m[3];
+    rod_sums<MODE>(a, r, active, sub, alpha, f, m);
+    if (!active || sub >= 3) return;
+    const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
+    double apar, aperp, rperp;
+    rod_mob(a, r, UNI, apar, aperp, rperp);
+    // translation a_perp f + (a_par - a_perp)(d.f) d; rotation Omega =
+    // r_perp dir x m (normal to the axis) and Omega x dir = r_perp (m - (d.m) d)
+    const double fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
+    const double md = dx * m[0] + dy * m[1] + dz * m[2];
+    double2 *out = reinterpret_cast<double2 *>(a.V + 6 * r);
+    if (sub == 0) out[0] = make_double2(aperp * f[0] + fd * dx, aperp * f[1] + fd * dy);
+    else if (sub == 1) out[1] = make_double2(aperp * f[2] + fd * dz, rperp * (m[0] - md * dx));
+    else out[2] = make_double2(rperp * (m[1] - md * dy), rperp * (m[2] - md * dz));
+}
+
+// ---------------------------------------------------------------------------
+// constraint kernel
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
+{
+    __shared__ double lds[kConBlock / 64 + 1][4];
+    if (MODE != kModeApply && a.state->done) return;
+    const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * kConBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kConBlock + threadIdx.x; c < a.nc; c += stride) {
+        const int2 ij = a.pp[c];
+        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
+        const double2 g0 = gd[0], g1 = gd[1], g2 = gd[2];
+        const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);
+        const double2 *Vj = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.y);
+        const double2 i0 = Vi[0], i1 = Vi[1], i2 = Vi[2];
+        const double2 j0 = Vj[0], j1 = Vj[1], j2 = Vj[2];
+        const double si = g1.y, sj = g2.x;
+        // velocity of the contact point on i minus that on j, along e
+        const double ux = (i0.x + si * i1.y) - (j0.x + sj * j1.y);
+        const double uy = (i0.y + si * i2.x) - (j0.y + sj * j2.x);
+        const double uz = (i1.x + si * i2.y) - (j1.x + sj * j2.y);
+        double w = g0.x * ux + g0.y * uy + g1.x * uz;
+        if (MODE == kModeApply) {
+            a.out[c] = w + g2.y;
+        } else if (MODE == kModeInit) {
+            w += g2.y;
+            const double gp = gamma_prime<kModeInit>(a.st[c].x, 0.0, 0.0);
+            a.st[c] = make_double2(gp, w);
+            a.stq[a.qpos[c]] = make_double2(gp, w);
+            p[2] += w * w;
+            p[3] = fmax(p[3], fabs(gp < w ? gp : w));
+        } else if (MODE == kModeAlpha0) {
+            const double2 sg = a.st[c];
+            const double gh = gamma_prime<kModeAlpha0>(sg.x, sg.y, 0.0);
+            p[0] += gh * gh;
+            p[1] += gh * w;
+        } else {
+            w += g2.y;
+            const double2 sg = a.st[c];
+            const double gp = gamma_prime<kModeLoop>(sg.x, sg.y, alpha);
+            const double sc = gp - sg.x, yc = w - sg.y;
+            a.st[c] = make_double2(gp, w);
+            a.stq[a.qpos[c]] = make_double2(gp, w);
+            p[0] += sc * sc;
+            p[1] += sc * yc;
+            p[2] += yc * yc;
+            p[3] = fmax(p[3], fabs(gp < w ? gp : w));
+        }
+    }
+    if (MODE == kModeApply) return;
+    block_reduce4_all<kConBlock / 64>(p, lds);
+    if (threadIdx.x == 0) {
+        double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)(k & 1) * a.gcon * 4 + 4 * blockIdx.x);
+        dst[0] = make_double2(p[0], p[1]);
+        dst[1] = make_double2(p[2], p[3]);
+    }
+}
+
+// One workgroup: totals of the start phases (g0 and the Cauchy step).
+template <int MODE>
+__global__ void __launch_bounds__(kRodBlock) k_fin(SolveArgs a)
+{
+    __shared__ double lds[kRodBlock / 64 + 1][4];
+    SolverState *st = a.state;
+    if (st->done) return;
+    double t[4];
+    sum_partials<kRodBlock / 64>(a.partial, a.gcon, t, lds);
+    if (threadIdx.x != 0) return;
+    if (MODE == kModeInit) {
+        st->res = t[3];
+        if (!isfinite(t[2]) || !isfinite(t[3])) {
+            st->status = RL_ERR_NONFINITE;
+            st->done = 1;
+        } else if (t[3] <= st->tol) {
+            st->status = RL_OK;
+            st->done = 1;
+        }
+    } else {
+        if (!isfinite(t[0]) || !isfinite(t[1])) {
+            st->status = RL_ERR_NONFINITE;
+            st->done = 1;
+            return;
+        }
+        if (t[0] == 0.0) {
+            st->status = RL_OK;
+            st->done = 1;
+            return;
+        }
+        const double a0 = t[1] > 0.0 ? t[0] / t[1] : 1.0;
+        st->alpha0 = a0;
+        st->alpha = a0;
+        st->amin = 1e-12 * a0;
+        st->amax = 1e12 * a0;
+        if (st->max_iter <= 0) {
+            st->status = RL_NOT_CONVERGED;
+            st->done = 1;
+        }
+    }
+}
+
+// U = M (D gamma + F) per rod, with the full 6x6 block (external torques may
+// have an axial part; the axial rotational mobility equals the normal one).
+// `perm` (may be null) maps the solver's rod order to the caller's.
+template <bool UNI>
+__global__ void __launch_bounds__(kRodBlock) k_velocity(SolveArgs a, const double *__restrict__ F,
+                                                        const int *__restrict__ perm, double *__restrict__ U)
+{
+    const int sub = threadIdx.x & (kRodLanes - 1);
+    const int64_t r = (int64_t)blockIdx.x * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const bool active = r < a.n;
+    double f[3], m[3];
+    rod_sums<kModeApply>(a, r, active, sub, 0.0, f, m);
+    if (!active || sub != 0) return;
+    const int64_t ro = perm ? (int64_t)perm[r] : r;
+    const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
+    // torque of the contact forces: dir x m
+    double tx = dy * m[2] - dz * m[1], ty = dz * m[0] - dx * m[2], tz = dx * m[1] - dy * m[0];
+    if (F) {
+        f[0] += F[6 * ro];
+        f[1] += F[6 * ro + 1];
+        f[2] += F[6 * ro + 2];
+        tx += F[6 * ro + 3];
+        ty += F[6 * ro + 4];
+        tz += F[6 * ro + 5];
+    }
+    double apar, aperp, rperp;
+    rod_mob(a, r, UNI, apar, aperp, rperp);
+    const double fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
+    double *u = U + 6 * ro;
+    u[0] = aperp * f[0] + fd * dx;
+    u[1] = aperp * f[1] + fd * dy;
+    u[2] = aperp * f[2] + fd * dz;
+    u[3] = rperp * tx;
+    u[4] = rperp * ty;
+    u[5] = rperp * tz;
+}
+
+__global__ void k_state_init(SolverState *st, double tol, long long max_iter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->alpha = st->alpha0 = 0.0;
+        st->amin = st->amax = 0.0;
+        st->res = st->ss = st->sy = st->yy = 0.0;
+        st->tol = tol;
+        st->iter = 0;
+        st->max_iter = max_iter;
+        st->done = 0;
+        st->status = RL_OK;
+    }
+}
+
+// x += h U_t wrapped into [0, box); theta += h Psi(theta) Omega, renormalised.
+__global__ void k_integrate(int64_t n, const double *__restrict__ U, double *__restrict__ x, double *__restrict__ quat,
+                            double dt, double b0, double b1, double b2)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double box[3] = {b0, b1, b2};
+    for (int a = 0; a < 3; ++a) {
+        double v = x[3 * i + a] + dt * U[6 * i + a];
+        v -= box[a] * floor(v / box[a]);
+        if (v >= box[a]) v -= box[a];
+        x[3 * i + a] = v;
+    }
+    const double wx = U[6 * i + 3], wy = U[6 * i + 4], wz = U[6 * i + 5];
+    double s = quat[4 * i], px = quat[4 * i + 1], py = quat[4 * i + 2], pz = quat[4 * i + 3];
+    // Psi(theta) Omega = 1/2 [ -p.Omega ; s Omega - p x Omega ]
+    const double ds = -0.5 * (px * wx + py * wy + pz * wz);
+    const double dpx = 0.5 * (s * wx - (py * wz - pz * wy));
+    const double dpy = 0.5 * (s * wy - (pz * wx - px * wz));
+    const double dpz = 0.5 * (s * wz - (px * wy - py * wx));
+    s += dt * ds;
+    px += dt * dpx;
+    py += dt * dpy;
+    pz += dt * dpz;
+    const double nrm = sqrt(s * s + px * px + py * py + pz * pz);
+    quat[4 * i] = s / nrm;
+    quat[4 * i + 1] = px / nrm;
+    quat[4 * i + 2] = py / nrm;
+    quat[4 * i + 3] = pz / nrm;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                  const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                  double *gamma, SolveArgs *out)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    int werr = 0;
+    SolveArgs s{};
+    s.n = n;
+    s.nc = nc;
+    s.dir = dir;
+    s.mob = mobility_host(len ? 1.0 : len0, p.diam, p.eta);
+    s.gcon = (int)std::min<int64_t>(std::max<int64_t>(grid_of(nc, kConBlock), 1), kConGridMax);
+    const int64_t nb = nc > 0 ? nc : 1, rb = n > 0 ? n : 1;
+    int32_t *pptr = (int32_t *)ws_get(h, kWsPptr, sizeof(int32_t) * (n + 1), &werr);
+    int32_t *qptr = (int32_t *)ws_get(h, kWsQptr, sizeof(int32_t) * (n + 1), &werr);
+    int32_t *qidx = (int32_t *)ws_get(h, kWsQidx, sizeof(int32_t) * nb, &werr);
+    int *qcnt = (int *)ws_get(h, kWsQcnt, sizeof(int) * rb, &werr);
+    int2 *pp = (int2 *)ws_get(h, kWsPP, sizeof(int2) * nb, &werr);
+    double *geo = (double *)ws_get(h, kWsGeo, sizeof(double) * 6 * nb, &werr);
+    s.st = (double2 *)ws_get(h, kWsSt, sizeof(double2) * nb, &werr);
+    s.stq = (double2 *)ws_get(h, kWsStq, sizeof(double2) * nb, &werr);
+    int32_t *qpos = (int32_t *)ws_get(h, kWsQpos, sizeof(int32_t) * nb, &werr);
+    double *qgeo = (double *)ws_get(h, kWsQgeo, sizeof(double) * 4 * nb, &werr);
+    s.V = (double *)ws_get(h, kWsV, sizeof(double) * 6 * rb, &werr);
+    s.partial = (double *)ws_get(h, kWsPartial, sizeof(double) * 8 * s.gcon, &werr);
+    s.alpha_buf = (double *)ws_get(h, kWsAlpha, sizeof(double) * 2, &werr);
+    double *coef = len ? (double *)ws_get(h, kWsCoef, sizeof(double) * 3 * rb, &werr) : nullptr;
+    if (werr) return werr;
+    s.coef = coef;
+    s.pptr = pptr;
+    s.qptr = qptr;
+    s.qidx = qidx;
+    s.pp = pp;
+    s.geo = geo;
+    s.qpos = qpos;
+    s.qgeo = qgeo;
+    s.state = h->state;
+    if (len) RL_HIP(launch_mobility_coeffs(st, n, len, p.diam, p.eta, coef));
+    RL_HIP(hipMemsetAsync(h->flag_dev, 0, sizeof(int), st));
+    hipLaunchKernelGGL(k_check_pairs, dim3(grid_of(nc + 1)), dim3(kBlock), 0, st, n, nc, pi, pj, pptr, h->flag_dev);
+    RL_HIP(hipGetLastError());
+    RL_HIP(hipMemcpyAsync(h->host_scratch, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipStreamSynchronize(st));
+    const int ferr = ((int *)h->host_scratch)[0];
+    if (ferr) {
+        set_error(ferr & 1 ? "pair indices must satisfy 0 <= pi <= pj < n" : "pi must be non-decreasing");
+        return RL_ERR_ARG;
+    }
+    if (n > 0) {
+        RL_HIP(hipMemsetAsync(qcnt, 0, sizeof(int) * n, st));
+        if (nc > 0) {
+            hipLaunchKernelGGL(k_qcount, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pj, qcnt);
+            RL_HIP(hipGetLastError());
+        }
+        RL_HIP(launch_scan(st, qcnt, n, qptr, nullptr));
+        if (nc > 0) {
+            RL_HIP(hipMemsetAsync(qcnt, 0, sizeof(int) * n, st));
+            hipLaunchKernelGGL(k_qfill, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pj, (const int32_t *)qptr, qcnt,
+                               qidx);
+            RL_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_qsort, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int32_t *)qptr, qidx);
+            RL_HIP(hipGetLastError());
+        }
+    }
+    if (nc > 0) {
+        hipLaunchKernelGGL(k_pack, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pi, pj, e, arm, q,
+                           (const double *)gamma, pp, geo, s.st);
+        RL_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_pack_q, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, (const int32_t *)qidx,
+                           (const double *)geo, (const double2 *)s.st, qpos, qgeo, s.stq);
+        RL_HIP(hipGetLastError());
+    }
+    *out = s;
+    return RL_OK;
+}
+
+template <int MODE>
+static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long long k)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
+    if (uni)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodBlock), 0, st, a, k);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false>), grid, dim3(kRodBlock), 0, st, a, k);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_con(hipStream_t st, const SolveArgs &a, long long k)
+{
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE>), dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
+    return hipGetLastError();
+}
+
+int apply_impl(rl_ctx *h, SolveArgs &a, double *w)
+{
+    if (a.nc == 0) return RL_OK;
+    a.out = w;
+    RL_HIP(launch_rod<kModeApply>(h->stream, a, a.coef == nullptr, 0));
+    RL_HIP(launch_con<kModeApply>(h->stream, a, 0));
+    return RL_OK;
+}
+
+// one loop iteration with events before, between and after its two kernels
+static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs &a, bool uni)
+{
+    hipStream_t st = h->stream;
+    for (int k = 0; k < 3; ++k)
+        if (!h->ev[v][k]) {
+            hipError_t e = hipEventCreate(&h->ev[v][k]);
+            if (e != hipSuccess) return e;
+        }
+    h->ev_iter[v] = it;
+    hipError_t e;
+    if ((e = hipEventRecord(h->ev[v][0], st)) != hipSuccess) return e;
+    if ((e = launch_rod<kModeLoop>(st, a, uni, it)) != hipSuccess) return e;
+    if ((e = hipEventRecord(h->ev[v][1], st)) != hipSuccess) return e;
+    if ((e = launch_con<kModeLoop>(st, a, it)) != hipSuccess) return e;
+    return hipEventRecord(h->ev[v][2], st);
+}
+
+int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamma_out, rl_solve_info *info,
+               const int *perm)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    const bool uni = a.coef == nullptr;
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, st, h->state, p.tol, (long long)p.max_iter);
+    RL_HIP(hipGetLastError());
+    long long iters = 0;
+    if (a.nc > 0) {
+        RL_HIP(launch_rod<kModeInit>(st, a, uni, 0));
+        RL_HIP(launch_con<kModeInit>(st, a, 0));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeInit>), dim3(1), dim3(kRodBlock), 0, st, a);
+        RL_HIP(hipGetLastError());
+        RL_HIP(launch_rod<kModeAlpha0>(st, a, uni, 0));
+        RL_HIP(launch_con<kModeAlpha0>(st, a, 0));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
+        RL_HIP(hipGetLastError());
+        const int every = p.check_every > 0 ? p.check_every : 32;
+        for (long long launched = 0;; launched += every) {
+            if (launched > p.max_iter + every) {
+                set_error("rl_solve_lcp: stop flag never raised");
+                return RL_ERR_HIP;
+            }
+            int nev = 0;
+            for (int k = 0; k < every; ++k) {
+                const long long it = launched + k;
+                const bool samp = h->prof_every > 0 && it % h->prof_every == 0 && nev < rl_ctx::kMaxEv;
+                if (samp) {
+                    RL_HIP(record_sample(h, nev, it, a, uni));
+                    ++nev;
+                } else {
+                    RL_HIP(launch_rod<kModeLoop>(st, a, uni, it));
+                    RL_HIP(launch_con<kModeLoop>(st, a, it));
+                }
+            }
+            RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+            RL_HIP(hipStreamSynchronize(st));
+            const bool done = h->state_host->done;
+            // samples at or after the stop iteration ran kernels that exited at once
+            const long long valid = done ? h->state_host->iter : launched + every;
+            for (int v = 0; v < nev; ++v) {
+                if (h->ev_iter[v] >= valid) continue;
+                float t0 = 0.f, t1 = 0.f;
+                RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
+                RL_HIP(hipEventElapsedTime(&t1, h->ev[v][1], h->ev[v][2]));
+                h->prof_ms[0] += t0;
+                h->prof_ms[1] += t1;
+                h->prof_cnt[0] += 1.0;
+                h->prof_cnt[1] += 1.0;
+            }
+            if (done) break;
+        }
+        iters = h->state_host->iter;
+        if (gamma_out) {
+            hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
+                               (const double2 *)a.st, gamma_out);
+            RL_HIP(hipGetLastError());
+        }
+    } else {
+        RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+    }
+    if (U && a.n > 0) {
+        const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
+        if (uni)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<true>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<false>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
+        RL_HIP(hipGetLastError());
+    }
+    RL_HIP(hipStreamSynchronize(st));
+    const SolverState &s = *h->state_host;
+    const int status = a.nc > 0 ? s.status : RL_OK;
+    if (info) {
+        info->iterations = a.nc > 0 ? iters : 0;
+        info->residual = a.nc > 0 ? s.res : 0.0;
+        info->alpha0 = s.alpha0;
+        info->status = status;
+        info->reserved = 0;
+    }
+    if (status == RL_ERR_NONFINITE) set_error("rl_solve_lcp: non-finite value in q or an iterate");
+    return status;
+}
+
+int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat)
+{
+    if (n <= 0) return RL_OK;
+    const rl_params &p = h->prm;
+    hipLaunchKernelGGL(k_integrate, dim3(grid_of(n)), dim3(kBlock), 0, h->stream, n, U, x, quat, p.dt, p.box[0],
+                       p.box[1], p.box[2]);
+    RL_HIP(hipGetLastError());
+    return RL_OK;
+}
+
+}  // namespace rl
