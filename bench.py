@@ -33,14 +33,16 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f) for f in
 
 
 def kernel_bytes(n: int, nc: int) -> dict:
-    """Algorithmic bytes per launch: every array element the kernel must touch
-    once (FP64 values, int32 indices).
-    rod kernel:        per rod pptr+qptr 8, dir 24, V write 48       -> 80 n
-                       per constraint gamma 8, g 8, e 24, arm 16, qidx 4 -> 60 nc
-    constraint kernel: per constraint pi+pj 8, e 24, arm 16, q 8,
-                       gamma r/w 16, g r/w 16                        -> 88 nc
-                       per rod V read 48                             -> 48 n"""
-    return {"rod": 80 * n + 60 * nc, "con": 88 * nc + 48 * n}
+    """Algorithmic bytes per launch of the two BBPGD loop kernels: every array
+    element the kernel must touch once (FP64 values, int32 indices).
+    rod kernel:        per rod pptr+qptr 8, dir 24, V write 48        -> 80 n
+                       per constraint, P side: (gamma, g) 16, (e, s_i) 32;
+                       Q side copy: (gamma, g) 16, (e, s_j) 32        -> 96 nc
+    constraint kernel: per constraint (pi, pj) 8, (e, s_i, s_j, q) 48,
+                       (gamma, g) read 16 + write 16, qpos 4,
+                       Q-side (gamma, g) write 16                     -> 108 nc
+                       per rod V read 48                              -> 48 n"""
+    return {"rod": 80 * n + 96 * nc, "con": 108 * nc + 48 * n}
 
 
 def source_hash() -> str:
@@ -93,6 +95,8 @@ def main() -> int:
     ap.add_argument("--profile-every", type=int, default=8, help="sample kernel events every k-th iteration")
     ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy a 1 GiB device buffer once (reference for HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -176,6 +180,14 @@ def main() -> int:
                                "samples": prof[f"{k}_launches"]} for k in ("rod", "con")},
     }
     slv.close()
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -152,7 +152,7 @@ int rl_destroy(rl_handle h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     for (int v = 0; v < rl_ctx::kMaxEv; ++v)
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 4; ++k)
             if (h->ev[v][k]) (void)hipEventDestroy(h->ev[v][k]);
     for (int s = 0; s < rl_ctx::kSlots; ++s)
         if (h->buf[s]) (void)hipFree(h->buf[s]);

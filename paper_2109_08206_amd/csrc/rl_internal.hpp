@@ -109,7 +109,7 @@ struct rl_ctx {
     // event sampling of the loop kernels
     static constexpr int kMaxEv = 64;
     int prof_every = 0;
-    hipEvent_t ev[kMaxEv][3] = {};
+    hipEvent_t ev[kMaxEv][4] = {};  // start/stop of the rod and the constraint kernel
     long long ev_iter[kMaxEv] = {};
     double prof_ms[2] = {0.0, 0.0};
     double prof_cnt[2] = {0.0, 0.0};

@@ -32,6 +32,8 @@
 // max |min(gamma', g')| <= tol; s = gamma' - gamma, y = g' - g; alpha =
 // s.s/s.y (k even) or s.y/y.y (k odd) when s.y > 0, clamped to
 // [1e-12, 1e12] * alpha0.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -271,40 +273,90 @@ __device__ __forceinline__ double gamma_prime(double gam, double g, double alpha
 
 // Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
 // rod r, split over the four lanes of the rod and combined by a fixed tree.
-// The torque on the rod is dir x m.
+// The torque on the rod is dir x m.  The first P-side and the first Q-side
+// record of each lane are loaded together (one memory round for almost every
+// rod: a lane holds up to four incidences per side in its first round);
+// longer lists continue in a loop.
+struct RodLoads {
+    int pb, pe, qb, qe;
+    double2 ps, pg0, pg1;  // first P record: (gamma, g), (ex, ey), (ez, s_i)
+    double2 qs, qg0, qg1;  // first Q record: (gamma, g), (ex, ey), (ez, s_j)
+};
+
+__device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
+{
+    L.pb = L.pe = L.qb = L.qe = 0;
+    if (active) {
+        L.pb = a.pptr[r] + sub;
+        L.pe = a.pptr[r + 1];
+        L.qb = a.qptr[r] + sub;
+        L.qe = a.qptr[r + 1];
+    }
+    const double2 z = make_double2(0.0, 0.0);
+    L.ps = L.pg0 = L.pg1 = L.qs = L.qg0 = L.qg1 = z;
+    if (L.pb < L.pe) {
+        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)L.pb);
+        L.ps = a.st[L.pb];
+        L.pg0 = gd[0];
+        L.pg1 = gd[1];
+    }
+    if (L.qb < L.qe) {
+        const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)L.qb);
+        L.qs = a.stq[L.qb];
+        L.qg0 = gd[0];
+        L.qg1 = gd[1];
+    }
+}
+
 template <int MODE>
-__device__ __forceinline__ void rod_sums(const SolveArgs &a, int64_t r, bool active, int sub, double alpha,
-                                         double f[3], double m[3])
+__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads &L, double alpha, double f[3],
+                                               double m[3])
 {
     f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    if (active) {
-        const int pb = a.pptr[r], pe = a.pptr[r + 1];
-        for (int c = pb + sub; c < pe; c += kRodLanes) {
+    if (L.pb < L.pe) {
+        const double gm = gamma_prime<MODE>(L.ps.x, L.ps.y, alpha);
+        const double gs = gm * L.pg1.y;
+        f[0] += gm * L.pg0.x;
+        f[1] += gm * L.pg0.y;
+        f[2] += gm * L.pg1.x;
+        m[0] += gs * L.pg0.x;
+        m[1] += gs * L.pg0.y;
+        m[2] += gs * L.pg1.x;
+        for (int c = L.pb + kRodLanes; c < L.pe; c += kRodLanes) {
             const double2 sg = a.st[c];
             const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)c);
             const double2 g0 = gd[0], g1 = gd[1];
-            const double gm = gamma_prime<MODE>(sg.x, sg.y, alpha);
-            const double gs = gm * g1.y;
-            f[0] += gm * g0.x;
-            f[1] += gm * g0.y;
-            f[2] += gm * g1.x;
-            m[0] += gs * g0.x;
-            m[1] += gs * g0.y;
-            m[2] += gs * g1.x;
+            const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
+            const double gsc = gmc * g1.y;
+            f[0] += gmc * g0.x;
+            f[1] += gmc * g0.y;
+            f[2] += gmc * g1.x;
+            m[0] += gsc * g0.x;
+            m[1] += gsc * g0.y;
+            m[2] += gsc * g1.x;
         }
-        const int qb = a.qptr[r], qe = a.qptr[r + 1];
-        for (int k = qb + sub; k < qe; k += kRodLanes) {
+    }
+    if (L.qb < L.qe) {
+        const double gm = gamma_prime<MODE>(L.qs.x, L.qs.y, alpha);
+        const double gs = gm * L.qg1.y;
+        f[0] -= gm * L.qg0.x;
+        f[1] -= gm * L.qg0.y;
+        f[2] -= gm * L.qg1.x;
+        m[0] -= gs * L.qg0.x;
+        m[1] -= gs * L.qg0.y;
+        m[2] -= gs * L.qg1.x;
+        for (int k = L.qb + kRodLanes; k < L.qe; k += kRodLanes) {
             const double2 sg = a.stq[k];
             const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)k);
             const double2 g0 = gd[0], g1 = gd[1];
-            const double gm = gamma_prime<MODE>(sg.x, sg.y, alpha);
-            const double gs = gm * g1.y;
-            f[0] -= gm * g0.x;
-            f[1] -= gm * g0.y;
-            f[2] -= gm * g1.x;
-            m[0] -= gs * g0.x;
-            m[1] -= gs * g0.y;
-            m[2] -= gs * g1.x;
+            const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
+            const double gsc = gmc * g1.y;
+            f[0] -= gmc * g0.x;
+            f[1] -= gmc * g0.y;
+            f[2] -= gmc * g1.x;
+            m[0] -= gsc * g0.x;
+            m[1] -= gsc * g0.y;
+            m[2] -= gsc * g1.x;
         }
     }
 #pragma unroll
@@ -315,6 +367,16 @@ __device__ __forceinline__ void rod_sums(const SolveArgs &a, int64_t r, bool act
             m[d] += __shfl_xor(m[d], o, 64);
         }
     }
+}
+
+// Workgroup -> work-tile map that gives each of the eight XCDs (which take
+// workgroups round-robin) a contiguous range of tiles, so that the rods and
+// constraints one XCD works on are neighbours in space and share its L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks)
+{
+    constexpr unsigned kXcd = 8;
+    if (nblocks % kXcd != 0) return b;
+    return (b % kXcd) * (nblocks / kXcd) + b / kXcd;
 }
 
 __device__ __forceinline__ void rod_mob(const SolveArgs &a, int64_t r, bool uni, double &apar, double &aperp,
@@ -337,6 +399,13 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
     __shared__ double lds[kRodBlock / 64 + 1][4];
     double alpha = 0.0;
     if (MODE != kModeApply && a.state->done) return;
+    const int sub = threadIdx.x & (kRodLanes - 1);
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const bool active = r < a.n;
+    // the incidence records do not depend on the step length: load them first
+    RodLoads L;
+    rod_load(a, r, active, sub, L);
     if (MODE == kModeLoop) {
         if (k == 0) {
             alpha = a.state->alpha;
@@ -363,11 +432,8 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
             alpha = d.alpha;
         }
     }
-    const int sub = threadIdx.x & (kRodLanes - 1);
-    const int64_t r = (int64_t)blockIdx.x * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
-    const bool active = r < a.n;
     double f[3], m[3];
-    rod_sums<MODE>(a, r, active, sub, alpha, f, m);
+    rod_accumulate<MODE>(a, L, alpha, f, m);
     if (!active || sub >= 3) return;
     const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
     double apar, aperp, rperp;
@@ -385,6 +451,70 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
 // ---------------------------------------------------------------------------
 // constraint kernel
 // ---------------------------------------------------------------------------
+// One constraint: w = e.(V_i + s_i W_i - V_j - s_j W_j) (+ q), from records
+// loaded beforehand so that two constraints' gathers are in flight at once.
+struct ConLoads {
+    double2 g0, g1, g2, sg;
+    int qp;
+    double2 i0, i1, i2, j0, j1, j2;
+};
+
+template <int MODE>
+__device__ __forceinline__ void con_load(const SolveArgs &a, int64_t c, ConLoads &L)
+{
+    const int2 ij = a.pp[c];
+    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
+    L.g0 = gd[0];
+    L.g1 = gd[1];
+    L.g2 = gd[2];
+    if (MODE != kModeApply) L.sg = a.st[c];
+    if (MODE == kModeInit || MODE == kModeLoop) L.qp = a.qpos[c];
+    const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);
+    const double2 *Vj = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.y);
+    L.i0 = Vi[0];
+    L.i1 = Vi[1];
+    L.i2 = Vi[2];
+    L.j0 = Vj[0];
+    L.j1 = Vj[1];
+    L.j2 = Vj[2];
+}
+
+template <int MODE>
+__device__ __forceinline__ void con_update(const SolveArgs &a, int64_t c, const ConLoads &L, double alpha,
+                                           double p[4])
+{
+    const double si = L.g1.y, sj = L.g2.x;
+    // velocity of the contact point on i minus that on j, along e
+    const double ux = (L.i0.x + si * L.i1.y) - (L.j0.x + sj * L.j1.y);
+    const double uy = (L.i0.y + si * L.i2.x) - (L.j0.y + sj * L.j2.x);
+    const double uz = (L.i1.x + si * L.i2.y) - (L.j1.x + sj * L.j2.y);
+    double w = L.g0.x * ux + L.g0.y * uy + L.g1.x * uz;
+    if (MODE == kModeApply) {
+        a.out[c] = w + L.g2.y;
+    } else if (MODE == kModeInit) {
+        w += L.g2.y;
+        const double gp = gamma_prime<kModeInit>(L.sg.x, 0.0, 0.0);
+        a.st[c] = make_double2(gp, w);
+        a.stq[L.qp] = make_double2(gp, w);
+        p[2] += w * w;
+        p[3] = fmax(p[3], fabs(gp < w ? gp : w));
+    } else if (MODE == kModeAlpha0) {
+        const double gh = gamma_prime<kModeAlpha0>(L.sg.x, L.sg.y, 0.0);
+        p[0] += gh * gh;
+        p[1] += gh * w;
+    } else {
+        w += L.g2.y;
+        const double gp = gamma_prime<kModeLoop>(L.sg.x, L.sg.y, alpha);
+        const double sc = gp - L.sg.x, yc = w - L.sg.y;
+        a.st[c] = make_double2(gp, w);
+        a.stq[L.qp] = make_double2(gp, w);
+        p[0] += sc * sc;
+        p[1] += sc * yc;
+        p[2] += yc * yc;
+        p[3] = fmax(p[3], fabs(gp < w ? gp : w));
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
 {
@@ -392,47 +522,17 @@ __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
     if (MODE != kModeApply && a.state->done) return;
     const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t stride = (int64_t)gridDim.x * kConBlock;
-    for (int64_t c = (int64_t)blockIdx.x * kConBlock + threadIdx.x; c < a.nc; c += stride) {
-        const int2 ij = a.pp[c];
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
-        const double2 g0 = gd[0], g1 = gd[1], g2 = gd[2];
-        const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);
-        const double2 *Vj = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.y);
-        const double2 i0 = Vi[0], i1 = Vi[1], i2 = Vi[2];
-        const double2 j0 = Vj[0], j1 = Vj[1], j2 = Vj[2];
-        const double si = g1.y, sj = g2.x;
-        // velocity of the contact point on i minus that on j, along e
-        const double ux = (i0.x + si * i1.y) - (j0.x + sj * j1.y);
-        const double uy = (i0.y + si * i2.x) - (j0.y + sj * j2.x);
-        const double uz = (i1.x + si * i2.y) - (j1.x + sj * j2.y);
-        double w = g0.x * ux + g0.y * uy + g1.x * uz;
-        if (MODE == kModeApply) {
-            a.out[c] = w + g2.y;
-        } else if (MODE == kModeInit) {
-            w += g2.y;
-            const double gp = gamma_prime<kModeInit>(a.st[c].x, 0.0, 0.0);
-            a.st[c] = make_double2(gp, w);
-            a.stq[a.qpos[c]] = make_double2(gp, w);
-            p[2] += w * w;
-            p[3] = fmax(p[3], fabs(gp < w ? gp : w));
-        } else if (MODE == kModeAlpha0) {
-            const double2 sg = a.st[c];
-            const double gh = gamma_prime<kModeAlpha0>(sg.x, sg.y, 0.0);
-            p[0] += gh * gh;
-            p[1] += gh * w;
-        } else {
-            w += g2.y;
-            const double2 sg = a.st[c];
-            const double gp = gamma_prime<kModeLoop>(sg.x, sg.y, alpha);
-            const double sc = gp - sg.x, yc = w - sg.y;
-            a.st[c] = make_double2(gp, w);
-            a.stq[a.qpos[c]] = make_double2(gp, w);
-            p[0] += sc * sc;
-            p[1] += sc * yc;
-            p[2] += yc * yc;
-            p[3] = fmax(p[3], fabs(gp < w ? gp : w));
-        }
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    // each workgroup takes a contiguous chunk of constraints, two per lane per round
+    const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
+    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += 2 * kConBlock) {
+        const int64_t c1 = c0 + kConBlock;
+        ConLoads A, B;
+        con_load<MODE>(a, c0, A);
+        if (c1 < hi) con_load<MODE>(a, c1, B);
+        con_update<MODE>(a, c0, A, alpha, p);
+        if (c1 < hi) con_update<MODE>(a, c1, B, alpha, p);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<kConBlock / 64>(p, lds);
@@ -495,8 +595,10 @@ __global__ void __launch_bounds__(kRodBlock) k_velocity(SolveArgs a, const doubl
     const int sub = threadIdx.x & (kRodLanes - 1);
     const int64_t r = (int64_t)blockIdx.x * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < a.n;
+    RodLoads L;
+    rod_load(a, r, active, sub, L);
     double f[3], m[3];
-    rod_sums<kModeApply>(a, r, active, sub, 0.0, f, m);
+    rod_accumulate<kModeApply>(a, L, 0.0, f, m);
     if (!active || sub != 0) return;
     const int64_t ro = perm ? (int64_t)perm[r] : r;
     const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
@@ -582,7 +684,9 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     s.nc = nc;
     s.dir = dir;
     s.mob = mobility_host(len ? 1.0 : len0, p.diam, p.eta);
-    s.gcon = (int)std::min<int64_t>(std::max<int64_t>(grid_of(nc, kConBlock), 1), kConGridMax);
+    // constraint workgroups: about two constraints per lane, at most kConGridMax, a multiple of 8 (XCDs)
+    int64_t gc = std::min<int64_t>(std::max<int64_t>(grid_of(nc, 2 * kConBlock), 1), kConGridMax);
+    s.gcon = (int)((gc + 7) / 8 * 8);
     const int64_t nb = nc > 0 ? nc : 1, rb = n > 0 ? n : 1;
     int32_t *pptr = (int32_t *)ws_get(h, kWsPptr, sizeof(int32_t) * (n + 1), &werr);
     int32_t *qptr = (int32_t *)ws_get(h, kWsQptr, sizeof(int32_t) * (n + 1), &werr);
@@ -647,11 +751,14 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     return RL_OK;
 }
 
+// rod kernel grid: a multiple of 8 so that each XCD gets a contiguous range of rods
+static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodBlock / kRodLanes) + 7) / 8 * 8; }
+
 template <int MODE>
 static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long long k)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
+    const dim3 grid(rod_grid(a.n));
     if (uni)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodBlock), 0, st, a, k);
     else
@@ -675,22 +782,31 @@ int apply_impl(rl_ctx *h, SolveArgs &a, double *w)
     return RL_OK;
 }
 
-// one loop iteration with events before, between and after its two kernels
+// One loop iteration whose two kernels are launched with start/stop events
+// taken by the dispatch itself (the same span a kernel trace reports).
 static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs &a, bool uni)
 {
     hipStream_t st = h->stream;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
         if (!h->ev[v][k]) {
             hipError_t e = hipEventCreate(&h->ev[v][k]);
             if (e != hipSuccess) return e;
         }
     h->ev_iter[v] = it;
-    hipError_t e;
-    if ((e = hipEventRecord(h->ev[v][0], st)) != hipSuccess) return e;
-    if ((e = launch_rod<kModeLoop>(st, a, uni, it)) != hipSuccess) return e;
-    if ((e = hipEventRecord(h->ev[v][1], st)) != hipSuccess) return e;
-    if ((e = launch_con<kModeLoop>(st, a, it)) != hipSuccess) return e;
-    return hipEventRecord(h->ev[v][2], st);
+    if (a.n > 0) {
+        const dim3 grid(rod_grid(a.n));
+        if (uni)
+            hipExtLaunchKernelGGL(k_rod<kModeLoop, true>, grid, dim3(kRodBlock), 0, st, h->ev[v][0], h->ev[v][1], 0,
+                                  a, (long long)it);
+        else
+            hipExtLaunchKernelGGL(k_rod<kModeLoop, false>, grid, dim3(kRodBlock), 0, st, h->ev[v][0], h->ev[v][1],
+                                  0, a, (long long)it);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipExtLaunchKernelGGL(k_con<kModeLoop>, dim3(a.gcon), dim3(kConBlock), 0, st, h->ev[v][2], h->ev[v][3], 0, a,
+                          (long long)it);
+    return hipGetLastError();
 }
 
 int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamma_out, rl_solve_info *info,
@@ -737,8 +853,8 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
             for (int v = 0; v < nev; ++v) {
                 if (h->ev_iter[v] >= valid) continue;
                 float t0 = 0.f, t1 = 0.f;
-                RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
-                RL_HIP(hipEventElapsedTime(&t1, h->ev[v][1], h->ev[v][2]));
+                if (a.n > 0) RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
+                RL_HIP(hipEventElapsedTime(&t1, h->ev[v][2], h->ev[v][3]));
                 h->prof_ms[0] += t0;
                 h->prof_ms[1] += t1;
                 h->prof_cnt[0] += 1.0;
