@@ -79,7 +79,12 @@ extern "C" {
 #define RL_ERR_NOMEM (-5)   /* workspace allocation failed */
 
 #define RL_FP64 0           /* all solver arithmetic in double precision */
-#define RL_FP32_MIXED 1     /* single-precision products, double reductions */
+#define RL_FP32_MIXED 1     /* BBPGD in single precision on a correction delta to an
+                               FP64 iterate (gamma = gamma64 + delta); the BB dot
+                               products and residuals accumulate in FP64 and an
+                               FP64 product re-anchors gamma64 and g whenever the
+                               FP32 residual has dropped by 1e-4 (or stalls); the
+                               stop test and the returned residual are FP64 */
 
 typedef struct rl_ctx *rl_handle;
 
@@ -97,10 +102,11 @@ typedef struct {
 
 typedef struct {
     int64_t iterations; /* BBPGD iterations taken (products Mc*gamma in the loop) */
-    double residual;    /* max_c |min(gamma_c, w_c)| at exit */
+    double residual;    /* max_c |min(gamma_c, w_c)| at exit, evaluated in FP64 */
     double alpha0;      /* initial step length */
     int32_t status;     /* RL_OK, RL_NOT_CONVERGED or RL_STAGNATED */
-    int32_t reserved;
+    int32_t fp64_refreshes; /* RL_FP32_MIXED: FP64 products that re-anchored the
+                               FP32 iteration (0 in RL_FP64) */
 } rl_solve_info;
 
 /* Handle lifecycle.  rl_create copies *prm (validated: RL_ERR_ARG on a bad

@@ -41,7 +41,7 @@ class Params(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("residual", C.c_double), ("alpha0", C.c_double),
-                ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("status", C.c_int32), ("fp64_refreshes", C.c_int32)]
 
 
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
@@ -121,6 +121,12 @@ class SolveResult:
     residual: float
     alpha0: float
     status: int
+    fp64_refreshes: int = 0
+
+
+def _result(info) -> "SolveResult":
+    return SolveResult(int(info.iterations), float(info.residual), float(info.alpha0), int(info.status),
+                       int(info.fp64_refreshes))
 
 
 class Solver:
@@ -268,8 +274,7 @@ class Solver:
             _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
             _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
         self._check(rc, "rl_solve_lcp")
-        return gamma, U, SolveResult(int(info.iterations), float(info.residual), float(info.alpha0),
-                                     int(info.status))
+        return gamma, U, _result(info)
 
     def step(self, x, quat, length, F=None, U=None):
         """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs)."""
@@ -285,8 +290,7 @@ class Solver:
                               _ptr(F, torch.float64, (n, 6), "F"), _ptr(U, torch.float64, (n, 6), "U"),
                               C.byref(info), C.byref(npairs))
         self._check(rc, "rl_step")
-        return U, SolveResult(int(info.iterations), float(info.residual), float(info.alpha0),
-                              int(info.status)), int(npairs.value)
+        return U, _result(info), int(npairs.value)
 
 
 def status_str(status: int) -> str:

@@ -25,6 +25,7 @@ enum Mode : int {
     kModeAlpha0 = 1,  // gamma' = projected gradient: alpha0 = gh.gh / gh.Mc gh
     kModeLoop = 2,    // gamma' = max(0, gamma - alpha g): one BBPGD iteration
     kModeApply = 3,   // gamma' = gamma (no projection): w = Mc gamma (+ q)
+    kModeRefresh = 4, // mixed precision: FP64 g = Mc gamma + q, residual, FP32 state reset
 };
 
 // Device-resident solver state.  The loop kernels never write fields that
@@ -39,6 +40,12 @@ struct SolverState {
     double res, ss, sy, yy;
     long long iter;
     int done, status;
+    // mixed precision: inner rounds run until the FP32 residual is below
+    // inner_tol; then an FP64 refresh recomputes g and the certified residual
+    double inner_tol, rho64;
+    long long refreshes;
+    int refresh;  // set by the rod kernel when the inner round ends
+    int pad;
 };
 
 // Per-rod mobility: a_par, a_perp (translation along / normal to the axis),
@@ -76,6 +83,13 @@ struct SolveArgs {
     int gcon;               // workgroups of the constraint kernel
     SolverState *state;
     double *out;            // kModeApply output
+    // mixed precision (RL_FP32_MIXED): gamma = gamma64 + delta with delta >= b = -gamma64
+    float4 *st32;           // [nc] (delta, h, b, h0): h approximates g, h0 = g at the last refresh
+    float4 *stq32;          // [nc] (delta, h, b, 0) in Q-side list order
+    const float4 *geo32;    // [nc] (ex, ey, ez, s_i)
+    const float *sj32;      // [nc] s_j
+    const float4 *qgeo32;   // [nc] Q-side list order: (ex, ey, ez, s_j)
+    float *V32;             // [n][8] (V, W, pad)
 };
 
 // --- kernels launchers (implemented in the .hip files) ----------------------
@@ -122,6 +136,7 @@ enum Slot : int {
     kWsCellOf, kWsCellCnt, kWsCellStart, kWsCellCur, kWsSorted, kWsXs, kWsDs, kWsLs, kWsPcnt, kWsPoff,
     kWsStepPi, kWsStepPj, kWsStepImg, kWsStepFlags, kWsStepPhi, kWsStepE, kWsStepArm, kWsStepQ, kWsStepGamma,
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
+    kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -151,6 +166,14 @@ int apply_impl(rl_ctx *h, SolveArgs &a, double *w);
 int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamma_out, rl_solve_info *info,
                const int *perm = nullptr);
 int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat);
+// mixed precision: FP32 copies of the geometry, then the refinement loop
+int prepare_mixed(rl_ctx *h, SolveArgs &a);
+int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes);
+// FP64 refresh for the mixed solver: gamma64 += delta (if accum), g64 = Mc gamma64 + q,
+// certified residual, FP32 state reset
+hipError_t launch_refresh64(rl_ctx *h, const SolveArgs &a, bool accum);
+hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a);
+hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U);
 
 }  // namespace rl
 

@@ -1,0 +1,346 @@
+// Mixed-precision BBPGD (RL_FP32_MIXED) on gfx950.
+//
+// The iterate is split as gamma = gamma64 + delta.  gamma64 and g64 =
+// Mc gamma64 + q are double precision and are recomputed only by FP64
+// "refresh" products; between refreshes the BB iteration runs in single
+// precision on the correction delta >= b = -gamma64, with h = h0 +
+// Mc32 delta standing in for the gradient (h0 = g64 at the refresh).  Only
+// the BB dot products s.s, s.y, y.y and the residual are accumulated in
+// double precision (from single-precision differences), as is every
+// refresh.  Because delta and its product shrink as the solve converges,
+// single-precision rounding stays below the residual it has to resolve;
+// each inner round ends when its residual has dropped by 1e-4 (or to the
+// tolerance, or it stalls), and the solve ends only when an FP64 refresh
+// certifies residual <= tol.
+//
+// The kernels mirror the FP64 ones (rl_solver.hip) with single-precision
+// records: 16-byte (delta, h, b, h0) state and 16-byte (e, s) geometry per
+// incidence instead of 16 + 32 bytes, and 32-byte per-rod velocities.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "rl_device.hpp"
+
+namespace rl {
+
+static inline unsigned grid_of(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+static inline unsigned rod_grid32(int64_t n) { return (grid_of(n, kRodBlock / kRodLanes) + 7) / 8 * 8; }
+
+constexpr long long kInnerRoundCap = 4000;  // inner iterations before a forced refresh
+
+// single-precision geometry records from the FP64 ones
+__global__ void k_pack32(int64_t nc, const double *__restrict__ geo, const double *__restrict__ qgeo,
+                         float4 *__restrict__ geo32, float *__restrict__ sj32, float4 *__restrict__ qgeo32)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double *g = geo + 6 * c;
+    geo32[c] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
+    sj32[c] = (float)g[4];
+    const double *qg = qgeo + 4 * c;  // list order, same length
+    qgeo32[c] = make_float4((float)qg[0], (float)qg[1], (float)qg[2], (float)qg[3]);
+}
+
+__device__ __forceinline__ float delta_prime(float4 s, float alpha)
+{
+    const float v = fmaf(-alpha, s.y, s.x);
+    return v > s.z ? v : s.z;
+}
+
+template <bool UNI>
+__global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, int first, long long round_start)
+{
+    __shared__ double lds[kRodBlock / 64 + 1][4];
+    SolverState *st = a.state;
+    if (st->done || st->refresh) return;
+    const int sub = threadIdx.x & (kRodLanes - 1);
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const bool active = r < a.n;
+    int pb = 0, pe = 0, qb = 0, qe = 0;
+    if (active) {
+        pb = a.pptr[r] + sub;
+        pe = a.pptr[r + 1];
+        qb = a.qptr[r] + sub;
+        qe = a.qptr[r + 1];
+    }
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 ps = z, pg = z, qs = z, qg = z;
+    if (pb < pe) {
+        ps = a.st32[pb];
+        pg = a.geo32[pb];
+    }
+    if (qb < qe) {
+        qs = a.stq32[qb];
+        qg = a.qgeo32[qb];
+    }
+    double alpha;
+    if (first) {
+        alpha = st->alpha;
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[k & 1] = alpha;
+    } else {
+        double t[4];
+        sum_partials<kRodBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+        const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
+        int done = 0, refresh = 0, status = RL_OK;
+        if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
+            done = 1;
+            status = RL_ERR_NONFINITE;
+        } else if (k >= st->max_iter) {
+            done = 1;
+            status = RL_NOT_CONVERGED;
+        } else if (res <= st->inner_tol || ss == 0.0 || k - round_start >= kInnerRoundCap) {
+            refresh = 1;
+        }
+        double al = a.alpha_buf[(k - 1) & 1];
+        if (sy > 0.0) {
+            al = ((k - 1) % 2 == 0) ? ss / sy : sy / yy;
+            al = al < st->amin ? st->amin : (al > st->amax ? st->amax : al);
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (done || refresh) {
+                st->iter = k;
+                st->res = res;
+                st->alpha = al;
+                if (done) {
+                    st->status = status;
+                    st->done = 1;
+                } else {
+                    st->refresh = 1;
+                }
+            } else {
+                a.alpha_buf[k & 1] = al;
+            }
+        }
+        if (done || refresh) return;
+        alpha = al;
+    }
+    const float a32 = (float)alpha;
+    float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
+    if (pb < pe) {
+        const float dp = delta_prime(ps, a32), ds = dp * pg.w;
+        f[0] += dp * pg.x;
+        f[1] += dp * pg.y;
+        f[2] += dp * pg.z;
+        m[0] += ds * pg.x;
+        m[1] += ds * pg.y;
+        m[2] += ds * pg.z;
+        for (int c = pb + kRodLanes; c < pe; c += kRodLanes) {
+            const float4 s4 = a.st32[c], g4 = a.geo32[c];
+            const float d2 = delta_prime(s4, a32), e2 = d2 * g4.w;
+            f[0] += d2 * g4.x;
+            f[1] += d2 * g4.y;
+            f[2] += d2 * g4.z;
+            m[0] += e2 * g4.x;
+            m[1] += e2 * g4.y;
+            m[2] += e2 * g4.z;
+        }
+    }
+    if (qb < qe) {
+        const float dp = delta_prime(qs, a32), ds = dp * qg.w;
+        f[0] -= dp * qg.x;
+        f[1] -= dp * qg.y;
+        f[2] -= dp * qg.z;
+        m[0] -= ds * qg.x;
+        m[1] -= ds * qg.y;
+        m[2] -= ds * qg.z;
+        for (int c = qb + kRodLanes; c < qe; c += kRodLanes) {
+            const float4 s4 = a.stq32[c], g4 = a.qgeo32[c];
+            const float d2 = delta_prime(s4, a32), e2 = d2 * g4.w;
+            f[0] -= d2 * g4.x;
+            f[1] -= d2 * g4.y;
+            f[2] -= d2 * g4.z;
+            m[0] -= e2 * g4.x;
+            m[1] -= e2 * g4.y;
+            m[2] -= e2 * g4.z;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < kRodLanes; o <<= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[d] += __shfl_xor(f[d], o, 64);
+            m[d] += __shfl_xor(m[d], o, 64);
+        }
+    }
+    if (!active || sub >= 2) return;
+    const float dx = (float)a.dir[3 * r], dy = (float)a.dir[3 * r + 1], dz = (float)a.dir[3 * r + 2];
+    float apar, aperp, rperp;
+    if (UNI) {
+        apar = (float)a.mob.apar;
+        aperp = (float)a.mob.aperp;
+        rperp = (float)a.mob.rperp;
+    } else {
+        apar = (float)a.coef[3 * r];
+        aperp = (float)a.coef[3 * r + 1];
+        rperp = (float)a.coef[3 * r + 2];
+    }
+    const float fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
+    const float md = dx * m[0] + dy * m[1] + dz * m[2];
+    float *out = a.V32 + 8 * r;
+    if (sub == 0)
+        *reinterpret_cast<float4 *>(out) =
+            make_float4(aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz, rperp * (m[0] - md * dx));
+    else
+        *reinterpret_cast<float2 *>(out + 4) = make_float2(rperp * (m[1] - md * dy), rperp * (m[2] - md * dz));
+}
+
+struct Con32Loads {
+    float4 g, s;
+    float sj;
+    int qp;
+    float4 vi, vj;
+    float2 wi, wj;
+};
+
+__device__ __forceinline__ void con32_load(const SolveArgs &a, int64_t c, Con32Loads &L)
+{
+    const int2 ij = a.pp[c];
+    L.g = a.geo32[c];
+    L.sj = a.sj32[c];
+    L.s = a.st32[c];
+    L.qp = a.qpos[c];
+    const float *Vi = a.V32 + 8 * (int64_t)ij.x;
+    const float *Vj = a.V32 + 8 * (int64_t)ij.y;
+    L.vi = *reinterpret_cast<const float4 *>(Vi);
+    L.wi = *reinterpret_cast<const float2 *>(Vi + 4);
+    L.vj = *reinterpret_cast<const float4 *>(Vj);
+    L.wj = *reinterpret_cast<const float2 *>(Vj + 4);
+}
+
+__device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, const Con32Loads &L, float a32,
+                                             double p[4])
+{
+    const float si = L.g.w, sj = L.sj;
+    // V = (vx, vy, vz), W = (wx, wy, wz) packed as (vx, vy, vz, wx), (wy, wz)
+    const float ux = (L.vi.x + si * L.vi.w) - (L.vj.x + sj * L.vj.w);
+    const float uy = (L.vi.y + si * L.wi.x) - (L.vj.y + sj * L.wj.x);
+    const float uz = (L.vi.z + si * L.wi.y) - (L.vj.z + sj * L.wj.y);
+    const float h = L.s.w + (L.g.x * ux + L.g.y * uy + L.g.z * uz);
+    const float dp = delta_prime(L.s, a32);
+    a.st32[c] = make_float4(dp, h, L.s.z, L.s.w);
+    a.stq32[L.qp] = make_float4(dp, h, L.s.z, 0.f);
+    const double sc = (double)dp - (double)L.s.x, yc = (double)h - (double)L.s.y;
+    const double gam = (double)dp - (double)L.s.z;
+    p[0] += sc * sc;
+    p[1] += sc * yc;
+    p[2] += yc * yc;
+    p[3] = fmax(p[3], fabs(gam < (double)h ? gam : (double)h));
+}
+
+__global__ void __launch_bounds__(kConBlock) k_con32(SolveArgs a, long long k)
+{
+    __shared__ double lds[kConBlock / 64 + 1][4];
+    if (a.state->done || a.state->refresh) return;
+    const float a32 = (float)a.alpha_buf[k & 1];
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
+    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += 2 * kConBlock) {
+        const int64_t c1 = c0 + kConBlock;
+        Con32Loads A, B;
+        con32_load(a, c0, A);
+        if (c1 < hi) con32_load(a, c1, B);
+        con32_update(a, c0, A, a32, p);
+        if (c1 < hi) con32_update(a, c1, B, a32, p);
+    }
+    block_reduce4_all<kConBlock / 64>(p, lds);
+    if (threadIdx.x == 0) {
+        double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)(k & 1) * a.gcon * 4 + 4 * blockIdx.x);
+        dst[0] = make_double2(p[0], p[1]);
+        dst[1] = make_double2(p[2], p[3]);
+    }
+}
+
+int prepare_mixed(rl_ctx *h, SolveArgs &a)
+{
+    int werr = 0;
+    const int64_t nb = a.nc > 0 ? a.nc : 1, rb = a.n > 0 ? a.n : 1;
+    a.st32 = (float4 *)ws_get(h, kWsSt32, sizeof(float4) * nb, &werr);
+    a.stq32 = (float4 *)ws_get(h, kWsStq32, sizeof(float4) * nb, &werr);
+    float4 *geo32 = (float4 *)ws_get(h, kWsGeo32, sizeof(float4) * nb, &werr);
+    float *sj32 = (float *)ws_get(h, kWsSj32, sizeof(float) * nb, &werr);
+    float4 *qgeo32 = (float4 *)ws_get(h, kWsQgeo32, sizeof(float4) * nb, &werr);
+    a.V32 = (float *)ws_get(h, kWsV32, sizeof(float) * 8 * rb, &werr);
+    if (werr) return werr;
+    a.geo32 = geo32;
+    a.sj32 = sj32;
+    a.qgeo32 = qgeo32;
+    if (a.nc > 0) {
+        hipLaunchKernelGGL(k_pack32, dim3(grid_of(a.nc, kBlock)), dim3(kBlock), 0, h->stream, a.nc, a.geo, a.qgeo,
+                           geo32, sj32, qgeo32);
+        RL_HIP(hipGetLastError());
+    }
+    return RL_OK;
+}
+
+static int read_state(rl_ctx *h)
+{
+    RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, h->stream));
+    RL_HIP(hipStreamSynchronize(h->stream));
+    return RL_OK;
+}
+
+int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    const bool uni = a.coef == nullptr;
+    // start: FP64 g0 and residual (also fills the FP32 state), then alpha0
+    RL_HIP(launch_refresh64(h, a, false));
+    RL_HIP(launch_alpha0_64(h, a));
+    int rc = read_state(h);
+    if (rc) return rc;
+    const int every = p.check_every > 0 ? p.check_every : 32;
+    long long k = 0, round_start = 0, launched = 0;
+    bool first = true;
+    const dim3 rgrid(rod_grid32(a.n));
+    while (!h->state_host->done) {
+        if (launched > p.max_iter + 4 * every + 64) {
+            set_error("rl_solve_lcp: mixed-precision loop did not stop");
+            return RL_ERR_HIP;
+        }
+        for (int i = 0; i < every; ++i, ++k, ++launched) {
+            const int fl = first ? 1 : 0;
+            first = false;
+            if (uni)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
+                                   round_start);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
+                                   round_start);
+            hipLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
+            RL_HIP(hipGetLastError());
+        }
+        if ((rc = read_state(h))) return rc;
+        const SolverState &s = *h->state_host;
+        if (s.done && s.status == RL_ERR_NONFINITE) break;
+        if (s.refresh || s.done) {
+            // the stop iteration: continue from there after the FP64 refresh
+            k = s.iter;
+            const bool was_done = s.done;
+            const int status = s.status;
+            RL_HIP(launch_refresh64(h, a, true));
+            if ((rc = read_state(h))) return rc;
+            if (was_done && !h->state_host->done) {
+                // iteration cap: keep the refreshed FP64 iterate, report the cap
+                SolverState fix = *h->state_host;
+                fix.done = 1;
+                fix.status = status;
+                fix.iter = k;
+                *h->state_host = fix;
+                break;
+            }
+            round_start = k;
+            first = true;
+        }
+    }
+    h->state_host->iter = std::max<long long>(h->state_host->iter, 0);
+    *refreshes = h->state_host->refreshes;
+    return RL_OK;
+}
+
+}  // namespace rl

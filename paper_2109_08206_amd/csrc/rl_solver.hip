@@ -37,7 +37,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "rl_internal.hpp"
+#include "rl_device.hpp"
 
 namespace rl {
 
@@ -153,110 +153,6 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
 hipError_t launch_scan(hipStream_t st, const int *in, int64_t m, int *out, int64_t *total);
 
 // ---------------------------------------------------------------------------
-// reductions
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Sums p[0..2] and takes the max of p[3] over the workgroup (fixed tree);
-// every thread receives the result.  lds holds NW x 4 doubles plus 4.
-template <int NW>
-__device__ __forceinline__ void block_reduce4_all(double p[4], double (*lds)[4])
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    p[0] = wave_sum(p[0]);
-    p[1] = wave_sum(p[1]);
-    p[2] = wave_sum(p[2]);
-    p[3] = wave_max(p[3]);
-    if (lane == 0) {
-        lds[wid][0] = p[0];
-        lds[wid][1] = p[1];
-        lds[wid][2] = p[2];
-        lds[wid][3] = p[3];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < NW; ++w) {
-            p[0] += lds[w][0];
-            p[1] += lds[w][1];
-            p[2] += lds[w][2];
-            p[3] = fmax(p[3], lds[w][3]);
-        }
-        lds[NW][0] = p[0];
-        lds[NW][1] = p[1];
-        lds[NW][2] = p[2];
-        lds[NW][3] = p[3];
-    }
-    __syncthreads();
-    p[0] = lds[NW][0];
-    p[1] = lds[NW][1];
-    p[2] = lds[NW][2];
-    p[3] = lds[NW][3];
-    __syncthreads();
-}
-
-// Totals of the gcon workgroup partials at `P`, identical in every workgroup.
-template <int NW>
-__device__ __forceinline__ void sum_partials(const double *__restrict__ P, int gcon, double p[4], double (*lds)[4])
-{
-    p[0] = p[1] = p[2] = p[3] = 0.0;
-    for (int b = threadIdx.x; b < gcon; b += blockDim.x) {
-        const double2 *src = reinterpret_cast<const double2 *>(P + 4 * (int64_t)b);
-        const double2 u = src[0], v = src[1];
-        p[0] += u.x;
-        p[1] += u.y;
-        p[2] += v.x;
-        p[3] = fmax(p[3], v.y);
-    }
-    block_reduce4_all<NW>(p, lds);
-}
-
-// Stop test and step length for iteration k >= 1 from the totals of
-// iteration k-1 (s.s, s.y, y.y, residual); status RL_OK / NOT_CONVERGED /
-// STAGNATED / ERR_NONFINITE when stopping.
-struct Decision {
-    double alpha;
-    int stop, status;
-};
-
-__device__ __forceinline__ Decision decide(const SolveArgs &a, long long k, const double t[4])
-{
-    const SolverState *st = a.state;
-    Decision d{0.0, 0, RL_OK};
-    const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
-    if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
-        d.stop = 1;
-        d.status = RL_ERR_NONFINITE;
-    } else if (res <= st->tol) {
-        d.stop = 1;
-        d.status = RL_OK;
-    } else if (ss == 0.0) {
-        d.stop = 1;
-        d.status = RL_STAGNATED;
-    } else if (k >= st->max_iter) {
-        d.stop = 1;
-        d.status = RL_NOT_CONVERGED;
-    }
-    double al = a.alpha_buf[(k - 1) & 1];
-    if (sy > 0.0) {
-        al = ((k - 1) % 2 == 0) ? ss / sy : sy / yy;
-        al = al < st->amin ? st->amin : (al > st->amax ? st->amax : al);
-    }
-    d.alpha = al;
-    return d;
-}
-
-// ---------------------------------------------------------------------------
 // rod kernel
 // ---------------------------------------------------------------------------
 template <int MODE>
@@ -369,16 +265,6 @@ __device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoad
     }
 }
 
-// Workgroup -> work-tile map that gives each of the eight XCDs (which take
-// workgroups round-robin) a contiguous range of tiles, so that the rods and
-// constraints one XCD works on are neighbours in space and share its L2.
-__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks)
-{
-    constexpr unsigned kXcd = 8;
-    if (nblocks % kXcd != 0) return b;
-    return (b % kXcd) * (nblocks / kXcd) + b / kXcd;
-}
-
 __device__ __forceinline__ void rod_mob(const SolveArgs &a, int64_t r, bool uni, double &apar, double &aperp,
                                         double &rperp)
 {
@@ -468,7 +354,7 @@ __device__ __forceinline__ void con_load(const SolveArgs &a, int64_t c, ConLoads
     L.g1 = gd[1];
     L.g2 = gd[2];
     if (MODE != kModeApply) L.sg = a.st[c];
-    if (MODE == kModeInit || MODE == kModeLoop) L.qp = a.qpos[c];
+    if (MODE == kModeInit || MODE == kModeLoop || MODE == kModeRefresh) L.qp = a.qpos[c];
     const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);
     const double2 *Vj = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.y);
     L.i0 = Vi[0];
@@ -502,6 +388,17 @@ __device__ __forceinline__ void con_update(const SolveArgs &a, int64_t c, const 
         const double gh = gamma_prime<kModeAlpha0>(L.sg.x, L.sg.y, 0.0);
         p[0] += gh * gh;
         p[1] += gh * w;
+    } else if (MODE == kModeRefresh) {
+        // FP64 gradient of the accumulated iterate; the FP32 correction restarts at 0
+        w += L.g2.y;
+        const double gp = gamma_prime<kModeInit>(L.sg.x, 0.0, 0.0);
+        a.st[c] = make_double2(gp, w);
+        a.stq[L.qp] = make_double2(gp, w);
+        const float hw = (float)w, bg = -(float)gp;
+        a.st32[c] = make_float4(0.0f, hw, bg, hw);
+        a.stq32[L.qp] = make_float4(0.0f, hw, bg, 0.0f);
+        p[2] += w * w;
+        p[3] = fmax(p[3], fabs(gp < w ? gp : w));
     } else {
         w += L.g2.y;
         const double gp = gamma_prime<kModeLoop>(L.sg.x, L.sg.y, alpha);
@@ -549,10 +446,27 @@ __global__ void __launch_bounds__(kRodBlock) k_fin(SolveArgs a)
 {
     __shared__ double lds[kRodBlock / 64 + 1][4];
     SolverState *st = a.state;
-    if (st->done) return;
+    if (st->done && MODE != kModeRefresh) return;
     double t[4];
     sum_partials<kRodBlock / 64>(a.partial, a.gcon, t, lds);
     if (threadIdx.x != 0) return;
+    if (MODE == kModeRefresh) {
+        st->res = t[3];
+        st->rho64 = t[3];
+        st->refreshes += 1;
+        st->refresh = 0;
+        if (!isfinite(t[2]) || !isfinite(t[3])) {
+            st->status = RL_ERR_NONFINITE;
+            st->done = 1;
+        } else if (t[3] <= st->tol) {
+            st->status = RL_OK;
+            st->done = 1;
+        } else {
+            // next inner round: four orders of magnitude, or the tolerance
+            st->inner_tol = fmax(0.5 * st->tol, 1e-4 * t[3]);
+        }
+        return;
+    }
     if (MODE == kModeInit) {
         st->res = t[3];
         if (!isfinite(t[2]) || !isfinite(t[3])) {
@@ -635,7 +549,23 @@ __global__ void k_state_init(SolverState *st, double tol, long long max_iter)
         st->max_iter = max_iter;
         st->done = 0;
         st->status = RL_OK;
+        st->inner_tol = tol;
+        st->rho64 = 0.0;
+        st->refreshes = 0;
+        st->refresh = 0;
     }
+}
+
+// mixed precision: gamma64 <- max(0, gamma64 + delta) in both orders
+__global__ void k_mix_accum(int64_t nc, const float4 *__restrict__ st32, const int32_t *__restrict__ qpos,
+                            double2 *__restrict__ st, double2 *__restrict__ stq)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double v = st[c].x + (double)st32[c].x;
+    const double g = v > 0.0 ? v : 0.0;
+    st[c].x = g;
+    stq[qpos[c]].x = g;
 }
 
 // x += h U_t wrapped into [0, box); theta += h Psi(theta) Omega, renormalised.
@@ -817,8 +747,19 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
     const bool uni = a.coef == nullptr;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, st, h->state, p.tol, (long long)p.max_iter);
     RL_HIP(hipGetLastError());
-    long long iters = 0;
-    if (a.nc > 0) {
+    long long iters = 0, refreshes = 0;
+    if (a.nc > 0 && p.precision == RL_FP32_MIXED) {
+        int rc = prepare_mixed(h, a);
+        if (rc) return rc;
+        rc = solve_mixed_impl(h, a, &refreshes);
+        if (rc) return rc;
+        iters = h->state_host->iter;
+        if (gamma_out) {
+            hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
+                               (const double2 *)a.st, gamma_out);
+            RL_HIP(hipGetLastError());
+        }
+    } else if (a.nc > 0) {
         RL_HIP(launch_rod<kModeInit>(st, a, uni, 0));
         RL_HIP(launch_con<kModeInit>(st, a, 0));
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeInit>), dim3(1), dim3(kRodBlock), 0, st, a);
@@ -887,10 +828,48 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         info->residual = a.nc > 0 ? s.res : 0.0;
         info->alpha0 = s.alpha0;
         info->status = status;
-        info->reserved = 0;
+        info->fp64_refreshes = (int32_t)refreshes;
     }
     if (status == RL_ERR_NONFINITE) set_error("rl_solve_lcp: non-finite value in q or an iterate");
     return status;
+}
+
+hipError_t launch_refresh64(rl_ctx *h, const SolveArgs &a, bool accum)
+{
+    hipStream_t st = h->stream;
+    const bool uni = a.coef == nullptr;
+    if (accum) {
+        hipLaunchKernelGGL(k_mix_accum, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc, (const float4 *)a.st32,
+                           a.qpos, a.st, a.stq);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_rod<kModeApply>(st, a, uni, 0);
+    if (e != hipSuccess) return e;
+    if ((e = launch_con<kModeRefresh>(st, a, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeRefresh>), dim3(1), dim3(kRodBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a)
+{
+    hipStream_t st = h->stream;
+    hipError_t e = launch_rod<kModeAlpha0>(st, a, a.coef == nullptr, 0);
+    if (e != hipSuccess) return e;
+    if ((e = launch_con<kModeAlpha0>(st, a, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
+    if (a.coef == nullptr)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<true>), grid, dim3(kRodBlock), 0, h->stream, a, F, perm, U);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<false>), grid, dim3(kRodBlock), 0, h->stream, a, F, perm, U);
+    return hipGetLastError();
 }
 
 int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat)
