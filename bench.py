@@ -85,6 +85,88 @@ def cpu_baseline(sysm, iters: int) -> dict:
             "pairs_assembly_s": round(t1 - t0, 3), "solve_s": round(t2 - t1, 3)}
 
 
+def _kernel_summary(prof, kb, names):
+    avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
+           "con": prof["con_ms"] / max(1, prof["con_launches"])}
+    return avg, {names[k]: {"avg_us": 1e3 * avg[k], "alg_bytes": kb[k],
+                            "alg_gbps": kb[k] / (avg[k] * 1e-3) / 1e9 if avg[k] > 0 else 0.0,
+                            "samples": prof[f"{k}_launches"]} for k in ("rod", "con")}
+
+
+def kernel_bytes32(n: int, nc: int) -> dict:
+    """Algorithmic bytes per launch of the single-precision loop kernels.
+    rod kernel:        per rod pptr+qptr 8, dir 24, V write 24        -> 56 n
+                       per constraint, P and Q side: state 16 + (e, s) 16 -> 64 nc
+    constraint kernel: per constraint (pi, pj) 8, (e, s_i) 16, s_j 4,
+                       state read 16 + write 16, qpos 4, Q-side state
+                       write 16                                       -> 80 nc
+                       per rod V read 24                              -> 24 n"""
+    return {"rod": 56 * n + 64 * nc, "con": 80 * nc + 24 * n}
+
+
+def form_precision(args, torch, rl, rodsynth) -> dict:
+    """FP64 against FP32-mixed whole steps on the precision workload."""
+    dev = torch.device("cuda:0")
+    n = args.rods if args.rods != 100_000 else 400_000
+    s = rodsynth.cfg_precision(args.seed, n=n, phi=args.phi if args.phi else 0.03)
+    x0, q0 = torch.as_tensor(s.x, device=dev), torch.as_tensor(s.quat, device=dev)
+    F, L = torch.as_tensor(s.force, device=dev), torch.as_tensor(s.length, device=dev)
+    x, q = torch.empty_like(x0), torch.empty_like(q0)
+    res = {}
+    Us = {}
+    for name, prec in (("fp64", rl.FP64), ("fp32_mixed", rl.FP32_MIXED)):
+        slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8,
+                        max_iter=200_000, precision=prec)
+        U = torch.empty((s.n, 6), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            x.copy_(x0); q.copy_(q0)
+            slv.step(x, q, L, F=F, U=U)
+        slv.profile_enable(args.profile_every)
+        slv.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, worst, status, npairs, refr = 0, 0.0, 0, 0, 0
+        for _ in range(args.steps):
+            x.copy_(x0); q.copy_(q0)
+            _, info, npairs = slv.step(x, q, L, F=F, U=U)
+            iters += info.iterations
+            worst = max(worst, info.residual)
+            status = max(status, info.status)
+            refr += info.fp64_refreshes
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = slv.profile_read()
+        slv.close()
+        kb = (kernel_bytes if prec == rl.FP64 else kernel_bytes32)(s.n, npairs)
+        names = {"rod": "k_rod<2,false>", "con": "k_con<2>"} if prec == rl.FP64 else \
+            {"rod": "k_rod32<false>", "con": "k_con32"}
+        avg, kern = _kernel_summary(prof, kb, names)
+        dom = max(avg, key=avg.get)
+        ach = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
+        res[name] = {"iters_per_s": iters / el, "ms_per_step": 1e3 * el / args.steps,
+                     "iters_per_solve": iters / args.steps, "fp64_refreshes_per_solve": refr / args.steps,
+                     "max_residual_fp64": worst, "status": status, "constraints": npairs,
+                     "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": ach, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None},
+                     "kernels": kern, "us_per_iteration": 1e3 * (avg["rod"] + avg["con"])}
+        Us[name] = U.cpu()
+    du = float(torch.linalg.norm(Us["fp32_mixed"] - Us["fp64"]) / torch.linalg.norm(Us["fp64"]))
+    return {
+        "metric": "precision form: FP32-mixed vs FP64 BBPGD, whole steps to residual 1e-8",
+        "value": res["fp32_mixed"]["iters_per_s"], "unit": "BBPGD iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["fp32_mixed"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{s.n} rods L~U[0.5,1.5] d=0.025 isotropic phi={args.phi or 0.03} (0.08 is "
+                               f"jammed for unrelaxed rods), one whole step to residual 1e-8",
+                   "rods": s.n, "box": round(s.box, 4), "seed": args.seed},
+        "fp64": res["fp64"], "fp32_mixed": res["fp32_mixed"],
+        "speedup_per_iteration": res["fp64"]["us_per_iteration"] / max(1e-9, res["fp32_mixed"]["us_per_iteration"]),
+        "speedup_per_step": res["fp64"]["ms_per_step"] / res["fp32_mixed"]["ms_per_step"],
+        "U_rel_diff_fp32_mixed_vs_fp64": du,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +177,9 @@ def main() -> int:
     ap.add_argument("--profile-every", type=int, default=8, help="sample kernel events every k-th iteration")
     ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", choices=["step", "precision"], default="step",
+                    help="step: the FP64 whole-step benchmark (default); precision: FP32-mixed vs FP64")
+    ap.add_argument("--phi", type=float, default=None, help="volume fraction override (precision form)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 1 GiB device buffer once (reference for HBM counters)")
     args = ap.parse_args()
@@ -111,6 +196,9 @@ def main() -> int:
     import rodsynth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.form == "precision":
+        print(json.dumps(form_precision(args, torch, rl, rodsynth)), flush=True)
+        return 0
     dev = torch.device("cuda:0")
     s = rodsynth.cfg_paper_scale(args.seed, n=args.rods)
     x0 = torch.as_tensor(s.x, device=dev)

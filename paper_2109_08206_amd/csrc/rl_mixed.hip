@@ -16,6 +16,7 @@
 // The kernels mirror the FP64 ones (rl_solver.hip) with single-precision
 // records: 16-byte (delta, h, b, h0) state and 16-byte (e, s) geometry per
 // incidence instead of 16 + 32 bytes, and 32-byte per-rod velocities.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -303,20 +304,53 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
             set_error("rl_solve_lcp: mixed-precision loop did not stop");
             return RL_ERR_HIP;
         }
+        int nev = 0;
+        const long long k_block = k;
         for (int i = 0; i < every; ++i, ++k, ++launched) {
             const int fl = first ? 1 : 0;
             first = false;
-            if (uni)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
-                                   round_start);
-            else
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
-                                   round_start);
-            hipLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
+            const bool samp = h->prof_every > 0 && k % h->prof_every == 0 && nev < rl_ctx::kMaxEv;
+            if (samp) {
+                // dispatch-stamped events around both kernels of this iteration
+                for (int e = 0; e < 4; ++e)
+                    if (!h->ev[nev][e]) RL_HIP(hipEventCreate(&h->ev[nev][e]));
+                h->ev_iter[nev] = k;
+                if (uni)
+                    hipExtLaunchKernelGGL(k_rod32<true>, rgrid, dim3(kRodBlock), 0, st, h->ev[nev][0],
+                                          h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
+                else
+                    hipExtLaunchKernelGGL(k_rod32<false>, rgrid, dim3(kRodBlock), 0, st, h->ev[nev][0],
+                                          h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
+                hipExtLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, h->ev[nev][2], h->ev[nev][3],
+                                      0, a, (long long)k);
+                ++nev;
+            } else {
+                if (uni)
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
+                                       round_start);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
+                                       round_start);
+                hipLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
+            }
             RL_HIP(hipGetLastError());
         }
         if ((rc = read_state(h))) return rc;
         const SolverState &s = *h->state_host;
+        {
+            // samples at or after a stop/refresh decision ran kernels that exited at once
+            const long long valid = (s.refresh || s.done) ? s.iter : k;
+            for (int v = 0; v < nev; ++v) {
+                if (h->ev_iter[v] >= valid || h->ev_iter[v] < k_block) continue;
+                float t0 = 0.f, t1 = 0.f;
+                RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
+                RL_HIP(hipEventElapsedTime(&t1, h->ev[v][2], h->ev[v][3]));
+                h->prof_ms[0] += t0;
+                h->prof_ms[1] += t1;
+                h->prof_cnt[0] += 1.0;
+                h->prof_cnt[1] += 1.0;
+            }
+        }
         if (s.done && s.status == RL_ERR_NONFINITE) break;
         if (s.refresh || s.done) {
             // the stop iteration: continue from there after the FP64 refresh
