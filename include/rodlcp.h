@@ -176,6 +176,30 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
             double *U, rl_solve_info *info, int64_t *n_pairs);
 
+/* Batching form: S independent periodic systems solved together (one set
+ * of launches per BBPGD phase for all of them, iterations replayed from a
+ * captured HIP graph, workgroup sizes picked by timing; the problem of each
+ * system is that of rl_solve_lcp).  The systems are concatenated: system s
+ * owns rods [rod_off[s], rod_off[s+1]) and constraints
+ * [pair_off[s], pair_off[s+1]) of the device arrays, which have the layouts
+ * above; pi and pj are indices into the concatenated rods and each
+ * constraint must join two rods of its own system.  rod_off and pair_off are
+ * HOST arrays of S + 1 entries starting at 0.  Each system has its own step
+ * length, stop test and iteration count; infos (host, S entries) receives
+ * them.  Returns the most severe status over the systems.  RL_FP64 only.
+ * Synchronises; work runs on a stream the handle owns, after the handle's
+ * stream has drained. */
+int rl_solve_lcp_batched(rl_handle h, int32_t S, const int64_t *rod_off, const int64_t *pair_off, const double *dir,
+                         const double *len, double len0, const int32_t *pi, const int32_t *pj, const double *e,
+                         const double *arm, const double *q, const double *F, double *gamma, double *U,
+                         rl_solve_info *infos);
+/* Workgroup sizes of the batched kernels: rod_block in {256, 1024} and
+ * con_block in {256, 512}, or both 0 to time the candidates on the first
+ * solve of each problem size (the default; cached in the handle and appended
+ * to the file named by the environment variable RODLCP_TUNE_CACHE if set).
+ * chosen (host, may be NULL) receives the sizes the last solve used. */
+int rl_batch_tuning(rl_handle h, int rod_block, int con_block, int *chosen);
+
 /* Kernel timing with HIP events on the handle's stream, for measurement.
  * With every > 0, every every-th BBPGD iteration of later solves records
  * events around its rod kernel and its constraint kernel (iterations after

@@ -46,7 +46,8 @@ class SolveInfo(C.Structure):
 
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
-           "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read")
+           "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
+           "rl_batch_tuning")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -77,6 +78,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_solve_lcp": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)], C.c_int),
             "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64)], C.c_int),
             "rl_profile_enable": ([H, C.c_int], C.c_int),
+            "rl_solve_lcp_batched": ([H, I32, P, P, P, P, D, P, P, P, P, P, P, P, P, P], C.c_int),
+            "rl_batch_tuning": ([H, C.c_int, C.c_int, P], C.c_int),
             "rl_profile_read": ([H, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -275,6 +278,38 @@ class Solver:
             _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
         self._check(rc, "rl_solve_lcp")
         return gamma, U, _result(info)
+
+    def solve_lcp_batched(self, rod_off, pair_off, dir_, length, pi, pj, e, arm, q, F=None, gamma=None, U=None):
+        """S systems concatenated (rod_off, pair_off: S+1 host offsets; pi, pj
+        index the concatenated rods).  Returns (gamma, U, [SolveResult] * S)."""
+        import numpy as np
+        torch = _torch()
+        ro = np.ascontiguousarray(rod_off, dtype=np.int64)
+        po = np.ascontiguousarray(pair_off, dtype=np.int64)
+        S = ro.shape[0] - 1
+        n, nc = int(ro[-1]), int(po[-1])
+        la, l0 = _len_args(length, n)
+        dev = dir_.device
+        gamma = torch.zeros(nc, dtype=torch.float64, device=dev) if gamma is None else gamma
+        U = torch.empty((n, 6), dtype=torch.float64, device=dev) if U is None else U
+        infos = (SolveInfo * S)()
+        self._stream()
+        rc = self.lib.rl_solve_lcp_batched(
+            self._h, S, ro.ctypes.data_as(C.c_void_p), po.ctypes.data_as(C.c_void_p),
+            _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, _ptr(pi, torch.int32, (nc,), "pi"),
+            _ptr(pj, torch.int32, (nc,), "pj"), _ptr(e, torch.float64, (nc, 3), "e"),
+            _ptr(arm, torch.float64, (nc, 2), "arm"), _ptr(q, torch.float64, (nc,), "q"),
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
+            _ptr(U, torch.float64, (n, 6), "U"), infos)
+        self._check(rc, "rl_solve_lcp_batched")
+        return gamma, U, [_result(i) for i in infos]
+
+    def batch_tuning(self, rod_block: int = 0, con_block: int = 0):
+        """Fix the batched workgroup sizes (0, 0 = time them); returns the
+        sizes the last batched solve used."""
+        out = (C.c_int * 2)()
+        self._check(self.lib.rl_batch_tuning(self._h, int(rod_block), int(con_block), out), "rl_batch_tuning")
+        return int(out[0]), int(out[1])
 
     def step(self, x, quat, length, F=None, U=None):
         """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs)."""

@@ -48,6 +48,29 @@ void *ws_get(rl_ctx *h, int s, size_t bytes, int *err)
     return p;
 }
 
+void *ws_get_host(rl_ctx *h, size_t bytes, int *err)
+{
+    if (bytes == 0) bytes = 8;
+    if (h->host_cap >= bytes) return h->host_buf;
+    if (h->host_buf) {
+        (void)hipStreamSynchronize(h->stream);
+        if (h->own_stream) (void)hipStreamSynchronize(h->own_stream);
+        (void)hipHostFree(h->host_buf);
+        h->host_buf = nullptr;
+        h->host_cap = 0;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("pinned host allocation of %zu bytes failed", bytes);
+        *err = RL_ERR_NOMEM;
+        return nullptr;
+    }
+    h->host_buf = p;
+    h->host_cap = bytes;
+    return p;
+}
+
 static int check_params(const rl_params *p)
 {
     if (!p) {
@@ -160,6 +183,11 @@ int rl_destroy(rl_handle h)
     if (h->flag_dev) (void)hipFree(h->flag_dev);
     if (h->state_host) (void)hipHostFree(h->state_host);
     if (h->host_scratch) (void)hipHostFree(h->host_scratch);
+    if (h->host_buf) (void)hipHostFree(h->host_buf);
+    if (h->own_stream) {
+        (void)hipStreamSynchronize(h->own_stream);
+        (void)hipStreamDestroy(h->own_stream);
+    }
     delete h;
     return RL_OK;
 }
@@ -327,6 +355,44 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     if (rc2) return rc2;
     RL_HIP(hipStreamSynchronize(h->stream));
     return rc;
+}
+
+int rl_solve_lcp_batched(rl_handle h, int32_t S, const int64_t *rod_off, const int64_t *pair_off, const double *dir,
+                         const double *len, double len0, const int32_t *pi, const int32_t *pj, const double *e,
+                         const double *arm, const double *q, const double *F, double *gamma, double *U,
+                         rl_solve_info *infos)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(S >= 1 && rod_off && pair_off, "rl_solve_lcp_batched: need S >= 1 and host offsets");
+    RL_REQUIRE(rod_off[0] == 0 && pair_off[0] == 0, "rl_solve_lcp_batched: offsets must start at 0");
+    for (int s = 0; s < S; ++s)
+        RL_REQUIRE(rod_off[s + 1] >= rod_off[s] && pair_off[s + 1] >= pair_off[s],
+                   "rl_solve_lcp_batched: offsets must be non-decreasing");
+    const int64_t n = rod_off[S], nc = pair_off[S];
+    RL_REQUIRE(n < 0x7fffffff && nc < 0x7fffffff, "rl_solve_lcp_batched: sizes overflow int32");
+    RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && q && gamma), "rl_solve_lcp_batched: NULL array");
+    RL_REQUIRE(n == 0 || dir || !U, "rl_solve_lcp_batched: NULL dir");
+    RL_REQUIRE(len || len0 > 0.0, "rl_solve_lcp_batched: len0 must be > 0 when len is NULL");
+    RL_REQUIRE(h->prm.precision == RL_FP64, "rl_solve_lcp_batched: the batched solve runs in RL_FP64");
+    SolveArgs a;
+    int rc = prepare_solve(h, n, dir, len, len0, nc, pi, pj, e, arm, q, gamma, &a);
+    if (rc) return rc;
+    return solve_batched_impl(h, S, rod_off, pair_off, a, pi, pj, e, arm, q, gamma, F, gamma, U, infos);
+}
+
+int rl_batch_tuning(rl_handle h, int rod_block, int con_block, int *chosen)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE((rod_block == 0 && con_block == 0) ||
+                   ((rod_block == 256 || rod_block == 1024) && (con_block == 256 || con_block == 512)),
+               "rl_batch_tuning: rod_block in {256, 1024} and con_block in {256, 512}, or both 0");
+    h->batch_rb = rod_block;
+    h->batch_cb = con_block;
+    if (chosen) {
+        chosen[0] = h->batch_rb_used;
+        chosen[1] = h->batch_cb_used;
+    }
+    return RL_OK;
 }
 
 int rl_profile_enable(rl_handle h, int every)

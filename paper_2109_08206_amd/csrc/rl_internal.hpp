@@ -127,6 +127,14 @@ struct rl_ctx {
     long long ev_iter[kMaxEv] = {};
     double prof_ms[2] = {0.0, 0.0};
     double prof_cnt[2] = {0.0, 0.0};
+    // batched solves: a stream of our own (graph capture), workgroup sizes
+    hipStream_t own_stream = nullptr;
+    int batch_rb = 0, batch_cb = 0;            // fixed by the caller; 0 = tune
+    int batch_rb_used = 0, batch_cb_used = 0;  // the last solve's choice
+    int tune_loaded = 0;
+    int tune_rb[64] = {}, tune_cb[64] = {};    // per log2(constraints) bucket
+    void *host_buf = nullptr;                  // pinned staging for tables
+    size_t host_cap = 0;
 };
 
 namespace rl {
@@ -137,12 +145,16 @@ enum Slot : int {
     kWsStepPi, kWsStepPj, kWsStepImg, kWsStepFlags, kWsStepPhi, kWsStepE, kWsStepArm, kWsStepQ, kWsStepGamma,
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
     kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
+    kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
+    kWsBatchPartial2, kWsBatchDone, kWsBatchMap,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
 
 // Returns a device buffer of at least `bytes` in slot `s` (grow-only).
 void *ws_get(rl_ctx *h, int s, size_t bytes, int *err);
+// Pinned host staging buffer of at least `bytes` (grow-only).
+void *ws_get_host(rl_ctx *h, size_t bytes, int *err);
 
 void set_error(const char *fmt, ...);
 
@@ -174,6 +186,13 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes);
 hipError_t launch_refresh64(rl_ctx *h, const SolveArgs &a, bool accum);
 hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a);
 hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U);
+hipError_t launch_velocity_on(hipStream_t st, const SolveArgs &a, const double *F, const int *perm, double *U);
+hipError_t launch_unpack_gamma(hipStream_t st, const SolveArgs &a, double *gamma);
+__global__ void k_restore_start(int64_t nc, const double *gamma_in, const int32_t *qpos, double2 *st,
+                                double2 *stq);
+int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *pair_off, SolveArgs &a,
+                       const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                       const double *gamma_in, const double *F, double *gamma_out, double *U, rl_solve_info *infos);
 
 }  // namespace rl
 

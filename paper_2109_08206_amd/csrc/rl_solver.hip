@@ -152,133 +152,6 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
 
 hipError_t launch_scan(hipStream_t st, const int *in, int64_t m, int *out, int64_t *total);
 
-// ---------------------------------------------------------------------------
-// rod kernel
-// ---------------------------------------------------------------------------
-template <int MODE>
-__device__ __forceinline__ double gamma_prime(double gam, double g, double alpha)
-{
-    if (MODE == kModeInit) return gam > 0.0 ? gam : 0.0;
-    if (MODE == kModeAlpha0) return (gam <= 0.0 && g > 0.0) ? 0.0 : g;
-    if (MODE == kModeLoop) {
-        const double v = fma(-alpha, g, gam);
-        return v > 0.0 ? v : 0.0;
-    }
-    return gam;
-}
-
-// Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
-// rod r, split over the four lanes of the rod and combined by a fixed tree.
-// The torque on the rod is dir x m.  The first P-side and the first Q-side
-// record of each lane are loaded together (one memory round for almost every
-// rod: a lane holds up to four incidences per side in its first round);
-// longer lists continue in a loop.
-struct RodLoads {
-    int pb, pe, qb, qe;
-    double2 ps, pg0, pg1;  // first P record: (gamma, g), (ex, ey), (ez, s_i)
-    double2 qs, qg0, qg1;  // first Q record: (gamma, g), (ex, ey), (ez, s_j)
-};
-
-__device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
-{
-    L.pb = L.pe = L.qb = L.qe = 0;
-    if (active) {
-        L.pb = a.pptr[r] + sub;
-        L.pe = a.pptr[r + 1];
-        L.qb = a.qptr[r] + sub;
-        L.qe = a.qptr[r + 1];
-    }
-    const double2 z = make_double2(0.0, 0.0);
-    L.ps = L.pg0 = L.pg1 = L.qs = L.qg0 = L.qg1 = z;
-    if (L.pb < L.pe) {
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)L.pb);
-        L.ps = a.st[L.pb];
-        L.pg0 = gd[0];
-        L.pg1 = gd[1];
-    }
-    if (L.qb < L.qe) {
-        const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)L.qb);
-        L.qs = a.stq[L.qb];
-        L.qg0 = gd[0];
-        L.qg1 = gd[1];
-    }
-}
-
-template <int MODE>
-__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads &L, double alpha, double f[3],
-                                               double m[3])
-{
-    f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    if (L.pb < L.pe) {
-        const double gm = gamma_prime<MODE>(L.ps.x, L.ps.y, alpha);
-        const double gs = gm * L.pg1.y;
-        f[0] += gm * L.pg0.x;
-        f[1] += gm * L.pg0.y;
-        f[2] += gm * L.pg1.x;
-        m[0] += gs * L.pg0.x;
-        m[1] += gs * L.pg0.y;
-        m[2] += gs * L.pg1.x;
-        for (int c = L.pb + kRodLanes; c < L.pe; c += kRodLanes) {
-            const double2 sg = a.st[c];
-            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)c);
-            const double2 g0 = gd[0], g1 = gd[1];
-            const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
-            const double gsc = gmc * g1.y;
-            f[0] += gmc * g0.x;
-            f[1] += gmc * g0.y;
-            f[2] += gmc * g1.x;
-            m[0] += gsc * g0.x;
-            m[1] += gsc * g0.y;
-            m[2] += gsc * g1.x;
-        }
-    }
-    if (L.qb < L.qe) {
-        const double gm = gamma_prime<MODE>(L.qs.x, L.qs.y, alpha);
-        const double gs = gm * L.qg1.y;
-        f[0] -= gm * L.qg0.x;
-        f[1] -= gm * L.qg0.y;
-        f[2] -= gm * L.qg1.x;
-        m[0] -= gs * L.qg0.x;
-        m[1] -= gs * L.qg0.y;
-        m[2] -= gs * L.qg1.x;
-        for (int k = L.qb + kRodLanes; k < L.qe; k += kRodLanes) {
-            const double2 sg = a.stq[k];
-            const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)k);
-            const double2 g0 = gd[0], g1 = gd[1];
-            const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
-            const double gsc = gmc * g1.y;
-            f[0] -= gmc * g0.x;
-            f[1] -= gmc * g0.y;
-            f[2] -= gmc * g1.x;
-            m[0] -= gsc * g0.x;
-            m[1] -= gsc * g0.y;
-            m[2] -= gsc * g1.x;
-        }
-    }
-#pragma unroll
-    for (int o = 1; o < kRodLanes; o <<= 1) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            f[d] += __shfl_xor(f[d], o, 64);
-            m[d] += __shfl_xor(m[d], o, 64);
-        }
-    }
-}
-
-__device__ __forceinline__ void rod_mob(const SolveArgs &a, int64_t r, bool uni, double &apar, double &aperp,
-                                        double &rperp)
-{
-    if (uni) {
-        apar = a.mob.apar;
-        aperp = a.mob.aperp;
-        rperp = a.mob.rperp;
-    } else {
-        apar = a.coef[3 * r];
-        aperp = a.coef[3 * r + 1];
-        rperp = a.coef[3 * r + 2];
-    }
-}
-
 template <int MODE, bool UNI>
 __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
 {
@@ -299,7 +172,7 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
         } else {
             double t[4];
             sum_partials<kRodBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
-            const Decision d = decide(a, k, t);
+            const Decision d = decide(a.state, a.alpha_buf, k, t);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 if (d.stop) {
                     SolverState *st = a.state;
@@ -337,81 +210,9 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
 // ---------------------------------------------------------------------------
 // constraint kernel
 // ---------------------------------------------------------------------------
-// One constraint: w = e.(V_i + s_i W_i - V_j - s_j W_j) (+ q), from records
-// loaded beforehand so that two constraints' gathers are in flight at once.
-struct ConLoads {
-    double2 g0, g1, g2, sg;
-    int qp;
-    double2 i0, i1, i2, j0, j1, j2;
-};
-
-template <int MODE>
-__device__ __forceinline__ void con_load(const SolveArgs &a, int64_t c, ConLoads &L)
-{
-    const int2 ij = a.pp[c];
-    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
-    L.g0 = gd[0];
-    L.g1 = gd[1];
-    L.g2 = gd[2];
-    if (MODE != kModeApply) L.sg = a.st[c];
-    if (MODE == kModeInit || MODE == kModeLoop || MODE == kModeRefresh) L.qp = a.qpos[c];
-    const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);
-    const double2 *Vj = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.y);
-    L.i0 = Vi[0];
-    L.i1 = Vi[1];
-    L.i2 = Vi[2];
-    L.j0 = Vj[0];
-    L.j1 = Vj[1];
-    L.j2 = Vj[2];
-}
-
-template <int MODE>
-__device__ __forceinline__ void con_update(const SolveArgs &a, int64_t c, const ConLoads &L, double alpha,
-                                           double p[4])
-{
-    const double si = L.g1.y, sj = L.g2.x;
-    // velocity of the contact point on i minus that on j, along e
-    const double ux = (L.i0.x + si * L.i1.y) - (L.j0.x + sj * L.j1.y);
-    const double uy = (L.i0.y + si * L.i2.x) - (L.j0.y + sj * L.j2.x);
-    const double uz = (L.i1.x + si * L.i2.y) - (L.j1.x + sj * L.j2.y);
-    double w = L.g0.x * ux + L.g0.y * uy + L.g1.x * uz;
-    if (MODE == kModeApply) {
-        a.out[c] = w + L.g2.y;
-    } else if (MODE == kModeInit) {
-        w += L.g2.y;
-        const double gp = gamma_prime<kModeInit>(L.sg.x, 0.0, 0.0);
-        a.st[c] = make_double2(gp, w);
-        a.stq[L.qp] = make_double2(gp, w);
-        p[2] += w * w;
-        p[3] = fmax(p[3], fabs(gp < w ? gp : w));
-    } else if (MODE == kModeAlpha0) {
-        const double gh = gamma_prime<kModeAlpha0>(L.sg.x, L.sg.y, 0.0);
-        p[0] += gh * gh;
-        p[1] += gh * w;
-    } else if (MODE == kModeRefresh) {
-        // FP64 gradient of the accumulated iterate; the FP32 correction restarts at 0
-        w += L.g2.y;
-        const double gp = gamma_prime<kModeInit>(L.sg.x, 0.0, 0.0);
-        a.st[c] = make_double2(gp, w);
-        a.stq[L.qp] = make_double2(gp, w);
-        const float hw = (float)w, bg = -(float)gp;
-        a.st32[c] = make_float4(0.0f, hw, bg, hw);
-        a.stq32[L.qp] = make_float4(0.0f, hw, bg, 0.0f);
-        p[2] += w * w;
-        p[3] = fmax(p[3], fabs(gp < w ? gp : w));
-    } else {
-        w += L.g2.y;
-        const double gp = gamma_prime<kModeLoop>(L.sg.x, L.sg.y, alpha);
-        const double sc = gp - L.sg.x, yc = w - L.sg.y;
-        a.st[c] = make_double2(gp, w);
-        a.stq[L.qp] = make_double2(gp, w);
-        p[0] += sc * sc;
-        p[1] += sc * yc;
-        p[2] += yc * yc;
-        p[3] = fmax(p[3], fabs(gp < w ? gp : w));
-    }
-}
-
+// ---------------------------------------------------------------------------
+// constraint kernel
+// ---------------------------------------------------------------------------
 template <int MODE>
 __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
 {
@@ -861,15 +662,38 @@ hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a)
     return hipGetLastError();
 }
 
-hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U)
+hipError_t launch_velocity_on(hipStream_t st, const SolveArgs &a, const double *F, const int *perm, double *U)
 {
     if (a.n <= 0) return hipSuccess;
     const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
     if (a.coef == nullptr)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<true>), grid, dim3(kRodBlock), 0, h->stream, a, F, perm, U);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<true>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<false>), grid, dim3(kRodBlock), 0, h->stream, a, F, perm, U);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<false>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
     return hipGetLastError();
+}
+
+hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U)
+{
+    return launch_velocity_on(h->stream, a, F, perm, U);
+}
+
+hipError_t launch_unpack_gamma(hipStream_t st, const SolveArgs &a, double *gamma)
+{
+    if (a.nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc, (const double2 *)a.st, gamma);
+    return hipGetLastError();
+}
+
+// the iterate back to the caller's start (after trial iterations)
+__global__ void k_restore_start(int64_t nc, const double *__restrict__ gamma_in, const int32_t *__restrict__ qpos,
+                                double2 *__restrict__ st, double2 *__restrict__ stq)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double2 v = make_double2(gamma_in[c], 0.0);
+    st[c] = v;
+    stq[qpos[c]] = v;
 }
 
 int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat)
