@@ -200,6 +200,67 @@ int rl_solve_lcp_batched(rl_handle h, int32_t S, const int64_t *rod_off, const i
  * chosen (host, may be NULL) receives the sizes the last solve used. */
 int rl_batch_tuning(rl_handle h, int rod_block, int con_block, int *chosen);
 
+/* Differentiation form.  Where the step is differentiable, the constraint
+ * rows of the active set A hold as equalities (eq. linearconstraints): on A,
+ * Mc_AA gamma_A + q_A = 0, and gamma = 0 off A.  Here c is in A when
+ * gamma_c > w_c for the solution gamma and w = Mc gamma + q.  The adjoint
+ * then solves Mc_AA lambda = D_A^T M U_bar by conjugate gradients (the
+ * Chronopoulos-Gear form, one fused reduction per iteration).  It starts
+ * from 0, which gives the minimum-norm lambda when Mc_AA is singular, and
+ * stops when ||r||_2 <= cg_tol * ||D_A^T M U_bar||_2 (cg_tol <= 0: 1e-10)
+ * or after prm.max_iter iterations.  All arithmetic is FP64 and every sum
+ * runs in a fixed order, so results are bitwise repeatable. */
+typedef struct {
+    int64_t cg_iterations;   /* CG iterations (products Mc_AA p) */
+    double cg_residual;      /* ||r||_2 / ||b||_2 at exit (0 when b = 0) */
+    int64_t n_active;        /* |A| */
+    int32_t status;          /* RL_OK, RL_NOT_CONVERGED (iteration cap) or
+                                RL_STAGNATED (CG breakdown, curvature <= 0) */
+    int32_t solve_status;    /* rl_step_adjoint: status of its forward solve */
+    int64_t solve_iterations;/* rl_step_adjoint: BBPGD iterations of it */
+    double solve_residual;   /* rl_step_adjoint: its residual */
+} rl_adjoint_info;
+
+/* Adjoint of rl_solve_lcp taken as the map (dir, e, arm, q, F) -> U, with
+ * gamma its solution.  q is an input in its own right here (its own
+ * dependence on D and F belongs to rl_step_adjoint).  Given U_bar[n][6],
+ * it writes the gradients of U_bar . U:
+ *   q_bar[nc]      = -lambda (0 off A)
+ *   e_bar[nc][3], arm_bar[nc][2]   through the columns of D
+ *   F_bar[n][6]    = M U_bar
+ *   dir_bar[n][3]  through the mobility blocks and the lever arms s * dir
+ * Inputs have the layouts of rl_solve_lcp (pi sorted, pi <= pj); gamma is
+ * the solution returned by rl_solve_lcp on the same inputs.  F may be NULL.
+ * Outputs are device arrays owned by the caller and are overwritten.
+ * Returns info->status, or an error (RL_ERR_ARG on a NULL array, an
+ * unsorted or out-of-range index, a bad size).  Synchronises. */
+int rl_solve_lcp_adjoint(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                         const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                         const double *F, const double *gamma, const double *U_bar, double cg_tol, double *q_bar,
+                         double *e_bar, double *arm_bar, double *F_bar, double *dir_bar, rl_adjoint_info *info);
+
+/* Adjoint of one rl_step.  The step is the map (x, theta, F) -> (x', theta')
+ * with x' = x + h U_t (wrapping shifts by whole box lengths and has
+ * derivative 1) and theta' = normalise(theta + h Psi(theta) Omega).  The
+ * entry point re-runs the forward step from (x, quat, F): pair search,
+ * geometry, BBPGD from gamma = 0.  It is the same computation as rl_step on
+ * those inputs, and x, quat are not changed.  Then it differentiates the
+ * step at that point, with the pair list and A held fixed:
+ *   x_bar[n][3]    in: adjoint of x'; out: adjoint of x
+ *   quat_bar[n][4] in: adjoint of theta'; out: adjoint of theta, with its
+ *                  component along theta removed (the gradient on the unit
+ *                  sphere; theta is renormalised each step)
+ *   F_bar[n][6]    out: adjoint of F (F may be NULL: zero load)
+ * The closest points are differentiated through the clamped normal
+ * equations.  Where an arclength sits on a rod end it is held there.  For
+ * parallel axes (1 - (di.dj)^2 <= 1e-14) the closest points are held fixed.
+ * For intersecting axes (distance < 1e-12) the normal is held fixed.
+ * Returns the CG status (>= 0; a forward solve that did not converge is
+ * reported in info->solve_status), or an error.  Synchronises. */
+int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat, const double *len, double len0,
+                    const double *F, double *x_bar, double *quat_bar, double *F_bar, double cg_tol,
+                    rl_adjoint_info *info);
+
 /* Kernel timing with HIP events on the handle's stream, for measurement.
  * With every > 0, every every-th BBPGD iteration of later solves records
  * events around its rod kernel and its constraint kernel (iterations after

@@ -44,10 +44,16 @@ class SolveInfo(C.Structure):
                 ("status", C.c_int32), ("fp64_refreshes", C.c_int32)]
 
 
+class AdjointInfo(C.Structure):
+    _fields_ = [("cg_iterations", C.c_int64), ("cg_residual", C.c_double), ("n_active", C.c_int64),
+                ("status", C.c_int32), ("solve_status", C.c_int32), ("solve_iterations", C.c_int64),
+                ("solve_residual", C.c_double)]
+
+
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
-           "rl_batch_tuning")
+           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -81,6 +87,9 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_solve_lcp_batched": ([H, I32, P, P, P, P, D, P, P, P, P, P, P, P, P, P], C.c_int),
             "rl_batch_tuning": ([H, C.c_int, C.c_int, P], C.c_int),
             "rl_profile_read": ([H, C.POINTER(C.c_double)], C.c_int),
+            "rl_solve_lcp_adjoint": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, D, P, P, P, P, P,
+                                      C.POINTER(AdjointInfo)], C.c_int),
+            "rl_step_adjoint": ([H, I64, P, P, P, D, P, P, P, P, D, C.POINTER(AdjointInfo)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -125,6 +134,22 @@ class SolveResult:
     alpha0: float
     status: int
     fp64_refreshes: int = 0
+
+
+@dataclass
+class AdjointResult:
+    cg_iterations: int
+    cg_residual: float
+    n_active: int
+    status: int
+    solve_status: int
+    solve_iterations: int
+    solve_residual: float
+
+
+def _adj_result(info) -> "AdjointResult":
+    return AdjointResult(int(info.cg_iterations), float(info.cg_residual), int(info.n_active), int(info.status),
+                         int(info.solve_status), int(info.solve_iterations), float(info.solve_residual))
 
 
 def _result(info) -> "SolveResult":
@@ -326,6 +351,49 @@ class Solver:
                               C.byref(info), C.byref(npairs))
         self._check(rc, "rl_step")
         return U, _result(info), int(npairs.value)
+
+    def solve_lcp_adjoint(self, dir_, length, pi, pj, e, arm, q, gamma, U_bar, F=None, cg_tol=0.0):
+        """Adjoint of solve_lcp as the map (dir, e, arm, q, F) -> U at its
+        solution gamma.  Returns (q_bar, e_bar, arm_bar, F_bar, dir_bar,
+        AdjointResult)."""
+        torch = _torch()
+        n, nc = dir_.shape[0], pi.shape[0]
+        la, l0 = _len_args(length, n)
+        dev = dir_.device
+        qb = torch.empty(nc, dtype=torch.float64, device=dev)
+        eb = torch.empty((nc, 3), dtype=torch.float64, device=dev)
+        ab = torch.empty((nc, 2), dtype=torch.float64, device=dev)
+        Fb = torch.empty((n, 6), dtype=torch.float64, device=dev)
+        db = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        info = AdjointInfo()
+        self._stream()
+        rc = self.lib.rl_solve_lcp_adjoint(
+            self._h, n, _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, nc, _ptr(pi, torch.int32, (nc,), "pi"),
+            _ptr(pj, torch.int32, (nc,), "pj"), _ptr(e, torch.float64, (nc, 3), "e"),
+            _ptr(arm, torch.float64, (nc, 2), "arm"), _ptr(q, torch.float64, (nc,), "q"),
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
+            _ptr(U_bar, torch.float64, (n, 6), "U_bar"), float(cg_tol), _ptr(qb), _ptr(eb), _ptr(ab), _ptr(Fb),
+            _ptr(db), C.byref(info))
+        self._check(rc, "rl_solve_lcp_adjoint")
+        return qb, eb, ab, Fb, db, _adj_result(info)
+
+    def step_adjoint(self, x, quat, length, F, x_bar, quat_bar, F_bar=None, cg_tol=0.0):
+        """Adjoint of step() at (x, quat, F): x_bar and quat_bar hold the
+        adjoints of the step's outputs on entry and of its inputs on return
+        (in place).  Returns (F_bar, AdjointResult)."""
+        torch = _torch()
+        n = x.shape[0]
+        la, l0 = _len_args(length, n)
+        F_bar = torch.empty((n, 6), dtype=torch.float64, device=x.device) if F_bar is None else F_bar
+        info = AdjointInfo()
+        self._stream()
+        rc = self.lib.rl_step_adjoint(
+            self._h, n, _ptr(x, torch.float64, (n, 3), "x"), _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(x_bar, torch.float64, (n, 3), "x_bar"),
+            _ptr(quat_bar, torch.float64, (n, 4), "quat_bar"), _ptr(F_bar, torch.float64, (n, 6), "F_bar"),
+            float(cg_tol), C.byref(info))
+        self._check(rc, "rl_step_adjoint")
+        return F_bar, _adj_result(info)
 
 
 def status_str(status: int) -> str:

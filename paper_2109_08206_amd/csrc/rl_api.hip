@@ -357,6 +357,104 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     return rc;
 }
 
+int rl_solve_lcp_adjoint(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                         const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                         const double *F, const double *gamma, const double *U_bar, double cg_tol, double *q_bar,
+                         double *e_bar, double *arm_bar, double *F_bar, double *dir_bar, rl_adjoint_info *info)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff && nc >= 0 && nc < 0x7fffffff, "rl_solve_lcp_adjoint: bad sizes");
+    RL_REQUIRE(nc == 0 || (pi && pj && e && arm && q && gamma && q_bar && e_bar && arm_bar),
+               "rl_solve_lcp_adjoint: NULL constraint array");
+    RL_REQUIRE(n == 0 || (dir && U_bar && F_bar && dir_bar), "rl_solve_lcp_adjoint: NULL rod array");
+    RL_REQUIRE(len || len0 > 0.0, "rl_solve_lcp_adjoint: len0 must be > 0 when len is NULL");
+    if (info) *info = rl_adjoint_info{0, 0.0, 0, RL_OK, RL_OK, 0, 0.0};
+    if (n == 0) return RL_OK;
+    SolveArgs a;
+    int rc = prepare_solve(h, n, dir, len, len0, nc, pi, pj, e, arm, q, const_cast<double *>(gamma), &a);
+    if (rc) return rc;
+    int err = 0;
+    double *dmob = (double *)ws_get(h, kWsAdjDmob, sizeof(double) * 3 * n, &err);
+    double *d_bar = (double *)ws_get(h, kWsAdjDbar, sizeof(double) * 6 * (nc > 0 ? nc : 1), &err);
+    if (err) return err;
+    AdjOut o{F_bar, q_bar, e_bar, arm_bar, d_bar, dmob};
+    rl_adjoint_info ai{0, 0.0, 0, RL_OK, RL_OK, 0, 0.0};
+    rc = adjoint_core(h, a, false, U_bar, F, nullptr, cg_tol, o, &ai);
+    if (rc < 0) return rc;
+    RL_HIP(launch_dir_bar(h->stream, a, dmob, d_bar, dir_bar));
+    RL_HIP(hipStreamSynchronize(h->stream));
+    if (info) *info = ai;
+    return rc;
+}
+
+int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat, const double *len, double len0,
+                    const double *F, double *x_bar, double *quat_bar, double *F_bar, double cg_tol,
+                    rl_adjoint_info *info)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff, "rl_step_adjoint: bad n");
+    RL_REQUIRE(n == 0 || (x && quat && x_bar && quat_bar && F_bar), "rl_step_adjoint: NULL array");
+    RL_REQUIRE(len || len0 > 0.0, "rl_step_adjoint: len0 must be > 0 when len is NULL");
+    if (info) *info = rl_adjoint_info{0, 0.0, 0, RL_OK, RL_OK, 0, 0.0};
+    if (n == 0) return RL_OK;
+    hipStream_t st = h->stream;
+    int err = 0;
+    double *dir = (double *)ws_get(h, kWsDir, sizeof(double) * 3 * n, &err);
+    if (err) return err;
+    RL_HIP(launch_directors(st, n, quat, dir));
+    // the forward step, as rl_step takes it (rods in cell order)
+    int64_t np = 0;
+    const int *perm = nullptr;
+    const double *xs = nullptr, *ds = nullptr, *ls = nullptr;
+    int rc = build_pairs_sorted(h, n, x, dir, len, len0, &np, &perm, &xs, &ds, &ls);
+    if (rc) return rc;
+    const int64_t nb = np > 0 ? np : 1;
+    double *phi = (double *)ws_get(h, kWsStepPhi, sizeof(double) * nb, &err);
+    double *e = (double *)ws_get(h, kWsStepE, sizeof(double) * 3 * nb, &err);
+    double *arm = (double *)ws_get(h, kWsStepArm, sizeof(double) * 2 * nb, &err);
+    double *q = (double *)ws_get(h, kWsStepQ, sizeof(double) * nb, &err);
+    double *gamma = (double *)ws_get(h, kWsStepGamma, sizeof(double) * nb, &err);
+    double *Fs = F ? (double *)ws_get(h, kWsFs, sizeof(double) * 6 * n, &err) : nullptr;
+    double *Uc = (double *)ws_get(h, kWsStepU, sizeof(double) * 6 * n, &err);
+    double *Ubar = (double *)ws_get(h, kWsAdjUbar, sizeof(double) * 6 * n, &err);
+    double *qbd = (double *)ws_get(h, kWsAdjQbd, sizeof(double) * 4 * n, &err);
+    double *dmob = (double *)ws_get(h, kWsAdjDmob, sizeof(double) * 3 * n, &err);
+    double *qbar = (double *)ws_get(h, kWsAdjQbar, sizeof(double) * nb, &err);
+    double *ebar = (double *)ws_get(h, kWsAdjEbar, sizeof(double) * 3 * nb, &err);
+    double *armbar = (double *)ws_get(h, kWsAdjArmbar, sizeof(double) * 2 * nb, &err);
+    double *dbar = (double *)ws_get(h, kWsAdjDbar, sizeof(double) * 6 * nb, &err);
+    double *gbar = (double *)ws_get(h, kWsAdjGbar, sizeof(double) * 9 * nb, &err);
+    if (err) return err;
+    if (F) RL_HIP(launch_gather6(st, n, perm, F, Fs));
+    const double *lsv = len ? ls : nullptr;
+    const int32_t *pi = (const int32_t *)h->buf[kWsStepPi], *pj = (const int32_t *)h->buf[kWsStepPj];
+    const int32_t *img = (const int32_t *)h->buf[kWsStepImg];
+    rc = assemble_impl(h, n, xs, ds, lsv, len0, np, pi, pj, img, Fs, phi, e, arm, q);
+    if (rc) return rc;
+    RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, st));
+    SolveArgs a;
+    rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a);
+    if (rc) return rc;
+    rl_solve_info si{0, 0.0, 0.0, RL_OK, 0};
+    const int src = solve_impl(h, a, F, Uc, nullptr, &si, perm);
+    if (src < 0) return src;
+    // adjoint: Euler update, then the solve, then the geometry
+    RL_HIP(launch_integrate_adj(st, n, perm, x_bar, quat_bar, quat, Uc, h->prm.dt, Ubar, qbd));
+    AdjOut o{F_bar, qbar, ebar, armbar, dbar, dmob};
+    rl_adjoint_info ai{0, 0.0, 0, RL_OK, RL_OK, 0, 0.0};
+    rc = adjoint_core(h, a, true, Ubar, F, perm, cg_tol, o, &ai);
+    if (rc < 0) return rc;
+    RL_HIP(launch_geo_adjoint(st, np, xs, ds, lsv, len0, h->prm.box, pi, pj, img, h->prm.dt, qbar, ebar, armbar, dbar,
+                              gbar));
+    RL_HIP(launch_step_bar(st, a, perm, gbar, dmob, qbd, quat, x_bar, quat_bar));
+    RL_HIP(hipStreamSynchronize(st));
+    ai.solve_status = si.status;
+    ai.solve_iterations = si.iterations;
+    ai.solve_residual = si.residual;
+    if (info) *info = ai;
+    return rc;
+}
+
 int rl_solve_lcp_batched(rl_handle h, int32_t S, const int64_t *rod_off, const int64_t *pair_off, const double *dir,
                          const double *len, double len0, const int32_t *pi, const int32_t *pj, const double *e,
                          const double *arm, const double *q, const double *F, double *gamma, double *U,

@@ -12,33 +12,10 @@
 #include <cstdarg>
 #include <cstring>
 
-#include "rl_internal.hpp"
+#include "rl_vec.hpp"
 
 namespace rl {
 
-// ---------------------------------------------------------------------------
-// small vector helpers
-// ---------------------------------------------------------------------------
-struct V3 {
-    double x, y, z;
-};
-__device__ __forceinline__ V3 v3(double a, double b, double c) { return V3{a, b, c}; }
-__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
-__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
-__device__ __forceinline__ V3 operator*(double s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
-__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ V3 cross(V3 a, V3 b)
-{
-    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ V3 load3(const double *p) { return v3(p[0], p[1], p[2]); }
-__device__ __forceinline__ void store3(double *p, V3 a)
-{
-    p[0] = a.x;
-    p[1] = a.y;
-    p[2] = a.z;
-}
-__device__ __forceinline__ double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // ---------------------------------------------------------------------------
 // directors: third column of R(theta) = (s^2 - p.p) I + 2 p p^T + 2 s [p]x
@@ -696,6 +673,84 @@ int assemble_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, cons
         return RL_ERR_ARG;
     }
     return RL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the constraint geometry (differentiation form)
+// ---------------------------------------------------------------------------
+// Per constraint, from phi_bar = q_bar / h, e_bar and the arclength
+// adjoints (s_bar, t_bar), the adjoints of r0 = x_i - x_j' and of the two
+// directors; d_bar (the lever-arm parts) is added to the director terms.
+// r = r0 + s di - t dj, phi = |r| - diam, e = r / |r|.  The arclengths are
+// stationary points of |r|^2 over the free ones: r.di = 0 when s is inside
+// (-L_i/2, L_i/2), r.dj = 0 when t is inside (-L_j/2, L_j/2); an arclength
+// on a rod end stays there.  Their derivatives follow from differentiating
+// those conditions (implicit function; unit directors, so the 2x2 system
+// has the matrix [[1, -b], [b, -1]], b = di.dj).  Parallel axes keep their
+// closest points fixed and intersecting axes their normal (the midpoint and
+// cross-product rules have no derivative that the step uses).
+__global__ void k_geo_adjoint(int64_t nc, const double *__restrict__ x, const double *__restrict__ dir,
+                              const double *__restrict__ len, double len0, GridDev g,
+                              const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                              const int32_t *__restrict__ img, double dt, const double *__restrict__ qbar,
+                              const double *__restrict__ ebar, const double *__restrict__ armbar,
+                              const double *__restrict__ dbar, double *__restrict__ gbar)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const int i = pi[c], j = pj[c], im = img[c];
+    const double sx = ((im >> 8) & 15) - 8, sy = ((im >> 4) & 15) - 8, sz = (im & 15) - 8;
+    const V3 xi = load3(x + 3 * (int64_t)i), di = load3(dir + 3 * (int64_t)i);
+    const V3 xj = load3(x + 3 * (int64_t)j) + v3(sx * g.box[0], sy * g.box[1], sz * g.box[2]);
+    const V3 dj = load3(dir + 3 * (int64_t)j);
+    const double hi = 0.5 * (len ? len[i] : len0), hj = 0.5 * (len ? len[j] : len0);
+    const Contact ct = closest_point(xi, di, hi, xj, dj, hj);
+    const double b = dot(di, dj), den = 1.0 - b * b;
+    const V3 r = (xi - xj) + ct.s * di - ct.t * dj;
+    const double phib = qbar[c] / dt;
+    const V3 eb = load3(ebar + 3 * c);
+    V3 rb = phib * ct.e;
+    if (!(ct.flags & 4u)) rb = rb + (1.0 / ct.dist) * (eb - dot(ct.e, eb) * ct.e);
+    const double sb = armbar[2 * c] + dot(rb, di);
+    const double tb = armbar[2 * c + 1] - dot(rb, dj);
+    V3 r0b = rb;
+    V3 dib = ct.s * rb + load3(dbar + 6 * c);
+    V3 djb = (-ct.t) * rb + load3(dbar + 6 * c + 3);
+    if (den > kEpsPar) {
+        const bool s_in = fabs(ct.s) < hi, t_in = fabs(ct.t) < hj;
+        // dF1 = dr0.di + (r + s di).ddi - t di.ddj (+ ds - b dt)
+        // dF2 = dr0.dj + s dj.ddi + (r - t dj).ddj (+ b ds - dt)
+        if (s_in && t_in) {
+            const double mu2 = -(tb + b * sb) / den, mu1 = sb - b * mu2;
+            r0b = r0b - (mu1 * di + mu2 * dj);
+            dib = dib - (mu1 * (r + ct.s * di) + (mu2 * ct.s) * dj);
+            djb = djb - ((-mu1 * ct.t) * di + mu2 * (r - ct.t * dj));
+        } else if (t_in) {
+            r0b = r0b + tb * dj;
+            dib = dib + (tb * ct.s) * dj;
+            djb = djb + tb * (r - ct.t * dj);
+        } else if (s_in) {
+            r0b = r0b - sb * di;
+            dib = dib - sb * (r + ct.s * di);
+            djb = djb + (sb * ct.t) * di;
+        }
+    }
+    store3(gbar + 9 * c, r0b);
+    store3(gbar + 9 * c + 3, dib);
+    store3(gbar + 9 * c + 6, djb);
+}
+
+hipError_t launch_geo_adjoint(hipStream_t st, int64_t nc, const double *x, const double *dir, const double *len,
+                              double len0, const double box[3], const int32_t *pi, const int32_t *pj,
+                              const int32_t *img, double dt, const double *q_bar, const double *e_bar,
+                              const double *arm_bar, const double *d_bar, double *gbar)
+{
+    if (nc <= 0) return hipSuccess;
+    GridDev g{};
+    for (int a = 0; a < 3; ++a) g.box[a] = box[a];
+    hipLaunchKernelGGL(k_geo_adjoint, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, x, dir, len, len0, g, pi, pj, img,
+                       dt, q_bar, e_bar, arm_bar, d_bar, gbar);
+    return hipGetLastError();
 }
 
 }  // namespace rl

@@ -113,7 +113,7 @@ struct rl_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     // grow-only workspace slots
-    static constexpr int kSlots = 64;
+    static constexpr int kSlots = 96;
     void *buf[kSlots] = {};
     size_t cap[kSlots] = {};
     rl::SolverState *state = nullptr;       // device
@@ -147,6 +147,8 @@ enum Slot : int {
     kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
     kWsBatchPartial2, kWsBatchDone, kWsBatchMap,
+    kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
+    kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -188,8 +190,42 @@ hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a);
 hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U);
 hipError_t launch_velocity_on(hipStream_t st, const SolveArgs &a, const double *F, const int *perm, double *U);
 hipError_t launch_unpack_gamma(hipStream_t st, const SolveArgs &a, double *gamma);
+__global__ void k_state_init(SolverState *st, double tol, long long max_iter);
 __global__ void k_restore_start(int64_t nc, const double *gamma_in, const int32_t *qpos, double2 *st,
                                 double2 *stq);
+// adjoint (rl_adjoint.hip): lambda on the active set by CG, then the
+// per-rod and per-constraint adjoints.  `a` is a prepared solve whose st
+// holds gamma; Ubar is in solver rod order; F and F_bar in the caller's
+// (perm maps solver -> caller, may be null).  step: q includes D^T M F
+// (rl_step_adjoint) rather than being an input of its own.
+struct AdjOut {
+    double *F_bar;     // [n][6] caller order
+    double *q_bar;     // [nc]
+    double *e_bar;     // [nc][3]
+    double *arm_bar;   // [nc][2]
+    double *d_bar;     // [nc][6] lever-arm parts of dir_bar (rod i, rod j)
+    double *dmob;      // [n][3] mobility part of dir_bar, solver order
+};
+int adjoint_core(rl_ctx *h, SolveArgs &a, bool step, const double *Ubar, const double *F, const int *perm,
+                 double cg_tol, const AdjOut &o, rl_adjoint_info *info);
+// dir_bar = dmob + sum of the lever-arm parts over each rod's constraints
+hipError_t launch_dir_bar(hipStream_t st, const SolveArgs &a, const double *dmob, const double *d_bar,
+                          double *dir_bar);
+// step: adjoint of the Euler update (solver order out), and the final
+// per-rod sums into x_bar / quat_bar (caller order, in place)
+hipError_t launch_integrate_adj(hipStream_t st, int64_t n, const int *perm, const double *x_bar,
+                                const double *quat_bar, const double *quat, const double *U, double dt,
+                                double *Ubar, double *qbd);
+hipError_t launch_step_bar(hipStream_t st, const SolveArgs &a, const int *perm, const double *gbar,
+                           const double *dmob, const double *qbd, const double *quat, double *x_bar,
+                           double *quat_bar);
+// closest-point adjoint (rl_geometry.hip): per constraint (r0_bar, dir_i_bar,
+// dir_j_bar) from (phi_bar = q_bar / h, e_bar, arm_bar) plus the lever-arm
+// parts d_bar
+hipError_t launch_geo_adjoint(hipStream_t st, int64_t nc, const double *x, const double *dir, const double *len,
+                              double len0, const double box[3], const int32_t *pi, const int32_t *pj,
+                              const int32_t *img, double dt, const double *q_bar, const double *e_bar,
+                              const double *arm_bar, const double *d_bar, double *gbar);
 int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *pair_off, SolveArgs &a,
                        const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
                        const double *gamma_in, const double *F, double *gamma_out, double *U, rl_solve_info *infos);

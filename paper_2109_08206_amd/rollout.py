@@ -1,0 +1,82 @@
+"""Differentiable multi-step rollout of the steric step.
+
+``Rollout`` is a ``torch.autograd.Function`` over the C-ABI.
+  * Forward: T calls of ``rl_step`` (the linearised Euler step of
+    eq. constrainedeom_euler, one complementarity solve per step).  It
+    keeps (x, theta) only every ``checkpoint_every`` steps.
+  * Backward: walks the segments in reverse.  For each one it recomputes the
+    segment's states from its checkpoint with ``rl_step``, then calls
+    ``rl_step_adjoint`` step by step in reverse.  Both calls are
+    deterministic (fixed summation orders), so the recomputed states are
+    bitwise those of the forward pass.
+The output is the unwrapped centres x0 + h sum_t U_t (plus theta_T).
+Wrapping into the periodic box shifts by whole box lengths and does not
+change the derivative.  Marshalling only: every step runs in the HIP
+kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import NOT_CONVERGED, STAGNATED, RodLCPError
+
+
+class Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x0, quat0, F, solver, length, checkpoint_every, cg_tol):
+        T, n = F.shape[0], x0.shape[0]
+        k = max(1, int(checkpoint_every))
+        dt = solver.params.dt
+        x = x0.detach().clone()
+        quat = quat0.detach().clone()
+        xu = x0.detach().clone()
+        U = torch.empty((n, 6), dtype=torch.float64, device=x0.device)
+        ckpt = []
+        infos = []
+        for t in range(T):
+            if t % k == 0:
+                ckpt.append((x.clone(), quat.clone()))
+            _, info, npairs = solver.step(x, quat, length, F[t], U=U)
+            if info.status in (NOT_CONVERGED, STAGNATED):
+                raise RodLCPError(info.status, "Rollout.forward", f"step {t} did not converge")
+            infos.append((info.iterations, npairs))
+            xu.add_(U[:, :3], alpha=dt)
+        ctx.solver, ctx.length, ctx.k, ctx.cg_tol = solver, length, k, cg_tol
+        ctx.ckpt = ckpt
+        ctx.infos = infos
+        ctx.save_for_backward(F)
+        ctx.mark_non_differentiable()
+        return xu, quat
+
+    @staticmethod
+    def backward(ctx, xu_bar, quat_bar):
+        (F,) = ctx.saved_tensors
+        solver, length, k = ctx.solver, ctx.length, ctx.k
+        T, n = F.shape[0], F.shape[1]
+        x_bar = (xu_bar if xu_bar is not None else torch.zeros((n, 3), dtype=torch.float64, device=F.device))
+        x_bar = x_bar.detach().clone().contiguous()
+        q_bar = (quat_bar if quat_bar is not None else torch.zeros((n, 4), dtype=torch.float64, device=F.device))
+        q_bar = q_bar.detach().clone().contiguous()
+        F_bar = torch.empty_like(F)
+        adj = []
+        for seg in reversed(range(len(ctx.ckpt))):
+            t0 = seg * k
+            t1 = min(T, t0 + k)
+            x, quat = (v.clone() for v in ctx.ckpt[seg])
+            states = []
+            for t in range(t0, t1):
+                states.append((x.clone(), quat.clone()))
+                if t < t1 - 1:
+                    solver.step(x, quat, length, F[t])
+            for t in reversed(range(t0, t1)):
+                xs, qs = states[t - t0]
+                _, info = solver.step_adjoint(xs, qs, length, F[t], x_bar, q_bar, F_bar=F_bar[t], cg_tol=ctx.cg_tol)
+                adj.append(info)
+        ctx.adjoint_infos = adj
+        return x_bar, q_bar, F_bar, None, None, None, None
+
+
+def rollout(solver, x0, quat0, length, F, checkpoint_every: int = 10, cg_tol: float = 0.0):
+    """Unwrapped final centres and final quaternions after F.shape[0] steps;
+    differentiable with respect to x0, quat0 (on the unit sphere) and F."""
+    return Rollout.apply(x0, quat0, F, solver, length, checkpoint_every, cg_tol)
