@@ -238,6 +238,75 @@ def form_batched(args, torch, rl, rodsynth) -> dict:
     }
 
 
+def form_adjoint(args, torch, rl, rodsynth) -> dict:
+    """Gradient of sum |x_T|^2 (unwrapped centres) over a checkpointed rollout
+    with respect to x0, theta0 and every step's forces, against the forward
+    rollout alone."""
+    import numpy as np
+
+    from paper_2109_08206_amd.rollout import rollout
+    dev = torch.device("cuda:0")
+    n = args.rods if args.rods != 100_000 else 50_000
+    s = rodsynth.cfg_rollout(args.seed, n=n)
+    T, k = args.rollout_steps, args.checkpoint_every
+    rng = np.random.default_rng([args.seed, 9])
+    F = torch.empty((T, n, 6), dtype=torch.float64, device=dev)
+    F[0] = torch.as_tensor(s.force, device=dev)
+    for t in range(1, T):
+        F[t] = torch.as_tensor(rng.standard_normal((n, 6)), device=dev)
+    x0 = torch.as_tensor(s.x, device=dev)
+    q0 = torch.as_tensor(s.quat, device=dev)
+    slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8, max_iter=200_000)
+
+    def grad_run(steps):
+        xg = x0.clone().requires_grad_(True)
+        qg = q0.clone().requires_grad_(True)
+        Fg = F[:steps].clone().requires_grad_(True)
+        xu, _ = rollout(slv, xg, qg, 1.0, Fg, checkpoint_every=k, cg_tol=args.cg_tol, tape=not args.no_tape)
+        loss = (xu * xu).sum()
+        loss.backward()
+        return xu, loss, xg, qg, Fg
+
+    for _ in range(args.warmup):
+        grad_run(min(T, 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        xu_f, _ = rollout(slv, x0, q0, 1.0, F, checkpoint_every=k, tape=not args.no_tape)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xu, loss, xg, qg, Fg = grad_run(T)
+    torch.cuda.synchronize()
+    t_tot = time.perf_counter() - t0
+    ctx = xu.grad_fn
+    fwd_it = [i for i, _ in ctx.infos]
+    adj = ctx.adjoint_infos
+    slv.close()
+    return {
+        "metric": "differentiation form: gradient of sum |x_T|^2 over a checkpointed rollout (forward + backward)",
+        "value": T / t_tot, "unit": "rollout steps/s with gradient", "n_gpus": 1, "steps": T,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_tot / T, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{n} rods L=1 d=0.025 phi=0.05 isotropic, {T} steps, checkpoint every {k}, "
+                               f"forward residual 1e-8, CG relative residual {args.cg_tol:g}",
+                   "rods": n, "steps": T, "checkpoint_every": k, "seed": args.seed,
+                   "gamma_tape": not args.no_tape},
+        "forward_only_ms_per_step": 1e3 * t_fwd / T,
+        "backward_ms_per_step": 1e3 * (t_tot - t_fwd) / T,
+        "gradient_over_forward_time": t_tot / t_fwd,
+        "mean_bbpgd_iterations": sum(fwd_it) / len(fwd_it),
+        "mean_constraints": sum(p for _, p in ctx.infos) / len(ctx.infos),
+        "mean_cg_iterations": sum(a.cg_iterations for a in adj) / len(adj),
+        "max_cg_iterations": max(a.cg_iterations for a in adj),
+        "mean_active": sum(a.n_active for a in adj) / len(adj),
+        "cg_statuses": sorted({a.status for a in adj}),
+        "loss": float(loss.detach()),
+        "grad_norms": {"x0": float(xg.grad.norm()), "theta0": float(qg.grad.norm()), "F": float(Fg.grad.norm())},
+        "forward_matches_gradient_run": bool(torch.equal(xu_f, xu.detach())),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,9 +317,14 @@ def main() -> int:
     ap.add_argument("--profile-every", type=int, default=8, help="sample kernel events every k-th iteration")
     ap.add_argument("--cpu-iters", type=int, default=200, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["step", "precision", "batched"], default="step",
+    ap.add_argument("--form", choices=["step", "precision", "batched", "adjoint"], default="step",
                     help="step: the FP64 whole-step benchmark (default); precision: FP32-mixed vs FP64; "
-                         "batched: many systems in one batched solve")
+                         "batched: many systems in one batched solve; adjoint: gradient of a rollout")
+    ap.add_argument("--rollout-steps", type=int, default=100, help="adjoint form: rollout length")
+    ap.add_argument("--checkpoint-every", type=int, default=10, help="adjoint form: checkpoint interval")
+    ap.add_argument("--cg-tol", type=float, default=1e-10, help="adjoint form: CG relative residual")
+    ap.add_argument("--no-tape", action="store_true",
+                    help="adjoint form: re-solve each step cold in the backward pass instead of replaying gamma")
     ap.add_argument("--phi", type=float, default=None, help="volume fraction override (precision form)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 1 GiB device buffer once (reference for HBM counters)")
@@ -273,6 +347,9 @@ def main() -> int:
         return 0
     if args.form == "batched":
         print(json.dumps(form_batched(args, torch, rl, rodsynth)), flush=True)
+        return 0
+    if args.form == "adjoint":
+        print(json.dumps(form_adjoint(args, torch, rl, rodsynth)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     s = rodsynth.cfg_paper_scale(args.seed, n=args.rods)

@@ -172,9 +172,28 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
  * first line; Psi of Appendix "Filament dynamics").  x and quat are updated
  * in place; U (may be NULL) receives the velocities; *n_pairs (host, may be
  * NULL) the constraint count.  Pair and constraint storage is the handle's.
+ *
+ * Tape (for differentiating rollouts): the step's constraint forces gamma,
+ * in the step's own constraint order (the canonical pair order of the rods
+ * renumbered in cell order; opaque to the caller, but a pure function of
+ * (x, quat, len)).  gamma_tape is a device array of tape_len doubles.
+ *   RL_TAPE_NONE    gamma_tape unused (may be NULL); cold start gamma = 0.
+ *   RL_TAPE_RECORD  cold start; the solution is written to gamma_tape.  If
+ *                   the constraint count exceeds tape_len, nothing is
+ *                   changed, *n_pairs holds the count and RL_ERR_CAPACITY
+ *                   is returned.
+ *   RL_TAPE_REPLAY  gamma_tape holds the tape recorded for the same
+ *                   (x, quat, len) and tape_len must equal its count
+ *                   (RL_ERR_ARG otherwise); the solve starts from it, so an
+ *                   identical state stops at once with the identical
+ *                   solution (written back to gamma_tape).
  * Synchronises. */
+#define RL_TAPE_NONE 0
+#define RL_TAPE_RECORD 1
+#define RL_TAPE_REPLAY 2
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
-            double *U, rl_solve_info *info, int64_t *n_pairs);
+            double *U, rl_solve_info *info, int64_t *n_pairs, double *gamma_tape, int64_t tape_len,
+            int32_t tape_mode);
 
 /* Batching form: S independent periodic systems solved together (one set
  * of launches per BBPGD phase for all of them, iterations replayed from a
@@ -255,11 +274,15 @@ int rl_solve_lcp_adjoint(rl_handle h, int64_t n, const double *dir, const double
  * equations.  Where an arclength sits on a rod end it is held there.  For
  * parallel axes (1 - (di.dj)^2 <= 1e-14) the closest points are held fixed.
  * For intersecting axes (distance < 1e-12) the normal is held fixed.
+ * gamma_tape (may be NULL) is the tape rl_step recorded for the same
+ * (x, quat, len) with tape_len its count.  The forward solve then starts
+ * from it and stops at once.  Without it, the solve runs from gamma = 0 to
+ * the same bitwise result.  RL_ERR_ARG if tape_len does not match.
  * Returns the CG status (>= 0; a forward solve that did not converge is
  * reported in info->solve_status), or an error.  Synchronises. */
 int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat, const double *len, double len0,
-                    const double *F, double *x_bar, double *quat_bar, double *F_bar, double cg_tol,
-                    rl_adjoint_info *info);
+                    const double *F, const double *gamma_tape, int64_t tape_len, double *x_bar, double *quat_bar,
+                    double *F_bar, double cg_tol, rl_adjoint_info *info);
 
 /* Kernel timing with HIP events on the handle's stream, for measurement.
  * With every > 0, every every-th BBPGD iteration of later solves records

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "librodlcp.so")
 OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
 ERR_ARG, ERR_CAPACITY, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = -1, -2, -3, -4, -5
 FP64, FP32_MIXED = 0, 1
+TAPE_NONE, TAPE_RECORD, TAPE_REPLAY = 0, 1, 2
 IMG_ZERO = 0x888
 
 _lib = None
@@ -82,14 +83,15 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_assemble_D": ([H, I64, P, P, P, D, I64, P, P, P, P, P, P, P, P], C.c_int),
             "rl_apply_M": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P], C.c_int),
             "rl_solve_lcp": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)], C.c_int),
-            "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64)], C.c_int),
+            "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64), P, I64, I32],
+                        C.c_int),
             "rl_profile_enable": ([H, C.c_int], C.c_int),
             "rl_solve_lcp_batched": ([H, I32, P, P, P, P, D, P, P, P, P, P, P, P, P, P], C.c_int),
             "rl_batch_tuning": ([H, C.c_int, C.c_int, P], C.c_int),
             "rl_profile_read": ([H, C.POINTER(C.c_double)], C.c_int),
             "rl_solve_lcp_adjoint": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, D, P, P, P, P, P,
                                       C.POINTER(AdjointInfo)], C.c_int),
-            "rl_step_adjoint": ([H, I64, P, P, P, D, P, P, P, P, D, C.POINTER(AdjointInfo)], C.c_int),
+            "rl_step_adjoint": ([H, I64, P, P, P, D, P, P, I64, P, P, P, D, C.POINTER(AdjointInfo)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -336,21 +338,44 @@ class Solver:
         self._check(self.lib.rl_batch_tuning(self._h, int(rod_block), int(con_block), out), "rl_batch_tuning")
         return int(out[0]), int(out[1])
 
-    def step(self, x, quat, length, F=None, U=None):
-        """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs)."""
+    def step(self, x, quat, length, F=None, U=None, tape=None, tape_mode=TAPE_NONE):
+        """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs).
+        tape: float64 device tensor for the step's constraint forces
+        (TAPE_RECORD writes them, TAPE_REPLAY starts from them)."""
         torch = _torch()
         n = x.shape[0]
         la, l0 = _len_args(length, n)
         U = torch.empty((n, 6), dtype=torch.float64, device=x.device) if U is None else U
         info = SolveInfo()
         npairs = C.c_int64(0)
+        tlen = 0 if tape is None else int(tape.shape[0])
         self._stream()
         rc = self.lib.rl_step(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
                               _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
                               _ptr(F, torch.float64, (n, 6), "F"), _ptr(U, torch.float64, (n, 6), "U"),
-                              C.byref(info), C.byref(npairs))
+                              C.byref(info), C.byref(npairs), _ptr(tape, torch.float64, None, "tape"), tlen,
+                              int(tape_mode))
+        if rc == ERR_CAPACITY and tape_mode == TAPE_RECORD:
+            err = RodLCPError(rc, "rl_step", f"tape too short for {int(npairs.value)} constraints")
+            err.count = int(npairs.value)
+            raise err
         self._check(rc, "rl_step")
         return U, _result(info), int(npairs.value)
+
+    def step_recording(self, x, quat, length, F=None, U=None, capacity=None):
+        """step() that records its tape; returns (U, SolveResult, tape)."""
+        torch = _torch()
+        cap = int(capacity) if capacity is not None else 16 * x.shape[0] + 64
+        for _ in range(2):
+            tape = torch.empty(max(cap, 1), dtype=torch.float64, device=x.device)
+            try:
+                U, info, npairs = self.step(x, quat, length, F=F, U=U, tape=tape, tape_mode=TAPE_RECORD)
+                return U, info, tape[:npairs]
+            except RodLCPError as err:
+                if err.status != ERR_CAPACITY:
+                    raise
+                cap = err.count
+        raise RodLCPError(ERR_CAPACITY, "rl_step", "tape capacity")
 
     def solve_lcp_adjoint(self, dir_, length, pi, pj, e, arm, q, gamma, U_bar, F=None, cg_tol=0.0):
         """Adjoint of solve_lcp as the map (dir, e, arm, q, F) -> U at its
@@ -377,19 +402,22 @@ class Solver:
         self._check(rc, "rl_solve_lcp_adjoint")
         return qb, eb, ab, Fb, db, _adj_result(info)
 
-    def step_adjoint(self, x, quat, length, F, x_bar, quat_bar, F_bar=None, cg_tol=0.0):
+    def step_adjoint(self, x, quat, length, F, x_bar, quat_bar, F_bar=None, cg_tol=0.0, tape=None):
         """Adjoint of step() at (x, quat, F): x_bar and quat_bar hold the
         adjoints of the step's outputs on entry and of its inputs on return
-        (in place).  Returns (F_bar, AdjointResult)."""
+        (in place).  tape: the step's recorded constraint forces (optional).
+        Returns (F_bar, AdjointResult)."""
         torch = _torch()
         n = x.shape[0]
         la, l0 = _len_args(length, n)
         F_bar = torch.empty((n, 6), dtype=torch.float64, device=x.device) if F_bar is None else F_bar
         info = AdjointInfo()
+        tlen = 0 if tape is None else int(tape.shape[0])
         self._stream()
         rc = self.lib.rl_step_adjoint(
             self._h, n, _ptr(x, torch.float64, (n, 3), "x"), _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
-            _ptr(F, torch.float64, (n, 6), "F"), _ptr(x_bar, torch.float64, (n, 3), "x_bar"),
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(tape, torch.float64, None, "tape"), tlen,
+            _ptr(x_bar, torch.float64, (n, 3), "x_bar"),
             _ptr(quat_bar, torch.float64, (n, 4), "quat_bar"), _ptr(F_bar, torch.float64, (n, 6), "F_bar"),
             float(cg_tol), C.byref(info))
         self._check(rc, "rl_step_adjoint")

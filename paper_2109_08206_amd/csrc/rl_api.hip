@@ -307,12 +307,16 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
 }
 
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
-            double *U, rl_solve_info *info, int64_t *n_pairs)
+            double *U, rl_solve_info *info, int64_t *n_pairs, double *gamma_tape, int64_t tape_len,
+            int32_t tape_mode)
 {
     RL_CHECK_HANDLE(h);
     RL_REQUIRE(n >= 0 && n < 0x7fffffff, "rl_step: bad n");
     RL_REQUIRE(n == 0 || (x && quat), "rl_step: NULL x or quat");
     RL_REQUIRE(len || len0 > 0.0, "rl_step: len0 must be > 0 when len is NULL");
+    RL_REQUIRE(tape_mode == RL_TAPE_NONE || tape_mode == RL_TAPE_RECORD || tape_mode == RL_TAPE_REPLAY,
+               "rl_step: bad tape_mode");
+    RL_REQUIRE(tape_mode == RL_TAPE_NONE || tape_len >= 0, "rl_step: tape_len < 0");
     if (n == 0) {
         if (n_pairs) *n_pairs = 0;
         if (info) *info = rl_solve_info{0, 0.0, 0.0, RL_OK, 0};
@@ -330,6 +334,17 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     int rc = build_pairs_sorted(h, n, x, dir, len, len0, &np, &perm, &xs, &ds, &ls);
     if (rc) return rc;
     if (n_pairs) *n_pairs = np;
+    if (tape_mode == RL_TAPE_RECORD && np > tape_len) {
+        set_error("rl_step: tape holds %lld values, the step has %lld constraints", (long long)tape_len,
+                  (long long)np);
+        return RL_ERR_CAPACITY;
+    }
+    if (tape_mode == RL_TAPE_REPLAY && np != tape_len) {
+        set_error("rl_step: tape of %lld values replayed on a step with %lld constraints", (long long)tape_len,
+                  (long long)np);
+        return RL_ERR_ARG;
+    }
+    RL_REQUIRE(tape_mode == RL_TAPE_NONE || np == 0 || gamma_tape, "rl_step: NULL gamma_tape");
     const int64_t nb = np > 0 ? np : 1;
     double *phi = (double *)ws_get(h, kWsStepPhi, sizeof(double) * nb, &err);
     double *e = (double *)ws_get(h, kWsStepE, sizeof(double) * 3 * nb, &err);
@@ -345,11 +360,14 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     const int32_t *img = (const int32_t *)h->buf[kWsStepImg];
     rc = assemble_impl(h, n, xs, ds, lsv, len0, np, pi, pj, img, Fs, phi, e, arm, q);
     if (rc) return rc;
-    RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, h->stream));
+    if (tape_mode == RL_TAPE_REPLAY && np > 0)
+        RL_HIP(hipMemcpyAsync(gamma, gamma_tape, sizeof(double) * np, hipMemcpyDeviceToDevice, h->stream));
+    else
+        RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, h->stream));
     SolveArgs a;
     rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a);
     if (rc) return rc;
-    rc = solve_impl(h, a, F, Uw, gamma, info, perm);
+    rc = solve_impl(h, a, F, Uw, tape_mode != RL_TAPE_NONE && np > 0 ? gamma_tape : gamma, info, perm);
     if (rc < 0) return rc;
     const int rc2 = integrate_impl(h, n, Uw, x, quat);
     if (rc2) return rc2;
@@ -388,8 +406,8 @@ int rl_solve_lcp_adjoint(rl_handle h, int64_t n, const double *dir, const double
 }
 
 int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat, const double *len, double len0,
-                    const double *F, double *x_bar, double *quat_bar, double *F_bar, double cg_tol,
-                    rl_adjoint_info *info)
+                    const double *F, const double *gamma_tape, int64_t tape_len, double *x_bar, double *quat_bar,
+                    double *F_bar, double cg_tol, rl_adjoint_info *info)
 {
     RL_CHECK_HANDLE(h);
     RL_REQUIRE(n >= 0 && n < 0x7fffffff, "rl_step_adjoint: bad n");
@@ -408,6 +426,11 @@ int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat,
     const double *xs = nullptr, *ds = nullptr, *ls = nullptr;
     int rc = build_pairs_sorted(h, n, x, dir, len, len0, &np, &perm, &xs, &ds, &ls);
     if (rc) return rc;
+    if (gamma_tape && tape_len != np) {
+        set_error("rl_step_adjoint: tape of %lld values for a step with %lld constraints", (long long)tape_len,
+                  (long long)np);
+        return RL_ERR_ARG;
+    }
     const int64_t nb = np > 0 ? np : 1;
     double *phi = (double *)ws_get(h, kWsStepPhi, sizeof(double) * nb, &err);
     double *e = (double *)ws_get(h, kWsStepE, sizeof(double) * 3 * nb, &err);
@@ -431,7 +454,10 @@ int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat,
     const int32_t *img = (const int32_t *)h->buf[kWsStepImg];
     rc = assemble_impl(h, n, xs, ds, lsv, len0, np, pi, pj, img, Fs, phi, e, arm, q);
     if (rc) return rc;
-    RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, st));
+    if (gamma_tape && np > 0)
+        RL_HIP(hipMemcpyAsync(gamma, gamma_tape, sizeof(double) * np, hipMemcpyDeviceToDevice, st));
+    else
+        RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, st));
     SolveArgs a;
     rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a);
     if (rc) return rc;

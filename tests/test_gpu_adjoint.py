@@ -158,16 +158,16 @@ def test_step_adjoint_is_bitwise_repeatable(gpu_lib):
         assert np.array_equal(a, b)
 
 
-def _gpu_rollout_grad(rl, s, F, k):
+def _gpu_rollout_grad(rl, s, F, k, tape=True):
     from paper_2109_08206_amd.rollout import rollout
     with _solver(rl, s) as slv:
         x0 = _t(s.x).requires_grad_(True)
         q0 = _t(s.quat).requires_grad_(True)
         Ft = _t(F).requires_grad_(True)
-        xu, _ = rollout(slv, x0, q0, _glen(s), Ft, checkpoint_every=k, cg_tol=1e-12)
+        xu, _ = rollout(slv, x0, q0, _glen(s), Ft, checkpoint_every=k, cg_tol=1e-12, tape=tape)
         loss = (xu * xu).sum()
         loss.backward()
-        return float(loss), x0.grad.cpu().numpy(), q0.grad.cpu().numpy(), Ft.grad.cpu().numpy()
+        return float(loss.detach()), x0.grad.cpu().numpy(), q0.grad.cpu().numpy(), Ft.grad.cpu().numpy()
 
 
 def test_rollout_matches_oracle(gpu_lib):
@@ -186,13 +186,103 @@ def test_rollout_matches_oracle(gpu_lib):
 
 def test_checkpointing_is_bitwise(gpu_lib):
     """Recomputed segments reproduce the forward states exactly, so the
-    gradient does not depend on the checkpoint interval."""
+    gradient does not depend on the checkpoint interval; replaying the
+    recorded constraint forces gives bitwise the result of cold solves."""
     s = SYSTEMS["rods200"]()
     rng = np.random.default_rng(12)
     F = np.stack([rng.standard_normal(s.force.shape) for _ in range(5)])
-    ref = _gpu_rollout_grad(gpu_lib, s, F, 1)
-    for k in (2, 5):
-        got = _gpu_rollout_grad(gpu_lib, s, F, k)
+    ref = _gpu_rollout_grad(gpu_lib, s, F, 1, tape=False)
+    for k, tape in ((2, False), (5, False), (1, True), (2, True), (5, True)):
+        got = _gpu_rollout_grad(gpu_lib, s, F, k, tape=tape)
         assert got[0] == ref[0]
         for a, b in zip(got[1:], ref[1:]):
             assert np.array_equal(a, b)
+
+
+def test_fullsize_step_adjoint_directional_derivatives(gpu_lib):
+    """50,000 rods at volume fraction 0.05 (the rollout workload), beyond the
+    oracle's reach.  Directional derivatives of L = w . h U_t along random
+    force and centre directions: central differences of the GPU forward
+    (residual 1e-10) against rl_step_adjoint.
+
+    The step is only piecewise smooth, and the checks are set for that.
+      * Active-set changes are kinks, so the test asserts that none happens
+        at the eps used (5 of the 122k active constraints have gamma < 1e-4).
+      * Forces: the geometry is fixed, so central differences are exact to
+        O(eps^2).  Bar 1e-6 relative; measured 3e-8.
+      * Centres: closest points are also only piecewise smooth.  An
+        arclength reaching a rod end is a kink, and for near-parallel pairs
+        ds/dx grows like 1/(1 - b^2), so even eps = 3e-8 crosses a few.  The
+        central difference then deviates at the 1e-5 level, and it stays
+        the same whether the forward residual is 1e-10 or 1e-11.  Bar 1e-4
+        relative; measured 1.5e-5.  A dropped term or a wrong sign is off
+        by O(1)."""
+    s = rodsynth.cfg_rollout(0)
+    rng = np.random.default_rng(13)
+    w = _t(rng.standard_normal((s.n, 3)))
+    vF = _t(rng.standard_normal((s.n, 6)))
+    vx = _t(rng.standard_normal((s.n, 3)))
+    x, quat, F = _t(s.x), _t(s.quat), _t(s.force)
+    box = s.box
+    with _solver(gpu_lib, s, max_iter=1_000_000) as slv:
+        d = slv.directors(quat)
+
+        def forward(Fv, xv):
+            xx = torch.remainder(xv, box).contiguous()
+            xx[xx >= box] -= box
+            pi, pj, img, _ = slv.build_pairs(xx, d, 1.0)
+            phi, e, arm, q = slv.assemble_D(xx, d, 1.0, pi, pj, img, Fv)
+            g, U, info = slv.solve_lcp(d, 1.0, pi, pj, e, arm, q, F=Fv)
+            assert info.status == 0
+            m = g > slv.apply_M(d, 1.0, pi, pj, e, arm, q, g)
+            key = pi.long() * (1 << 40) + pj.long() * (1 << 12) + img.long()
+            return float((w * (s.dt * U[:, :3])).sum()), torch.sort(key[m]).values
+
+        _, act0 = forward(F, x)
+        x_bar, q_bar = w.clone(), torch.zeros((s.n, 4), dtype=torch.float64, device=DEV)
+        F_bar, ai = slv.step_adjoint(x, quat, 1.0, F, x_bar, q_bar, cg_tol=1e-12)
+        print(f"50k: active {ai.n_active}, CG {ai.cg_iterations} it (res {ai.cg_residual:.1e}), "
+              f"forward {ai.solve_iterations} it", flush=True)
+        assert ai.status == 0 and ai.n_active == act0.numel()
+        # the x term of x' = x + h U_t contributes w . v exactly; compare the U part
+        an_x = float((x_bar * vx).sum()) - float((w * vx).sum())
+        for name, eps, an, bar, vf, vxx in (("F", 1e-5, float((F_bar * vF).sum()), 1e-6, vF, None),
+                                            ("x", 3e-8, an_x, 1e-4, None, vx)):
+            lp, ap = forward(F + eps * vf if vf is not None else F, x + eps * vxx if vxx is not None else x)
+            lm, am = forward(F - eps * vf if vf is not None else F, x - eps * vxx if vxx is not None else x)
+            assert torch.equal(ap, act0) and torch.equal(am, act0), "active set changed: eps too large"
+            fd = (lp - lm) / (2 * eps)
+            print(f"  {name}: adjoint {an:.10e}  central difference {fd:.10e}  rel {abs(fd - an) / abs(an):.2e}",
+                  flush=True)
+            assert abs(fd - an) <= bar * abs(an)
+
+
+def test_tape_replay_and_errors(gpu_lib):
+    """A recorded tape replayed on the same state stops at once with the same
+    solution and the same velocities; a tape of the wrong length is an
+    argument error; a short record buffer is a capacity error that leaves
+    the state unchanged."""
+    s = SYSTEMS["rods200"]()
+    with _solver(gpu_lib, s) as slv:
+        x, q = _t(s.x), _t(s.quat)
+        U0, i0, tape = slv.step_recording(x.clone(), q.clone(), 1.0, F=_t(s.force))
+        assert i0.iterations > 10
+        x1, q1 = x.clone(), q.clone()
+        g = tape.clone()
+        U1, i1, n1 = slv.step(x1, q1, 1.0, F=_t(s.force), tape=g, tape_mode=gpu_lib.TAPE_REPLAY)
+        assert i1.iterations == 0 and n1 == tape.shape[0]
+        assert torch.equal(U1, U0) and torch.equal(g, tape)
+        with pytest.raises(gpu_lib.RodLCPError) as ei:
+            slv.step(x.clone(), q.clone(), 1.0, F=_t(s.force), tape=tape[:-1].clone(),
+                     tape_mode=gpu_lib.TAPE_REPLAY)
+        assert ei.value.status == gpu_lib.ERR_ARG
+        xs, qs = x.clone(), q.clone()
+        with pytest.raises(gpu_lib.RodLCPError) as ei:
+            slv.step(xs, qs, 1.0, F=_t(s.force), tape=torch.empty(3, dtype=torch.float64, device=DEV),
+                     tape_mode=gpu_lib.TAPE_RECORD)
+        assert ei.value.status == gpu_lib.ERR_CAPACITY and ei.value.count == tape.shape[0]
+        assert torch.equal(xs, x) and torch.equal(qs, q)
+        with pytest.raises(gpu_lib.RodLCPError) as ei:
+            slv.step_adjoint(x, q, 1.0, _t(s.force), torch.zeros_like(x), torch.zeros_like(q),
+                             tape=tape[:-1].clone())
+        assert ei.value.status == gpu_lib.ERR_ARG
