@@ -57,8 +57,15 @@ struct Mob {
 // Host-side view of the mobility constants of a uniform-length system.
 Mob mobility_host(double L, double diam, double eta);
 
-constexpr int kRodBlock = 1024;  // rod kernel: 4 lanes per rod, 256 rods per workgroup
-constexpr int kRodLanes = 4;
+// rod kernel: kRodLanes lanes per rod, kRodBlock / kRodLanes rods per workgroup
+#ifndef RL_ROD_BLOCK
+#define RL_ROD_BLOCK 1024
+#endif
+#ifndef RL_ROD_LANES
+#define RL_ROD_LANES 4
+#endif
+constexpr int kRodBlock = RL_ROD_BLOCK;
+constexpr int kRodLanes = RL_ROD_LANES;
 constexpr int kConBlock = 512;   // constraint kernel workgroup
 constexpr int kConGridMax = 512; // constraint kernel grid cap (grid-stride beyond)
 
