@@ -112,9 +112,9 @@ __global__ void __launch_bounds__(kConBlock) k_cg_start(CgArgs g, const double *
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
     for (int64_t c = lo + threadIdx.x; c < hi; c += kConBlock) {
         const int2 ij = a.pp[c];
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
+        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * c);
         const double m = a.st[c].x > wsol[c] ? 1.0 : 0.0;
-        const double b = m > 0.0 ? con_rate(a, c, ij, gd[0], gd[1], gd[2]) : 0.0;
+        const double b = m > 0.0 ? con_rate(a, c, ij, gd[0], gd[1], a.geo2[c]) : 0.0;
         double2 *cs = reinterpret_cast<double2 *>(g.cs + 4 * c);
         double2 *cr = reinterpret_cast<double2 *>(g.cr + 4 * c);
         double2 *cq = reinterpret_cast<double2 *>(g.cq + 4 * (int64_t)a.qpos[c]);
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(kRodBlock) k_cg_rod(CgArgs g, long long k)
         const int pe = a.pptr[r + 1];
         for (int c = a.pptr[r] + sub; c < pe; c += kRodLanes) {
             const double2 *cr = reinterpret_cast<const double2 *>(g.cr + 4 * (int64_t)c);
-            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)c);
+            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)c);
             const double2 rs = cr[0], w0 = cr[1], g0 = gd[0], g1 = gd[1];
             const double v = cg_next_r(rs.x, rs.y, w0.x, alpha, beta), vs = v * g1.y;
             fm[0] += v * g0.x;
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
     for (int64_t c = lo + threadIdx.x; c < hi; c += kConBlock) {
         const int2 ij = a.pp[c];
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
+        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * c);
         double2 *cs = reinterpret_cast<double2 *>(g.cs + 4 * c);
         double2 *cr = reinterpret_cast<double2 *>(g.cr + 4 * c);
         const double2 lp = cs[0], mk = cs[1], rs = cr[0], w0 = cr[1];
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
             sv = s1;
             pv = p1;
         }
-        const double w = mk.x > 0.0 ? con_rate(a, c, ij, gd[0], gd[1], gd[2]) : 0.0;
+        const double w = mk.x > 0.0 ? con_rate(a, c, ij, gd[0], gd[1], a.geo2[c]) : 0.0;
         cs[0] = make_double2(lam, pv);
         cr[0] = make_double2(rv, sv);
         cr[1] = make_double2(w, 0.0);
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(kRodBlock) k_adj_rod(CgArgs g, const double *_
     if (active) {
         const int pe = a.pptr[r + 1];
         for (int c = a.pptr[r] + sub; c < pe; c += kRodLanes) {
-            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)c);
+            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)c);
             const double2 g0 = gd[0], g1 = gd[1];
             const double gm = a.st[c].x, lm = g.cs[4 * (int64_t)c];
             const double e3[3] = {g0.x, g0.y, g1.x};
@@ -383,8 +383,8 @@ __global__ void k_adj_con(CgArgs g, const double *__restrict__ PQ, double *__res
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= a.nc) return;
     const int2 ij = a.pp[c];
-    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
-    const double2 g0 = gd[0], g1 = gd[1], g2 = gd[2];
+    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * c);
+    const double2 g0 = gd[0], g1 = gd[1], g2 = a.geo2[c];
     const V3 e = v3(g0.x, g0.y, g1.x);
     const double si = g1.y, sj = g2.x;
     const double lam = g.cs[4 * c], gam = g.cs[4 * c + 2] > 0.0 ? a.st[c].x : 0.0;

@@ -232,7 +232,7 @@ int rl_reserve(rl_handle h, int64_t max_rods, int64_t max_pairs)
         {kWsStepImg, sizeof(int) * nc},    {kWsStepFlags, (size_t)nc},                 {kWsStepPhi, sizeof(double) * nc},
         {kWsStepE, sizeof(double) * 3 * nc}, {kWsStepArm, sizeof(double) * 2 * nc},
         {kWsStepQ, sizeof(double) * nc},   {kWsStepGamma, sizeof(double) * nc}, {kWsStepU, sizeof(double) * 6 * n},
-        {kWsPP, sizeof(int) * 2 * nc},     {kWsGeo, sizeof(double) * 6 * nc},  {kWsSt, sizeof(double) * 2 * nc},
+        {kWsPP, sizeof(int) * 2 * nc},     {kWsGeo, sizeof(double) * 4 * nc}, {kWsGeo2, sizeof(double) * 2 * nc},  {kWsSt, sizeof(double) * 2 * nc},
         {kWsAlpha, sizeof(double) * 2},    {kWsQpos, sizeof(int) * nc},        {kWsQgeo, sizeof(double) * 4 * nc},
         {kWsStq, sizeof(double) * 2 * nc},
     };

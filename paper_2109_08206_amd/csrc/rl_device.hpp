@@ -158,7 +158,7 @@ __device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool act
     const double2 z = make_double2(0.0, 0.0);
     L.ps = L.pg0 = L.pg1 = L.qs = L.qg0 = L.qg1 = z;
     if (L.pb < L.pe) {
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)L.pb);
+        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)L.pb);
         L.ps = a.st[L.pb];
         L.pg0 = gd[0];
         L.pg1 = gd[1];
@@ -187,7 +187,7 @@ __device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoad
         m[2] += gs * L.pg1.x;
         for (int c = L.pb + kRodLanes; c < L.pe; c += kRodLanes) {
             const double2 sg = a.st[c];
-            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * (int64_t)c);
+            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)c);
             const double2 g0 = gd[0], g1 = gd[1];
             const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
             const double gsc = gmc * g1.y;
@@ -258,10 +258,10 @@ template <int MODE>
 __device__ __forceinline__ void con_load(const SolveArgs &a, int64_t c, ConLoads &L)
 {
     const int2 ij = a.pp[c];
-    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 6 * c);
+    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * c);
     L.g0 = gd[0];
     L.g1 = gd[1];
-    L.g2 = gd[2];
+    L.g2 = a.geo2[c];
     if (MODE != kModeApply) L.sg = a.st[c];
     if (MODE == kModeInit || MODE == kModeLoop || MODE == kModeRefresh) L.qp = a.qpos[c];
     const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);

@@ -66,8 +66,18 @@ Mob mobility_host(double L, double diam, double eta);
 #endif
 constexpr int kRodBlock = RL_ROD_BLOCK;
 constexpr int kRodLanes = RL_ROD_LANES;
-constexpr int kConBlock = 512;   // constraint kernel workgroup
-constexpr int kConGridMax = 512; // constraint kernel grid cap (grid-stride beyond)
+#ifndef RL_CON_BLOCK
+#define RL_CON_BLOCK 512
+#endif
+#ifndef RL_CON_GRIDMAX
+#define RL_CON_GRIDMAX 512
+#endif
+#ifndef RL_CON_CPL
+#define RL_CON_CPL 2
+#endif
+constexpr int kConBlock = RL_CON_BLOCK;     // constraint kernel workgroup
+constexpr int kConGridMax = RL_CON_GRIDMAX; // constraint kernel grid cap (grid-stride beyond)
+constexpr int kConCpl = RL_CON_CPL;         // constraints per lane per round, loaded together
 
 // Arguments shared by the solver kernels (passed by value).
 struct SolveArgs {
@@ -80,7 +90,8 @@ struct SolveArgs {
     const int32_t *qptr;    // [n+1] Q-side incidence offsets
     const int32_t *qidx;    // [nc] constraints with pj == r, ascending
     const int32_t *qpos;    // [nc] position of constraint c in the Q-side list
-    const double *geo;      // [nc][6] (ex, ey, ez, s_i, s_j, q)
+    const double *geo;      // [nc][4] (ex, ey, ez, s_i): what the rod kernel reads
+    const double2 *geo2;    // [nc] (s_j, q): the rest of the constraint record
     const double *qgeo;     // [nc][4] Q-side list order: (ex, ey, ez, s_j)
     double2 *st;            // [nc] (gamma, g) of the current iterate
     double2 *stq;           // [nc] the same in Q-side list order
@@ -153,7 +164,7 @@ enum Slot : int {
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
     kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
-    kWsBatchPartial2, kWsBatchDone, kWsBatchMap,
+    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots

@@ -32,14 +32,15 @@ static inline unsigned rod_grid32(int64_t n) { return (grid_of(n, kRodBlock / kR
 constexpr long long kInnerRoundCap = 4000;  // inner iterations before a forced refresh
 
 // single-precision geometry records from the FP64 ones
-__global__ void k_pack32(int64_t nc, const double *__restrict__ geo, const double *__restrict__ qgeo,
-                         float4 *__restrict__ geo32, float *__restrict__ sj32, float4 *__restrict__ qgeo32)
+__global__ void k_pack32(int64_t nc, const double *__restrict__ geo, const double2 *__restrict__ geo2,
+                         const double *__restrict__ qgeo, float4 *__restrict__ geo32, float *__restrict__ sj32,
+                         float4 *__restrict__ qgeo32)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nc) return;
-    const double *g = geo + 6 * c;
+    const double *g = geo + 4 * c;
     geo32[c] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
-    sj32[c] = (float)g[4];
+    sj32[c] = (float)geo2[c].x;
     const double *qg = qgeo + 4 * c;  // list order, same length
     qgeo32[c] = make_float4((float)qg[0], (float)qg[1], (float)qg[2], (float)qg[3]);
 }
@@ -271,7 +272,7 @@ int prepare_mixed(rl_ctx *h, SolveArgs &a)
     a.sj32 = sj32;
     a.qgeo32 = qgeo32;
     if (a.nc > 0) {
-        hipLaunchKernelGGL(k_pack32, dim3(grid_of(a.nc, kBlock)), dim3(kBlock), 0, h->stream, a.nc, a.geo, a.qgeo,
+        hipLaunchKernelGGL(k_pack32, dim3(grid_of(a.nc, kBlock)), dim3(kBlock), 0, h->stream, a.nc, a.geo, a.geo2, a.qgeo,
                            geo32, sj32, qgeo32);
         RL_HIP(hipGetLastError());
     }

@@ -109,37 +109,37 @@ __global__ void k_qsort(int64_t n, const int32_t *__restrict__ qptr, int32_t *__
     }
 }
 
-// constraint records: (pi, pj), (ex, ey, ez, s_i, s_j, q), (gamma, g = 0)
+// constraint records: (pi, pj), (ex, ey, ez, s_i) and (s_j, q), (gamma, g = 0)
 __global__ void k_pack(int64_t nc, const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
                        const double *__restrict__ e, const double *__restrict__ arm, const double *__restrict__ q,
                        const double *__restrict__ gamma, int2 *__restrict__ pp, double *__restrict__ geo,
-                       double2 *__restrict__ st)
+                       double2 *__restrict__ geo2, double2 *__restrict__ st)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nc) return;
     pp[c] = make_int2(pi[c], pj[c]);
-    double2 *gd = reinterpret_cast<double2 *>(geo + 6 * c);
+    double2 *gd = reinterpret_cast<double2 *>(geo + 4 * c);
     gd[0] = make_double2(e[3 * c], e[3 * c + 1]);
     gd[1] = make_double2(e[3 * c + 2], arm[2 * c]);
-    gd[2] = make_double2(arm[2 * c + 1], q ? q[c] : 0.0);
+    geo2[c] = make_double2(arm[2 * c + 1], q ? q[c] : 0.0);
     st[c] = make_double2(gamma[c], 0.0);
 }
 
 // Q-side copies: qpos (inverse of qidx), the geometry a rod needs on its Q
 // side in list order, and the start iterate in list order
 __global__ void k_pack_q(int64_t nc, const int32_t *__restrict__ qidx, const double *__restrict__ geo,
-                         const double2 *__restrict__ st, int32_t *__restrict__ qpos, double *__restrict__ qgeo,
-                         double2 *__restrict__ stq)
+                         const double2 *__restrict__ geo2, const double2 *__restrict__ st, int32_t *__restrict__ qpos,
+                         double *__restrict__ qgeo, double2 *__restrict__ stq)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= nc) return;
     const int c = qidx[k];
     qpos[c] = (int32_t)k;
-    const double2 *gd = reinterpret_cast<const double2 *>(geo + 6 * (int64_t)c);
-    const double2 g0 = gd[0], g1 = gd[1], g2 = gd[2];
+    const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
+    const double2 g0 = gd[0], g1 = gd[1];
     double2 *qd = reinterpret_cast<double2 *>(qgeo + 4 * k);
     qd[0] = g0;
-    qd[1] = make_double2(g1.x, g2.x);
+    qd[1] = make_double2(g1.x, geo2[c].x);
     stq[k] = st[c];
 }
 
@@ -224,13 +224,14 @@ __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
     // each workgroup takes a contiguous chunk of constraints, two per lane per round
     const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
-    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += 2 * kConBlock) {
-        const int64_t c1 = c0 + kConBlock;
-        ConLoads A, B;
-        con_load<MODE>(a, c0, A);
-        if (c1 < hi) con_load<MODE>(a, c1, B);
-        con_update<MODE>(a, c0, A, alpha, p);
-        if (c1 < hi) con_update<MODE>(a, c1, B, alpha, p);
+    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += kConCpl * kConBlock) {
+        ConLoads L[kConCpl];
+#pragma unroll
+        for (int u = 0; u < kConCpl; ++u)
+            if (c0 + u * kConBlock < hi) con_load<MODE>(a, c0 + u * kConBlock, L[u]);
+#pragma unroll
+        for (int u = 0; u < kConCpl; ++u)
+            if (c0 + u * kConBlock < hi) con_update<MODE>(a, c0 + u * kConBlock, L[u], alpha, p);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<kConBlock / 64>(p, lds);
@@ -416,7 +417,7 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     s.dir = dir;
     s.mob = mobility_host(len ? 1.0 : len0, p.diam, p.eta);
     // constraint workgroups: about two constraints per lane, at most kConGridMax, a multiple of 8 (XCDs)
-    int64_t gc = std::min<int64_t>(std::max<int64_t>(grid_of(nc, 2 * kConBlock), 1), kConGridMax);
+    int64_t gc = std::min<int64_t>(std::max<int64_t>(grid_of(nc, kConCpl * kConBlock), 1), kConGridMax);
     s.gcon = (int)((gc + 7) / 8 * 8);
     const int64_t nb = nc > 0 ? nc : 1, rb = n > 0 ? n : 1;
     int32_t *pptr = (int32_t *)ws_get(h, kWsPptr, sizeof(int32_t) * (n + 1), &werr);
@@ -424,7 +425,8 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     int32_t *qidx = (int32_t *)ws_get(h, kWsQidx, sizeof(int32_t) * nb, &werr);
     int *qcnt = (int *)ws_get(h, kWsQcnt, sizeof(int) * rb, &werr);
     int2 *pp = (int2 *)ws_get(h, kWsPP, sizeof(int2) * nb, &werr);
-    double *geo = (double *)ws_get(h, kWsGeo, sizeof(double) * 6 * nb, &werr);
+    double *geo = (double *)ws_get(h, kWsGeo, sizeof(double) * 4 * nb, &werr);
+    double2 *geo2 = (double2 *)ws_get(h, kWsGeo2, sizeof(double2) * nb, &werr);
     s.st = (double2 *)ws_get(h, kWsSt, sizeof(double2) * nb, &werr);
     s.stq = (double2 *)ws_get(h, kWsStq, sizeof(double2) * nb, &werr);
     int32_t *qpos = (int32_t *)ws_get(h, kWsQpos, sizeof(int32_t) * nb, &werr);
@@ -440,6 +442,7 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     s.qidx = qidx;
     s.pp = pp;
     s.geo = geo;
+    s.geo2 = geo2;
     s.qpos = qpos;
     s.qgeo = qgeo;
     s.state = h->state;
@@ -472,10 +475,10 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     }
     if (nc > 0) {
         hipLaunchKernelGGL(k_pack, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pi, pj, e, arm, q,
-                           (const double *)gamma, pp, geo, s.st);
+                           (const double *)gamma, pp, geo, geo2, s.st);
         RL_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_pack_q, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, (const int32_t *)qidx,
-                           (const double *)geo, (const double2 *)s.st, qpos, qgeo, s.stq);
+                           (const double *)geo, (const double2 *)geo2, (const double2 *)s.st, qpos, qgeo, s.stq);
         RL_HIP(hipGetLastError());
     }
     *out = s;
