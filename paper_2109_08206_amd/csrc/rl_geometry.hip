@@ -284,63 +284,133 @@ __device__ __forceinline__ bool lex_positive(int a, int b, int c)
 // One lane per rod (in cell order t).  INTERNAL: rods are numbered by their
 // cell-order slot; otherwise by the caller's index sorted[t].  A pair is
 // listed by its smaller rod number (self-images: positive shifts only).
-template <bool FILL, bool INTERNAL>
-__global__ void k_pairs(int64_t n, GridDev g, double diam, double cutoff, const int *__restrict__ sorted,
-                        const double *__restrict__ xs, const double *__restrict__ ds, const double *__restrict__ ls,
-                        const int *__restrict__ cell_start, int *__restrict__ pcnt, const int *__restrict__ poff,
-                        int32_t *__restrict__ pi, int32_t *__restrict__ pj, int32_t *__restrict__ img,
-                        uint8_t *__restrict__ flags)
+// Pair search, one workgroup per home cell.  The home cell's rods and then,
+// one stencil cell at a time, the neighbour cell's rods (shifted by the
+// periodic image) are staged in LDS; every (home, neighbour) combination is
+// tested from LDS in parallel with the cheap necessary conditions (centre
+// distance within reach; axis lines closer than the threshold).  Survivors
+// go to an LDS queue and get the exact closest-point test together, on full
+// waves.  Counting pass: per-rod counts.  Filling pass: each pair takes the
+// next slot of its rod (LDS atomic); the order within a rod is then fixed by
+// the per-rod sort that follows.
+constexpr int kPairBlock = 256;
+constexpr int kCellChunk = 256;  // rods of one cell staged at a time
+constexpr int kQueue = 4096;     // candidate (home, neighbour) pairs per flush
+
+struct CellStage {
+    double p[7][kCellChunk];  // x, y, z, dx, dy, dz, length
+    int idx[kCellChunk];      // rod index (the caller's or the cell order's)
+};
+
+template <bool INTERNAL>
+__device__ __forceinline__ void stage_cell(CellStage &S, int q0, int m, V3 shift, const int *sorted,
+                                           const double *xs, const double *ds, const double *ls)
 {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int i = INTERNAL ? (int)t : sorted[t];
-    const V3 xi = load3(xs + 3 * t), di = load3(ds + 3 * t);
-    const double Li = ls[t];
-    const int kx = cell_coord(xi.x, g.cell[0], g.nc[0]);
-    const int ky = cell_coord(xi.y, g.cell[1], g.nc[1]);
-    const int kz = cell_coord(xi.z, g.cell[2], g.nc[2]);
-    int cnt = 0;
-    const int base = FILL ? poff[i] : 0;
-    for (int ox = -g.S[0]; ox <= g.S[0]; ++ox) {
-        const int ux = kx + ox;
-        const int wx = ((ux % g.nc[0]) + g.nc[0]) % g.nc[0];
-        const int sx = (ux - wx) / g.nc[0];
-        for (int oy = -g.S[1]; oy <= g.S[1]; ++oy) {
-            const int uy = ky + oy;
+    for (int u = threadIdx.x; u < m; u += kPairBlock) {
+        const int64_t q = q0 + u;
+        S.p[0][u] = xs[3 * q] + shift.x;
+        S.p[1][u] = xs[3 * q + 1] + shift.y;
+        S.p[2][u] = xs[3 * q + 2] + shift.z;
+        S.p[3][u] = ds[3 * q];
+        S.p[4][u] = ds[3 * q + 1];
+        S.p[5][u] = ds[3 * q + 2];
+        S.p[6][u] = ls[q];
+        S.idx[u] = INTERNAL ? (int)q : sorted[q];
+    }
+}
+
+template <bool FILL, bool INTERNAL>
+__global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, double cutoff,
+                                                      const int *__restrict__ sorted, const double *__restrict__ xs,
+                                                      const double *__restrict__ ds, const double *__restrict__ ls,
+                                                      const int *__restrict__ cell_start, int *__restrict__ pcnt,
+                                                      const int *__restrict__ poff, int32_t *__restrict__ pi,
+                                                      int32_t *__restrict__ pj, int32_t *__restrict__ img,
+                                                      uint8_t *__restrict__ flags)
+{
+    __shared__ CellStage H, Nb;
+    __shared__ int hcnt[kCellChunk], hoff[kCellChunk];
+    __shared__ int queue[kQueue];
+    __shared__ int qn;
+    const int h = blockIdx.x;
+    const int hz = h % g.nc[2], hy = (h / g.nc[2]) % g.nc[1], hx = h / (g.nc[2] * g.nc[1]);
+    const int hb = cell_start[h], he = cell_start[h + 1];
+    const double gap = diam + cutoff + 1e-9, gap2 = gap * gap;
+    const int NY = 2 * g.S[1] + 1, NZ = 2 * g.S[2] + 1, NS = (2 * g.S[0] + 1) * NY * NZ;
+    for (int a0 = hb; a0 < he; a0 += kCellChunk) {
+        const int na = he - a0 < kCellChunk ? he - a0 : kCellChunk;
+        stage_cell<INTERNAL>(H, a0, na, v3(0.0, 0.0, 0.0), sorted, xs, ds, ls);
+        for (int u = threadIdx.x; u < na; u += kPairBlock) {
+            hcnt[u] = 0;
+            if (FILL) hoff[u] = poff[INTERNAL ? a0 + u : sorted[a0 + u]];
+        }
+        __syncthreads();
+        for (int sc = 0; sc < NS; ++sc) {
+            const int ux = hx + sc / (NY * NZ) - g.S[0];
+            const int uy = hy + (sc / NZ) % NY - g.S[1];
+            const int uz = hz + sc % NZ - g.S[2];
+            const int wx = ((ux % g.nc[0]) + g.nc[0]) % g.nc[0];
             const int wy = ((uy % g.nc[1]) + g.nc[1]) % g.nc[1];
-            const int sy = (uy - wy) / g.nc[1];
-            for (int oz = -g.S[2]; oz <= g.S[2]; ++oz) {
-                const int uz = kz + oz;
-                const int wz = ((uz % g.nc[2]) + g.nc[2]) % g.nc[2];
-                const int sz = (uz - wz) / g.nc[2];
-                const bool selfok = lex_positive(sx, sy, sz);
-                const V3 shift = v3(sx * g.box[0], sy * g.box[1], sz * g.box[2]);
-                const int w = (wx * g.nc[1] + wy) * g.nc[2] + wz;
-                const int qb = cell_start[w], qe = cell_start[w + 1];
-                for (int q = qb; q < qe; ++q) {
-                    const int j = INTERNAL ? q : sorted[q];
-                    if (j < i || (j == i && !selfok)) continue;
-                    const V3 xj = load3(xs + 3 * (int64_t)q) + shift;
-                    const V3 r0 = xi - xj;
-                    const double Lj = ls[q];
-                    const double reach = 0.5 * (Li + Lj) + diam + cutoff;
-                    if (dot(r0, r0) >= reach * reach) continue;
-                    const Contact c = closest_point(xi, di, 0.5 * Li, xj, load3(ds + 3 * (int64_t)q), 0.5 * Lj);
-                    const double phi = c.dist - diam;
-                    if (!(phi < cutoff)) continue;
-                    if (FILL) {
-                        const int o = base + cnt;
-                        pi[o] = i;
-                        pj[o] = j;
-                        img[o] = ((sx + 8) << 8) | ((sy + 8) << 4) | (sz + 8);
-                        flags[o] = (uint8_t)(c.flags | (fabs(phi - cutoff) <= kCutoffBand ? 1u : 0u));
+            const int wz = ((uz % g.nc[2]) + g.nc[2]) % g.nc[2];
+            const int sx = (ux - wx) / g.nc[0], sy = (uy - wy) / g.nc[1], sz = (uz - wz) / g.nc[2];
+            const bool selfok = lex_positive(sx, sy, sz);
+            const int packed = ((sx + 8) << 8) | ((sy + 8) << 4) | (sz + 8);
+            const V3 shift = v3(sx * g.box[0], sy * g.box[1], sz * g.box[2]);
+            const int w = (wx * g.nc[1] + wy) * g.nc[2] + wz;
+            const int nb = cell_start[w], ne = cell_start[w + 1];
+            for (int b0 = nb; b0 < ne; b0 += kCellChunk) {
+                const int nn = ne - b0 < kCellChunk ? ne - b0 : kCellChunk;
+                // rods in cell order: a neighbour chunk entirely below the home
+                // chunk holds no j >= i
+                if (INTERNAL && b0 + nn <= a0) continue;
+                __syncthreads();
+                stage_cell<INTERNAL>(Nb, b0, nn, shift, sorted, xs, ds, ls);
+                __syncthreads();
+                const int total = na * nn;
+                for (int base = 0; base < total; base += kQueue) {
+                    if (threadIdx.x == 0) qn = 0;
+                    __syncthreads();
+                    const int lim = total - base < kQueue ? total - base : kQueue;
+                    for (int e = threadIdx.x; e < lim; e += kPairBlock) {
+                        const int a = (base + e) / nn, b = (base + e) % nn;
+                        const int i = H.idx[a], j = Nb.idx[b];
+                        if (j < i || (j == i && !selfok)) continue;
+                        const V3 r0 = v3(H.p[0][a] - Nb.p[0][b], H.p[1][a] - Nb.p[1][b], H.p[2][a] - Nb.p[2][b]);
+                        const double reach = 0.5 * (H.p[6][a] + Nb.p[6][b]) + diam + cutoff;
+                        if (dot(r0, r0) >= reach * reach) continue;
+                        // two segments are never closer than their axis lines (margin
+                        // far above rounding; near-parallel lines go through)
+                        const V3 nrm = cross(v3(H.p[3][a], H.p[4][a], H.p[5][a]), v3(Nb.p[3][b], Nb.p[4][b], Nb.p[5][b]));
+                        const double nn2 = dot(nrm, nrm), rn = dot(r0, nrm);
+                        if (nn2 > 1e-6 && rn * rn > gap2 * nn2) continue;
+                        queue[atomicAdd(&qn, 1)] = (a << 16) | b;
                     }
-                    ++cnt;
+                    __syncthreads();
+                    const int nq = qn;
+                    for (int u = threadIdx.x; u < nq; u += kPairBlock) {
+                        const int a = queue[u] >> 16, b = queue[u] & 0xffff;
+                        const V3 xi = v3(H.p[0][a], H.p[1][a], H.p[2][a]), di = v3(H.p[3][a], H.p[4][a], H.p[5][a]);
+                        const V3 xj = v3(Nb.p[0][b], Nb.p[1][b], Nb.p[2][b]), dj = v3(Nb.p[3][b], Nb.p[4][b], Nb.p[5][b]);
+                        const Contact c = closest_point(xi, di, 0.5 * H.p[6][a], xj, dj, 0.5 * Nb.p[6][b]);
+                        const double phi = c.dist - diam;
+                        if (!(phi < cutoff)) continue;
+                        const int slot = atomicAdd(&hcnt[a], 1);
+                        if (FILL) {
+                            const int o = hoff[a] + slot;
+                            pi[o] = H.idx[a];
+                            pj[o] = Nb.idx[b];
+                            img[o] = packed;
+                            flags[o] = (uint8_t)(c.flags | (fabs(phi - cutoff) <= kCutoffBand ? 1u : 0u));
+                        }
+                    }
+                    __syncthreads();
                 }
             }
         }
+        if (!FILL)
+            for (int u = threadIdx.x; u < na; u += kPairBlock) pcnt[H.idx[u]] = hcnt[u];
+        __syncthreads();
     }
-    if (!FILL) pcnt[i] = cnt;
 }
 
 // copies of centres, directors, lengths (and forces) in cell order
@@ -500,13 +570,9 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     }
     RL_HIP(hipGetLastError());
     if (internal)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, true>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g, p.diam,
-                           p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
-                           (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, true>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, false>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g,
-                           p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr,
-                           (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, false>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
     RL_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pcnt, n, poff, tot);
     RL_HIP(hipGetLastError());
@@ -534,12 +600,9 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     }
     if (total == 0) return RL_OK;
     if (internal)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, true>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g, p.diam,
-                           p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, true>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, false>), dim3(grid_of(n)), dim3(kBlock), 0, st, n, g,
-                           p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img,
-                           flags);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, false>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags);
     RL_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sort_pairs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)poff, pj, img, flags);
     RL_HIP(hipGetLastError());

@@ -164,7 +164,7 @@ enum Slot : int {
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
     kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
-    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2,
+    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
