@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "BBPGD iters/sec and LCP solves/sec at 100k rods; HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bbpgd_rods100k.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f) for f in ("rl_solver.hip",)]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f)
+                  for f in ("rl_solver.hip", "rl_device.hpp", "rl_internal.hpp")]
 
 
 def kernel_bytes(n: int, nc: int) -> dict:

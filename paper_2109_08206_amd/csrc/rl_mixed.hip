@@ -314,7 +314,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
             if (samp) {
                 // dispatch-stamped events around both kernels of this iteration
                 for (int e = 0; e < 4; ++e)
-                    if (!h->ev[nev][e]) RL_HIP(hipEventCreate(&h->ev[nev][e]));
+                    if (!h->ev[nev][e]) RL_HIP(hipEventCreateWithFlags(&h->ev[nev][e], hipEventDisableSystemFence));
                 h->ev_iter[nev] = k;
                 if (uni)
                     hipExtLaunchKernelGGL(k_rod32<true>, rgrid, dim3(kRodBlock), 0, st, h->ev[nev][0],

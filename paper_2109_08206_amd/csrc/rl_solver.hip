@@ -523,7 +523,7 @@ static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs 
     hipStream_t st = h->stream;
     for (int k = 0; k < 4; ++k)
         if (!h->ev[v][k]) {
-            hipError_t e = hipEventCreate(&h->ev[v][k]);
+            hipError_t e = hipEventCreateWithFlags(&h->ev[v][k], hipEventDisableSystemFence);
             if (e != hipSuccess) return e;
         }
     h->ev_iter[v] = it;
