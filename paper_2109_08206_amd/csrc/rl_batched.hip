@@ -79,15 +79,16 @@ __global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
     __shared__ double lds[RB / 64 + 1][4];
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     if ((int)tile >= b.nrb) return;
+    const int sub = threadIdx.x & (kRodLanes - 1);
+    const int64_t r = (int64_t)b.rblk_lo[tile] + threadIdx.x / kRodLanes;
+    const bool active = r < b.rblk_hi[tile];
+    // records first: they depend neither on the system's state nor on its step
+    RodLoads L;
+    rod_load(b.a, r, active, sub, L);
     const int s = b.rblk_sys[tile];
     SolverState *st = b.sst + s;
     if (MODE != kModeApply && st->done) return;
     const long long k = MODE == kModeLoop ? *b.kbase + i : 0;
-    const int sub = threadIdx.x & (kRodLanes - 1);
-    const int64_t r = (int64_t)b.rblk_lo[tile] + threadIdx.x / kRodLanes;
-    const bool active = r < b.rblk_hi[tile];
-    RodLoads L;
-    rod_load(b.a, r, active, sub, L);
     double alpha = 0.0;
     if (MODE == kModeLoop) {
         const bool publisher = (int)tile == b.sys_r0[s] && threadIdx.x == 0;
@@ -129,20 +130,26 @@ __global__ void __launch_bounds__(CB) k_con_b(BatchArgs b, int i)
     __shared__ double lds[CB / 64 + 1][4];
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     if ((int)tile >= b.ncb) return;
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t hi = b.cblk_hi[tile];
+    // first round peeled: its records are in flight before the system's stop
+    // flag and step are read (every thread reaches the test)
+    int64_t c0 = b.cblk_lo[tile] + threadIdx.x;
+    ConLoads A, B;
+    if (c0 < hi) con_load<MODE>(b.a, c0, A);
+    if (c0 + CB < hi) con_load<MODE>(b.a, c0 + CB, B);
     const int s = b.cblk_sys[tile];
     SolverState *st = b.sst + s;
     if (MODE != kModeApply && st->done) return;
     const long long k = MODE == kModeLoop ? *b.kbase + i : 0;
     const double alpha = MODE == kModeLoop ? b.alpha_s[2 * s + (k & 1)] : 0.0;
-    double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t hi = b.cblk_hi[tile];
-    for (int64_t c0 = b.cblk_lo[tile] + threadIdx.x; c0 < hi; c0 += 2 * CB) {
-        const int64_t c1 = c0 + CB;
-        ConLoads A, B;
+    for (;;) {
+        if (c0 < hi) con_update<MODE>(b.a, c0, A, alpha, p);
+        if (c0 + CB < hi) con_update<MODE>(b.a, c0 + CB, B, alpha, p);
+        c0 += 2 * CB;
+        if (c0 >= hi) break;
         con_load<MODE>(b.a, c0, A);
-        if (c1 < hi) con_load<MODE>(b.a, c1, B);
-        con_update<MODE>(b.a, c0, A, alpha, p);
-        if (c1 < hi) con_update<MODE>(b.a, c1, B, alpha, p);
+        if (c0 + CB < hi) con_load<MODE>(b.a, c0 + CB, B);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<CB / 64>(p, lds);

@@ -157,14 +157,15 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
 {
     __shared__ double lds[kRodBlock / 64 + 1][4];
     double alpha = 0.0;
-    if (MODE != kModeApply && a.state->done) return;
     const int sub = threadIdx.x & (kRodLanes - 1);
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < a.n;
-    // the incidence records do not depend on the step length: load them first
+    // the incidence records depend neither on the step length nor on the stop
+    // flag: load them first (after the stop they are read for nothing)
     RodLoads L;
     rod_load(a, r, active, sub, L);
+    if (MODE != kModeApply && a.state->done) return;
     if (MODE == kModeLoop) {
         if (k == 0) {
             alpha = a.state->alpha;
@@ -217,21 +218,30 @@ template <int MODE>
 __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
 {
     __shared__ double lds[kConBlock / 64 + 1][4];
-    if (MODE != kModeApply && a.state->done) return;
-    const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     // each workgroup takes a contiguous chunk of constraints, two per lane per round
     const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
-    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += kConCpl * kConBlock) {
-        ConLoads L[kConCpl];
+    // first round peeled: its records are in flight before the stop flag and
+    // the step length are read (every thread reaches the test)
+    const int64_t step = (int64_t)kConCpl * kConBlock;
+    int64_t c0 = lo + threadIdx.x;
+    ConLoads L[kConCpl];
 #pragma unroll
-        for (int u = 0; u < kConCpl; ++u)
-            if (c0 + u * kConBlock < hi) con_load<MODE>(a, c0 + u * kConBlock, L[u]);
+    for (int u = 0; u < kConCpl; ++u)
+        if (c0 + u * kConBlock < hi) con_load<MODE>(a, c0 + u * kConBlock, L[u]);
+    if (MODE != kModeApply && a.state->done) return;
+    const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
+    for (;;) {
 #pragma unroll
         for (int u = 0; u < kConCpl; ++u)
             if (c0 + u * kConBlock < hi) con_update<MODE>(a, c0 + u * kConBlock, L[u], alpha, p);
+        c0 += step;
+        if (c0 >= hi) break;
+#pragma unroll
+        for (int u = 0; u < kConCpl; ++u)
+            if (c0 + u * kConBlock < hi) con_load<MODE>(a, c0 + u * kConBlock, L[u]);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<kConBlock / 64>(p, lds);
