@@ -225,41 +225,6 @@ __global__ void k_bin(int64_t n, const double *__restrict__ x, const double *__r
     atomicAdd(cell_cnt + id, 1);
 }
 
-// exclusive scan of m int32 counts into m+1 offsets, one workgroup of 1024
-__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ in, int64_t m, int *__restrict__ out,
-                                               int64_t *__restrict__ total)
-{
-    __shared__ long long part[1024];
-    const int tid = threadIdx.x;
-    const int64_t chunk = (m + 1023) / 1024;
-    const int64_t beg = tid * chunk;
-    const int64_t end = beg + chunk < m ? beg + chunk : m;
-    long long s = 0;
-    for (int64_t k = beg; k < end; ++k) s += in[k];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        long long v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    long long run = part[tid] - s;
-    for (int64_t k = beg; k < end; ++k) {
-        out[k] = (int)run;
-        run += in[k];
-    }
-    if (tid == 1023) {
-        out[m] = (int)part[1023];
-        if (total) *total = part[1023];
-    }
-}
-
-hipError_t launch_scan(hipStream_t st, const int *in, int64_t m, int *out, int64_t *total)
-{
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, in, m, out, total);
-    return hipGetLastError();
-}
 
 __global__ void k_scatter(int64_t n, const double *__restrict__ x, const double *__restrict__ dir,
                           const double *__restrict__ len, double len0, const int *__restrict__ cell_of,
@@ -319,19 +284,55 @@ __device__ __forceinline__ void stage_cell(CellStage &S, int q0, int m, V3 shift
     }
 }
 
-template <bool FILL, bool INTERNAL>
+// Pass modes: count pairs per rod, fill the per-rod slots, or emit every
+// pair once as a sort key (pi, pj, shift) with its flags at a slot reserved
+// per flush (the list is put in canonical order by a radix sort afterwards).
+enum PairPass : int { kPairCount = 0, kPairFill = 1, kPairEmit = 2 };
+
+// exclusive prefix of v over the workgroup; tot = the sum (lds: 5 ints)
+__device__ __forceinline__ void block_excl_scan(int v, int &excl, int &tot, int *lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    if (lane == 63) lds[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < kPairBlock / 64; ++k) {
+            const int t = lds[k];
+            lds[k] = run;
+            run += t;
+        }
+        lds[kPairBlock / 64] = run;
+    }
+    __syncthreads();
+    excl = lds[w] + incl - v;
+    tot = lds[kPairBlock / 64];
+}
+
+template <int PASS, bool INTERNAL>
 __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, double cutoff,
                                                       const int *__restrict__ sorted, const double *__restrict__ xs,
                                                       const double *__restrict__ ds, const double *__restrict__ ls,
                                                       const int *__restrict__ cell_start, int *__restrict__ pcnt,
                                                       const int *__restrict__ poff, int32_t *__restrict__ pi,
                                                       int32_t *__restrict__ pj, int32_t *__restrict__ img,
-                                                      uint8_t *__restrict__ flags)
+                                                      uint8_t *__restrict__ flags, unsigned long long *ecount,
+                                                      unsigned long long *__restrict__ ekeys,
+                                                      uint8_t *__restrict__ eflags, int64_t ecap, int kshift)
 {
+    constexpr bool FILL = PASS == kPairFill;
     __shared__ CellStage H, Nb;
     __shared__ int hcnt[kCellChunk], hoff[kCellChunk];
     __shared__ int queue[kQueue];
     __shared__ int qn;
+    __shared__ int scan_lds[kPairBlock / 64 + 1];
+    __shared__ unsigned long long ebase;
     const int h = blockIdx.x;
     const int hz = h % g.nc[2], hy = (h / g.nc[2]) % g.nc[1], hx = h / (g.nc[2] * g.nc[1]);
     const int hb = cell_start[h], he = cell_start[h + 1];
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
         stage_cell<INTERNAL>(H, a0, na, v3(0.0, 0.0, 0.0), sorted, xs, ds, ls);
         for (int u = threadIdx.x; u < na; u += kPairBlock) {
             hcnt[u] = 0;
-            if (FILL) hoff[u] = poff[INTERNAL ? a0 + u : sorted[a0 + u]];
+            if (PASS == kPairFill) hoff[u] = poff[INTERNAL ? a0 + u : sorted[a0 + u]];
         }
         __syncthreads();
         for (int sc = 0; sc < NS; ++sc) {
@@ -387,27 +388,53 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
                     }
                     __syncthreads();
                     const int nq = qn;
+                    int mine = 0;
                     for (int u = threadIdx.x; u < nq; u += kPairBlock) {
-                        const int a = queue[u] >> 16, b = queue[u] & 0xffff;
+                        const int a = (queue[u] >> 16) & 0xff, b = queue[u] & 0xff;
                         const V3 xi = v3(H.p[0][a], H.p[1][a], H.p[2][a]), di = v3(H.p[3][a], H.p[4][a], H.p[5][a]);
                         const V3 xj = v3(Nb.p[0][b], Nb.p[1][b], Nb.p[2][b]), dj = v3(Nb.p[3][b], Nb.p[4][b], Nb.p[5][b]);
                         const Contact c = closest_point(xi, di, 0.5 * H.p[6][a], xj, dj, 0.5 * Nb.p[6][b]);
                         const double phi = c.dist - diam;
                         if (!(phi < cutoff)) continue;
+                        const unsigned fl = c.flags | (fabs(phi - cutoff) <= kCutoffBand ? 1u : 0u);
+                        if (PASS == kPairEmit) {
+                            // mark the entry: bit 31 = pair, bits 24..27 = flags
+                            queue[u] = (int)(0x80000000u | (fl << 24) | (unsigned)queue[u]);
+                            ++mine;
+                            continue;
+                        }
                         const int slot = atomicAdd(&hcnt[a], 1);
                         if (FILL) {
                             const int o = hoff[a] + slot;
                             pi[o] = H.idx[a];
                             pj[o] = Nb.idx[b];
                             img[o] = packed;
-                            flags[o] = (uint8_t)(c.flags | (fabs(phi - cutoff) <= kCutoffBand ? 1u : 0u));
+                            flags[o] = (uint8_t)fl;
+                        }
+                    }
+                    if (PASS == kPairEmit) {
+                        int excl = 0, tot = 0;
+                        block_excl_scan(mine, excl, tot, scan_lds);
+                        if (threadIdx.x == 0) ebase = tot > 0 ? atomicAdd(ecount, (unsigned long long)tot) : 0ull;
+                        __syncthreads();
+                        unsigned long long o = ebase + (unsigned long long)excl;
+                        for (int u = threadIdx.x; u < nq; u += kPairBlock) {
+                            const unsigned v = (unsigned)queue[u];
+                            if (!(v >> 31)) continue;
+                            if (o < (unsigned long long)ecap) {
+                                const int a = (v >> 16) & 0xff, b = v & 0xff;
+                                ekeys[o] = ((unsigned long long)(unsigned)H.idx[a] << kshift) |
+                                           ((unsigned long long)(unsigned)Nb.idx[b] << 12) | (unsigned long long)packed;
+                                eflags[o] = (uint8_t)((v >> 24) & 15u);
+                            }
+                            ++o;
                         }
                     }
                     __syncthreads();
                 }
             }
         }
-        if (!FILL)
+        if (PASS == kPairCount)
             for (int u = threadIdx.x; u < na; u += kPairBlock) pcnt[H.idx[u]] = hcnt[u];
         __syncthreads();
     }
@@ -554,8 +581,10 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     RL_HIP(hipMemsetAsync(cell_cnt, 0, sizeof(int) * ncell, st));
     hipLaunchKernelGGL(k_bin, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, g, cell_of, cell_cnt, h->flag_dev);
     RL_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cell_cnt, ncell, cell_start, (int64_t *)nullptr);
-    RL_HIP(hipGetLastError());
+    {
+        const int rc = device_scan(h, cell_cnt, ncell, cell_start, nullptr);
+        if (rc) return rc;
+    }
     if (internal) {
         int bits = 1;
         while ((1LL << bits) < ncell) ++bits;
@@ -569,14 +598,49 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
                            cell_start, cell_cur, sorted, xs, ds, ls);
     }
     RL_HIP(hipGetLastError());
-    if (internal)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, true>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<false, false>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
-    RL_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pcnt, n, poff, tot);
-    RL_HIP(hipGetLastError());
-    RL_HIP(hipMemcpyAsync(h->host_scratch, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    // one pass emitting sort keys (pi, pj, shift), then a radix sort into the
+    // canonical order; rod counts above 2^26 do not fit the 64-bit key and
+    // take the counting and filling passes with a per-rod sort instead
+    int ibits = 1;
+    while ((1LL << ibits) < n) ++ibits;
+    const bool emit = 2 * ibits + 12 <= 64;
+    const dim3 pgrid((unsigned)ncell), pblock(kPairBlock);
+    auto *none_u64 = (unsigned long long *)nullptr;
+    auto *none_u8 = (uint8_t *)nullptr;
+    if (emit) {
+        const int64_t ecap = capacity > 0 ? capacity : 0;
+        auto *ecount = (unsigned long long *)ws_get(h, kWsEmitCount, sizeof(unsigned long long), &werr);
+        auto *ekeys = (unsigned long long *)ws_get(h, kWsEmitKeys, sizeof(unsigned long long) * (ecap > 0 ? ecap : 1), &werr);
+        auto *eflags = (uint8_t *)ws_get(h, kWsEmitFlags, (size_t)(ecap > 0 ? ecap : 1), &werr);
+        if (werr) return werr;
+        RL_HIP(hipMemsetAsync(ecount, 0, sizeof(unsigned long long), st));
+        const int kshift = ibits + 12;
+        if (internal)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairEmit, true>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+                               sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
+                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, ecount, ekeys, eflags, ecap, kshift);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairEmit, false>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+                               sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
+                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, ecount, ekeys, eflags, ecap, kshift);
+        RL_HIP(hipGetLastError());
+        RL_HIP(hipMemcpyAsync(h->host_scratch, ecount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    } else {
+        if (internal)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairCount, true>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+                               sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
+                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, none_u64, none_u64, none_u8,
+                               (int64_t)0, 0);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairCount, false>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+                               sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
+                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, none_u64, none_u64, none_u8,
+                               (int64_t)0, 0);
+        RL_HIP(hipGetLastError());
+        const int rc = device_scan(h, pcnt, n, poff, tot);
+        if (rc) return rc;
+        RL_HIP(hipMemcpyAsync(h->host_scratch, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    }
     RL_HIP(hipMemcpyAsync(h->host_scratch + 1, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     RL_HIP(hipStreamSynchronize(st));
     const int64_t total = h->host_scratch[0];
@@ -599,10 +663,21 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
         return RL_ERR_CAPACITY;
     }
     if (total == 0) return RL_OK;
+    if (emit) {
+        auto *ekeys = (unsigned long long *)h->buf[kWsEmitKeys];
+        auto *eflags = (uint8_t *)h->buf[kWsEmitFlags];
+        const int rc = sort_pair_keys(h, total, 2 * ibits + 12, ekeys, eflags, ibits, pi, pj, img, flags);
+        if (rc) return rc;
+        return RL_OK;
+    }
     if (internal)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, true>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairFill, true>), pgrid, pblock, 0, st, g, p.diam, p.cutoff, sorted,
+                           xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags, none_u64, none_u64,
+                           none_u8, (int64_t)0, 0);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<true, false>), dim3((unsigned)ncell), dim3(kPairBlock), 0, st, g, p.diam, p.cutoff, sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairFill, false>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+                           sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags, none_u64,
+                           none_u64, none_u8, (int64_t)0, 0);
     RL_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sort_pairs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)poff, pj, img, flags);
     RL_HIP(hipGetLastError());

@@ -164,7 +164,7 @@ enum Slot : int {
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
     kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
-    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache,
+    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
@@ -183,6 +183,13 @@ int build_pairs_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, c
                      int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs);
 hipError_t launch_gather6(hipStream_t st, int64_t n, const int *perm, const double *src, double *dst);
 int stable_sort_by_key(rl_ctx *h, int64_t n, const int *keys, int bits, int *keys_out, int *perm);
+// out[0..m] = exclusive prefix sums of in[0..m-1] (out[m] = the total, also
+// written to *total when given), on the handle's stream
+int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total);
+// sorts m pair keys ((pi << (ibits + 12)) | (pj << 12) | shift, `bits` wide)
+// with their flags and writes the canonical pi, pj, img, flags lists
+int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *keys, const uint8_t *kflags, int ibits,
+                   int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags);
 // Pair list in the solver's own rod order (cell order).  On return *perm
 // (device, n) maps solver rod -> caller rod and xs/ds/ls hold the rods'
 // centres, directors and lengths in solver order (handle workspace).

@@ -150,7 +150,6 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
     gamma[c] = st[c].x;
 }
 
-hipError_t launch_scan(hipStream_t st, const int *in, int64_t m, int *out, int64_t *total);
 
 template <int MODE, bool UNI>
 __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
@@ -473,7 +472,8 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
             hipLaunchKernelGGL(k_qcount, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pj, qcnt);
             RL_HIP(hipGetLastError());
         }
-        RL_HIP(launch_scan(st, qcnt, n, qptr, nullptr));
+        const int rc = device_scan(h, qcnt, n, qptr, nullptr);
+        if (rc) return rc;
         if (nc > 0) {
             RL_HIP(hipMemsetAsync(qcnt, 0, sizeof(int) * n, st));
             hipLaunchKernelGGL(k_qfill, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pj, (const int32_t *)qptr, qcnt,

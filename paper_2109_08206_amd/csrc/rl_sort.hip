@@ -29,4 +29,59 @@ int stable_sort_by_key(rl_ctx *h, int64_t n, const int *keys, int bits, int *key
     return RL_OK;
 }
 
+__global__ void k_scan_ends(int64_t m, int *__restrict__ out, int64_t *__restrict__ total)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    out[0] = 0;
+    if (total) *total = out[m];
+}
+
+int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total)
+{
+    hipStream_t st = h->stream;
+    if (m > 0) {
+        int werr = 0;
+        size_t tmp_bytes = 0;
+        RL_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, out + 1, (int)m, st));
+        void *tmp = ws_get(h, kWsScanTmp, tmp_bytes, &werr);
+        if (werr) return werr;
+        RL_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, out + 1, (int)m, st));
+    }
+    hipLaunchKernelGGL(k_scan_ends, dim3(1), dim3(64), 0, st, m, out, total);
+    RL_HIP(hipGetLastError());
+    return RL_OK;
+}
+
+__global__ void k_decode_pairs(int64_t m, const unsigned long long *__restrict__ keys,
+                               const uint8_t *__restrict__ kflags, int ibits, int32_t *__restrict__ pi,
+                               int32_t *__restrict__ pj, int32_t *__restrict__ img, uint8_t *__restrict__ flags)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const unsigned long long k = keys[t];
+    pi[t] = (int32_t)(k >> (ibits + 12));
+    pj[t] = (int32_t)((k >> 12) & ((1ull << ibits) - 1ull));
+    img[t] = (int32_t)(k & 0xfffull);
+    flags[t] = kflags[t];
+}
+
+int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *keys, const uint8_t *kflags, int ibits,
+                   int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags)
+{
+    hipStream_t st = h->stream;
+    int werr = 0;
+    auto *k2 = (unsigned long long *)ws_get(h, kWsEmitKeys2, sizeof(unsigned long long) * m, &werr);
+    auto *f2 = (uint8_t *)ws_get(h, kWsEmitFlags2, (size_t)m, &werr);
+    if (werr) return werr;
+    size_t tmp_bytes = 0;
+    RL_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, k2, kflags, f2, (int)m, 0, bits, st));
+    void *tmp = ws_get(h, kWsSortTmp, tmp_bytes, &werr);
+    if (werr) return werr;
+    RL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, k2, kflags, f2, (int)m, 0, bits, st));
+    hipLaunchKernelGGL(k_decode_pairs, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, m,
+                       (const unsigned long long *)k2, (const uint8_t *)f2, ibits, pi, pj, img, flags);
+    RL_HIP(hipGetLastError());
+    return RL_OK;
+}
+
 }  // namespace rl
