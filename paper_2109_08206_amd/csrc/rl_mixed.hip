@@ -56,7 +56,6 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
 {
     __shared__ double lds[kRodBlock / 64 + 1][4];
     SolverState *st = a.state;
-    if (st->done || st->refresh) return;
     const int sub = threadIdx.x & (kRodLanes - 1);
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
@@ -78,6 +77,8 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
         qs = a.stq32[qb];
         qg = a.qgeo32[qb];
     }
+    // the first records are in flight; now the stop and refresh flags
+    if (st->done || st->refresh) return;
     double alpha;
     if (first) {
         alpha = st->alpha;
@@ -235,19 +236,26 @@ __device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, cons
 __global__ void __launch_bounds__(kConBlock) k_con32(SolveArgs a, long long k)
 {
     __shared__ double lds[kConBlock / 64 + 1][4];
-    if (a.state->done || a.state->refresh) return;
-    const float a32 = (float)a.alpha_buf[k & 1];
     double p[4] = {0.0, 0.0, 0.0, 0.0};
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
-    for (int64_t c0 = lo + threadIdx.x; c0 < hi; c0 += 2 * kConBlock) {
+    // the first two records go out before the flags are read; nothing in this
+    // launch writes the flags, so the early return is uniform
+    int64_t c0 = lo + threadIdx.x;
+    Con32Loads A, B;
+    if (c0 < hi) con32_load(a, c0, A);
+    if (c0 + kConBlock < hi) con32_load(a, c0 + kConBlock, B);
+    if (a.state->done || a.state->refresh) return;
+    const float a32 = (float)a.alpha_buf[k & 1];
+    while (c0 < hi) {
         const int64_t c1 = c0 + kConBlock;
-        Con32Loads A, B;
-        con32_load(a, c0, A);
-        if (c1 < hi) con32_load(a, c1, B);
         con32_update(a, c0, A, a32, p);
         if (c1 < hi) con32_update(a, c1, B, a32, p);
+        c0 += 2 * kConBlock;
+        if (c0 >= hi) break;
+        con32_load(a, c0, A);
+        if (c0 + kConBlock < hi) con32_load(a, c0 + kConBlock, B);
     }
     block_reduce4_all<kConBlock / 64>(p, lds);
     if (threadIdx.x == 0) {
