@@ -36,14 +36,14 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f)
 def kernel_bytes(n: int, nc: int) -> dict:
     """Algorithmic bytes per launch of the two BBPGD loop kernels: every array
     element the kernel must touch once (FP64 values, int32 indices).
-    rod kernel:        per rod pptr+qptr 8, dir 24, V write 48        -> 80 n
-                       per constraint, P side: (gamma, g) 16, (e, s_i) 32;
-                       Q side copy: (gamma, g) 16, (e, s_j) 32        -> 96 nc
-    constraint kernel: per constraint (pi, pj) 8, (e, s_i, s_j, q) 48,
-                       (gamma, g) read 16 + write 16, qpos 4,
-                       Q-side (gamma, g) write 16                     -> 108 nc
-                       per rod V read 48                              -> 48 n"""
-    return {"rod": 80 * n + 96 * nc, "con": 108 * nc + 48 * n}
+    rod kernel:        per rod pptr+qptr 8, dir 24                    -> 32 n
+                       per constraint, P side: (gamma, g) 16, (e, s_i) 32,
+                       u_P write 8; Q side copy: (gamma, g) 16,
+                       (e, s_j) 32, u_Q write 8                       -> 112 nc
+    constraint kernel: per constraint qpos 4, u_P 8, u_Q 8, q 8,
+                       (gamma, g) read 16 + write 16,
+                       Q-side (gamma, g) write 16                     -> 76 nc"""
+    return {"rod": 32 * n + 112 * nc, "con": 76 * nc}
 
 
 def source_hash() -> str:

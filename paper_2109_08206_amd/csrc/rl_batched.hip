@@ -111,17 +111,16 @@ __global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
     }
     double f[3], m[3];
     rod_accumulate<MODE>(b.a, L, alpha, f, m);
-    if (!active || sub >= 3) return;
+    if (!active) return;
     const SolveArgs &a = b.a;
     const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
     double apar, aperp, rperp;
     rod_mob(a, r, UNI, apar, aperp, rperp);
     const double fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
     const double md = dx * m[0] + dy * m[1] + dz * m[2];
-    double2 *out = reinterpret_cast<double2 *>(a.V + 6 * r);
-    if (sub == 0) out[0] = make_double2(aperp * f[0] + fd * dx, aperp * f[1] + fd * dy);
-    else if (sub == 1) out[1] = make_double2(aperp * f[2] + fd * dz, rperp * (m[0] - md * dx));
-    else out[2] = make_double2(rperp * (m[1] - md * dy), rperp * (m[2] - md * dz));
+    const double v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
+    const double w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
+    rod_emit_u(a, L, v, w);
 }
 
 template <int MODE, int CB>
@@ -135,21 +134,21 @@ __global__ void __launch_bounds__(CB) k_con_b(BatchArgs b, int i)
     // first round peeled: its records are in flight before the system's stop
     // flag and step are read (every thread reaches the test)
     int64_t c0 = b.cblk_lo[tile] + threadIdx.x;
-    ConLoads A, B;
-    if (c0 < hi) con_load<MODE>(b.a, c0, A);
-    if (c0 + CB < hi) con_load<MODE>(b.a, c0 + CB, B);
+    ConLoadsU A, B;
+    if (c0 < hi) con_load_u<MODE>(b.a, c0, A);
+    if (c0 + CB < hi) con_load_u<MODE>(b.a, c0 + CB, B);
     const int s = b.cblk_sys[tile];
     SolverState *st = b.sst + s;
     if (MODE != kModeApply && st->done) return;
     const long long k = MODE == kModeLoop ? *b.kbase + i : 0;
     const double alpha = MODE == kModeLoop ? b.alpha_s[2 * s + (k & 1)] : 0.0;
     for (;;) {
-        if (c0 < hi) con_update<MODE>(b.a, c0, A, alpha, p);
-        if (c0 + CB < hi) con_update<MODE>(b.a, c0 + CB, B, alpha, p);
+        if (c0 < hi) con_update_u<MODE>(b.a, c0, A, alpha, p);
+        if (c0 + CB < hi) con_update_u<MODE>(b.a, c0 + CB, B, alpha, p);
         c0 += 2 * CB;
         if (c0 >= hi) break;
-        con_load<MODE>(b.a, c0, A);
-        if (c0 + CB < hi) con_load<MODE>(b.a, c0 + CB, B);
+        con_load_u<MODE>(b.a, c0, A);
+        if (c0 + CB < hi) con_load_u<MODE>(b.a, c0 + CB, B);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<CB / 64>(p, lds);

@@ -57,18 +57,35 @@ __device__ __forceinline__ void block_reduce4_all(double p[4], double (*lds)[4])
     __syncthreads();
 }
 
-// Totals of the gcon workgroup partials at `P`, identical in every workgroup.
+// Totals of the `count` workgroup partials at `P`, identical in every
+// workgroup.  Each thread sums its partials in index order; kPartChunk of its
+// loads are in flight together.
+constexpr int kPartChunk = 2;
+
 template <int NW>
-__device__ __forceinline__ void sum_partials(const double *__restrict__ P, int gcon, double p[4], double (*lds)[4])
+__device__ __forceinline__ void sum_partials(const double *__restrict__ P, int count, double p[4], double (*lds)[4])
 {
+    constexpr int NT = NW * 64;
     p[0] = p[1] = p[2] = p[3] = 0.0;
-    for (int b = threadIdx.x; b < gcon; b += blockDim.x) {
-        const double2 *src = reinterpret_cast<const double2 *>(P + 4 * (int64_t)b);
-        const double2 u = src[0], v = src[1];
-        p[0] += u.x;
-        p[1] += u.y;
-        p[2] += v.x;
-        p[3] = fmax(p[3], v.y);
+    for (int b0 = threadIdx.x; b0 < count; b0 += kPartChunk * NT) {
+        double2 u[kPartChunk], v[kPartChunk];
+#pragma unroll
+        for (int j = 0; j < kPartChunk; ++j) {
+            // clamped, so that every load is issued before the first wait
+            const int b = min(b0 + j * NT, count - 1);
+            const double2 *src = reinterpret_cast<const double2 *>(P + 4 * (int64_t)b);
+            u[j] = src[0];
+            v[j] = src[1];
+        }
+#pragma unroll
+        for (int j = 0; j < kPartChunk; ++j) {
+            if (b0 + j * NT < count) {
+                p[0] += u[j].x;
+                p[1] += u[j].y;
+                p[2] += v[j].x;
+                p[3] = fmax(p[3], v[j].y);
+            }
+        }
     }
     block_reduce4_all<NW>(p, lds);
 }
@@ -81,31 +98,47 @@ struct Decision {
     int stop, status;
 };
 
-// st: the system's state; abuf: its two step lengths by iteration parity
-__device__ __forceinline__ Decision decide(const SolverState *st, const double *abuf, long long k, const double t[4])
+// The state a decision reads, loaded ahead of it (st: the system's state;
+// abuf: its two step lengths by iteration parity).
+struct DecideIn {
+    double tol, amin, amax, aprev;
+    long long max_iter;
+};
+
+__device__ __forceinline__ DecideIn decide_in(const SolverState *st, const double *abuf, long long k)
+{
+    return DecideIn{st->tol, st->amin, st->amax, abuf[(k - 1) & 1], st->max_iter};
+}
+
+__device__ __forceinline__ Decision decide_from(const DecideIn &in, long long k, const double t[4])
 {
     Decision d{0.0, 0, RL_OK};
     const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
     if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
         d.stop = 1;
         d.status = RL_ERR_NONFINITE;
-    } else if (res <= st->tol) {
+    } else if (res <= in.tol) {
         d.stop = 1;
         d.status = RL_OK;
     } else if (ss == 0.0) {
         d.stop = 1;
         d.status = RL_STAGNATED;
-    } else if (k >= st->max_iter) {
+    } else if (k >= in.max_iter) {
         d.stop = 1;
         d.status = RL_NOT_CONVERGED;
     }
-    double al = abuf[(k - 1) & 1];
+    double al = in.aprev;
     if (sy > 0.0) {
         al = ((k - 1) % 2 == 0) ? ss / sy : sy / yy;
-        al = al < st->amin ? st->amin : (al > st->amax ? st->amax : al);
+        al = al < in.amin ? in.amin : (al > in.amax ? in.amax : al);
     }
     d.alpha = al;
     return d;
+}
+
+__device__ __forceinline__ Decision decide(const SolverState *st, const double *abuf, long long k, const double t[4])
+{
+    return decide_from(decide_in(st, abuf, k), k, t);
 }
 
 // Workgroup -> work-tile map that gives each of the eight XCDs (which take
@@ -135,16 +168,43 @@ __device__ __forceinline__ double gamma_prime(double gam, double g, double alpha
 }
 
 // Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
-// rod r, split over the four lanes of the rod and combined by a fixed tree.
-// The torque on the rod is dir x m.  The first P-side and the first Q-side
-// record of each lane are loaded together (one memory round for almost every
-// rod: a lane holds up to four incidences per side in its first round);
-// longer lists continue in a loop.
+// rod r, split over the kRodLanes lanes of the rod and combined by a fixed
+// tree.  The torque on the rod is dir x m.  A lane takes the records sub,
+// sub + kRodLanes, ... of each side.  Its first two rounds of both sides are
+// loaded into registers (the first always before the step-length wait, the
+// second before it too when kRodPreload2 is set); longer lists continue in a
+// loop.  The registers stay live for the contact-velocity emission.
+#ifndef RL_ROD_PRELOAD2
+#define RL_ROD_PRELOAD2 1
+#endif
+constexpr bool kRodPreload2 = RL_ROD_PRELOAD2 != 0;
+
+struct RodRec {
+    double2 s, g0, g1;  // (gamma, g), (ex, ey), (ez, s)
+};
+
 struct RodLoads {
     int pb, pe, qb, qe;
-    double2 ps, pg0, pg1;  // first P record: (gamma, g), (ex, ey), (ez, s_i)
-    double2 qs, qg0, qg1;  // first Q record: (gamma, g), (ex, ey), (ez, s_j)
+    RodRec p1, q1, p2, q2;  // rounds 1 and 2 of the P and Q sides
 };
+
+__device__ __forceinline__ void rod_rec_load(const double2 *st, const double *geo, int c, int end, RodRec &R)
+{
+    const double2 z = make_double2(0.0, 0.0);
+    R.s = R.g0 = R.g1 = z;
+    if (c < end) {
+        const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
+        R.s = st[c];
+        R.g0 = gd[0];
+        R.g1 = gd[1];
+    }
+}
+
+__device__ __forceinline__ void rod_load_round2(const SolveArgs &a, RodLoads &L)
+{
+    rod_rec_load(a.st, a.geo, L.pb + kRodLanes, L.pe, L.p2);
+    rod_rec_load(a.stq, a.qgeo, L.qb + kRodLanes, L.qe, L.q2);
+}
 
 __device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
 {
@@ -155,73 +215,47 @@ __device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool act
         L.qb = a.qptr[r] + sub;
         L.qe = a.qptr[r + 1];
     }
-    const double2 z = make_double2(0.0, 0.0);
-    L.ps = L.pg0 = L.pg1 = L.qs = L.qg0 = L.qg1 = z;
-    if (L.pb < L.pe) {
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)L.pb);
-        L.ps = a.st[L.pb];
-        L.pg0 = gd[0];
-        L.pg1 = gd[1];
-    }
-    if (L.qb < L.qe) {
-        const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)L.qb);
-        L.qs = a.stq[L.qb];
-        L.qg0 = gd[0];
-        L.qg1 = gd[1];
+    rod_rec_load(a.st, a.geo, L.pb, L.pe, L.p1);
+    rod_rec_load(a.stq, a.qgeo, L.qb, L.qe, L.q1);
+    if (kRodPreload2) rod_load_round2(a, L);
+}
+
+// f += +-gamma' e, m += +-gamma' s e for one incidence record
+__device__ __forceinline__ void rod_add(double sign, double gm, double2 g0, double2 g1, double f[3], double m[3])
+{
+    const double gv = sign * gm, gs = gv * g1.y;
+    f[0] += gv * g0.x;
+    f[1] += gv * g0.y;
+    f[2] += gv * g1.x;
+    m[0] += gs * g0.x;
+    m[1] += gs * g0.y;
+    m[2] += gs * g1.x;
+}
+
+template <int MODE>
+__device__ __forceinline__ void rod_side(double sign, const double2 *st, const double *geo, int b, int e,
+                                         const RodRec &r1, const RodRec &r2, double alpha, double f[3], double m[3])
+{
+    if (b >= e) return;
+    rod_add(sign, gamma_prime<MODE>(r1.s.x, r1.s.y, alpha), r1.g0, r1.g1, f, m);
+    const int b2 = b + kRodLanes;
+    if (b2 >= e) return;
+    rod_add(sign, gamma_prime<MODE>(r2.s.x, r2.s.y, alpha), r2.g0, r2.g1, f, m);
+    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) {
+        const double2 sg = st[c];
+        const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
+        rod_add(sign, gamma_prime<MODE>(sg.x, sg.y, alpha), gd[0], gd[1], f, m);
     }
 }
 
 template <int MODE>
-__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads &L, double alpha, double f[3],
+__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, RodLoads &L, double alpha, double f[3],
                                                double m[3])
 {
     f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    if (L.pb < L.pe) {
-        const double gm = gamma_prime<MODE>(L.ps.x, L.ps.y, alpha);
-        const double gs = gm * L.pg1.y;
-        f[0] += gm * L.pg0.x;
-        f[1] += gm * L.pg0.y;
-        f[2] += gm * L.pg1.x;
-        m[0] += gs * L.pg0.x;
-        m[1] += gs * L.pg0.y;
-        m[2] += gs * L.pg1.x;
-        for (int c = L.pb + kRodLanes; c < L.pe; c += kRodLanes) {
-            const double2 sg = a.st[c];
-            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)c);
-            const double2 g0 = gd[0], g1 = gd[1];
-            const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
-            const double gsc = gmc * g1.y;
-            f[0] += gmc * g0.x;
-            f[1] += gmc * g0.y;
-            f[2] += gmc * g1.x;
-            m[0] += gsc * g0.x;
-            m[1] += gsc * g0.y;
-            m[2] += gsc * g1.x;
-        }
-    }
-    if (L.qb < L.qe) {
-        const double gm = gamma_prime<MODE>(L.qs.x, L.qs.y, alpha);
-        const double gs = gm * L.qg1.y;
-        f[0] -= gm * L.qg0.x;
-        f[1] -= gm * L.qg0.y;
-        f[2] -= gm * L.qg1.x;
-        m[0] -= gs * L.qg0.x;
-        m[1] -= gs * L.qg0.y;
-        m[2] -= gs * L.qg1.x;
-        for (int k = L.qb + kRodLanes; k < L.qe; k += kRodLanes) {
-            const double2 sg = a.stq[k];
-            const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)k);
-            const double2 g0 = gd[0], g1 = gd[1];
-            const double gmc = gamma_prime<MODE>(sg.x, sg.y, alpha);
-            const double gsc = gmc * g1.y;
-            f[0] -= gmc * g0.x;
-            f[1] -= gmc * g0.y;
-            f[2] -= gmc * g1.x;
-            m[0] -= gsc * g0.x;
-            m[1] -= gsc * g0.y;
-            m[2] -= gsc * g1.x;
-        }
-    }
+    if (!kRodPreload2) rod_load_round2(a, L);
+    rod_side<MODE>(1.0, a.st, a.geo, L.pb, L.pe, L.p1, L.p2, alpha, f, m);
+    rod_side<MODE>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.q1, L.q2, alpha, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -246,79 +280,106 @@ __device__ __forceinline__ void rod_mob(const SolveArgs &a, int64_t r, bool uni,
     }
 }
 
-// One constraint: w = e.(V_i + s_i W_i - V_j - s_j W_j) (+ q), from records
-// loaded beforehand so that two constraints' gathers are in flight at once.
-struct ConLoads {
-    double2 g0, g1, g2, sg;
-    int qp;
-    double2 i0, i1, i2, j0, j1, j2;
-};
-
+// The rest of one constraint's update once its rate w = D_c^T (V, W) is
+// known (w without q): by mode, the product, the start state, the Cauchy-step
+// dot products, the FP64 refresh, or one BBPGD step with its BB dot products
+// and natural residual.
 template <int MODE>
-__device__ __forceinline__ void con_load(const SolveArgs &a, int64_t c, ConLoads &L)
+__device__ __forceinline__ void con_apply(const SolveArgs &a, int64_t c, double w, double q, double2 sg, int qp,
+                                          double alpha, double p[4])
 {
-    const int2 ij = a.pp[c];
-    const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * c);
-    L.g0 = gd[0];
-    L.g1 = gd[1];
-    L.g2 = a.geo2[c];
-    if (MODE != kModeApply) L.sg = a.st[c];
-    if (MODE == kModeInit || MODE == kModeLoop || MODE == kModeRefresh) L.qp = a.qpos[c];
-    const double2 *Vi = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.x);
-    const double2 *Vj = reinterpret_cast<const double2 *>(a.V + 6 * (int64_t)ij.y);
-    L.i0 = Vi[0];
-    L.i1 = Vi[1];
-    L.i2 = Vi[2];
-    L.j0 = Vj[0];
-    L.j1 = Vj[1];
-    L.j2 = Vj[2];
-}
-
-template <int MODE>
-__device__ __forceinline__ void con_update(const SolveArgs &a, int64_t c, const ConLoads &L, double alpha,
-                                           double p[4])
-{
-    const double si = L.g1.y, sj = L.g2.x;
-    // velocity of the contact point on i minus that on j, along e
-    const double ux = (L.i0.x + si * L.i1.y) - (L.j0.x + sj * L.j1.y);
-    const double uy = (L.i0.y + si * L.i2.x) - (L.j0.y + sj * L.j2.x);
-    const double uz = (L.i1.x + si * L.i2.y) - (L.j1.x + sj * L.j2.y);
-    double w = L.g0.x * ux + L.g0.y * uy + L.g1.x * uz;
     if (MODE == kModeApply) {
-        a.out[c] = w + L.g2.y;
+        a.out[c] = w + q;
     } else if (MODE == kModeInit) {
-        w += L.g2.y;
-        const double gp = gamma_prime<kModeInit>(L.sg.x, 0.0, 0.0);
+        w += q;
+        const double gp = gamma_prime<kModeInit>(sg.x, 0.0, 0.0);
         a.st[c] = make_double2(gp, w);
-        a.stq[L.qp] = make_double2(gp, w);
+        a.stq[qp] = make_double2(gp, w);
         p[2] += w * w;
         p[3] = fmax(p[3], fabs(gp < w ? gp : w));
     } else if (MODE == kModeAlpha0) {
-        const double gh = gamma_prime<kModeAlpha0>(L.sg.x, L.sg.y, 0.0);
+        const double gh = gamma_prime<kModeAlpha0>(sg.x, sg.y, 0.0);
         p[0] += gh * gh;
         p[1] += gh * w;
     } else if (MODE == kModeRefresh) {
         // FP64 gradient of the accumulated iterate; the FP32 correction restarts at 0
-        w += L.g2.y;
-        const double gp = gamma_prime<kModeInit>(L.sg.x, 0.0, 0.0);
+        w += q;
+        const double gp = gamma_prime<kModeInit>(sg.x, 0.0, 0.0);
         a.st[c] = make_double2(gp, w);
-        a.stq[L.qp] = make_double2(gp, w);
+        a.stq[qp] = make_double2(gp, w);
         const float hw = (float)w, bg = -(float)gp;
         a.st32[c] = make_float4(0.0f, hw, bg, hw);
-        a.stq32[L.qp] = make_float4(0.0f, hw, bg, 0.0f);
+        a.stq32[qp] = make_float4(0.0f, hw, bg, 0.0f);
         p[2] += w * w;
         p[3] = fmax(p[3], fabs(gp < w ? gp : w));
     } else {
-        w += L.g2.y;
-        const double gp = gamma_prime<kModeLoop>(L.sg.x, L.sg.y, alpha);
-        const double sc = gp - L.sg.x, yc = w - L.sg.y;
+        w += q;
+        const double gp = gamma_prime<kModeLoop>(sg.x, sg.y, alpha);
+        const double sc = gp - sg.x, yc = w - sg.y;
         a.st[c] = make_double2(gp, w);
-        a.stq[L.qp] = make_double2(gp, w);
+        a.stq[qp] = make_double2(gp, w);
         p[0] += sc * sc;
         p[1] += sc * yc;
         p[2] += yc * yc;
         p[3] = fmax(p[3], fabs(gp < w ? gp : w));
     }
+}
+
+// ---------------------------------------------------------------------------
+// contact-velocity form: the rod kernel projects its rod's
+// (V, W) onto e at every contact point it takes part in, u = e.(V + s W), so
+// the constraint side reads two numbers instead of gathering two rods' six
+// and the geometry: w = u_P - u_Q.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double u_along(double2 g0, double2 g1, const double v[3], const double w[3])
+{
+    const double s = g1.y;
+    return g0.x * (v[0] + s * w[0]) + g0.y * (v[1] + s * w[1]) + g1.x * (v[2] + s * w[2]);
+}
+
+// The lane's incidences in the same order as rod_accumulate: the first two
+// rounds are still in registers, later ones (rare) are read again.
+__device__ __forceinline__ void emit_side(double *u, const double *geo, int b, int e, const RodRec &r1,
+                                          const RodRec &r2, const double v[3], const double w[3])
+{
+    if (b >= e) return;
+    u[b] = u_along(r1.g0, r1.g1, v, w);
+    const int b2 = b + kRodLanes;
+    if (b2 >= e) return;
+    u[b2] = u_along(r2.g0, r2.g1, v, w);
+    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) {
+        const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
+        u[c] = u_along(gd[0], gd[1], v, w);
+    }
+}
+
+__device__ __forceinline__ void rod_emit_u(const SolveArgs &a, const RodLoads &L, const double v[3], const double w[3])
+{
+    emit_side(a.uP, a.geo, L.pb, L.pe, L.p1, L.p2, v, w);
+    emit_side(a.uQ, a.qgeo, L.qb, L.qe, L.q1, L.q2, v, w);
+}
+
+struct ConLoadsU {
+    double2 sg;
+    double q, up, uq;
+    int qp;
+};
+
+template <int MODE>
+__device__ __forceinline__ void con_load_u(const SolveArgs &a, int64_t c, ConLoadsU &L)
+{
+    L.qp = a.qpos[c];
+    L.up = a.uP[c];
+    L.q = a.qv[c];
+    if (MODE != kModeApply) L.sg = a.st[c];
+    L.uq = a.uQ[L.qp];
+}
+
+template <int MODE>
+__device__ __forceinline__ void con_update_u(const SolveArgs &a, int64_t c, const ConLoadsU &L, double alpha,
+                                             double p[4])
+{
+    con_apply<MODE>(a, c, L.up - L.uq, L.q, L.sg, L.qp, alpha, p);
 }
 
 }  // namespace rl

@@ -66,6 +66,10 @@ Mob mobility_host(double L, double diam, double eta);
 #endif
 constexpr int kRodBlock = RL_ROD_BLOCK;
 constexpr int kRodLanes = RL_ROD_LANES;
+#ifndef RL_ROD_LOOP_BLOCK
+#define RL_ROD_LOOP_BLOCK 256
+#endif
+constexpr int kRodLoopBlock = RL_ROD_LOOP_BLOCK;  // workgroup of the single-solve rod kernel
 #ifndef RL_CON_BLOCK
 #define RL_CON_BLOCK 512
 #endif
@@ -95,7 +99,10 @@ struct SolveArgs {
     const double *qgeo;     // [nc][4] Q-side list order: (ex, ey, ez, s_j)
     double2 *st;            // [nc] (gamma, g) of the current iterate
     double2 *stq;           // [nc] the same in Q-side list order
-    double *V;              // [n][6] per rod: M_t F_c and Omega_c x dir
+    double *V;              // [n][6] per rod: M_t F_c and Omega_c x dir (adjoint kernels)
+    const double *qv;       // [nc] q alone, for the constraint kernel
+    double *uP;             // [nc] e.(V_i + s_i W_i): velocity of the contact point on pi along e
+    double *uQ;             // [nc] e.(V_j + s_j W_j) in Q-side list order
     double *partial;        // [2][gcon][4] workgroup partials, by iteration parity
     double *alpha_buf;      // [2] step length of iteration k at k & 1
     int gcon;               // workgroups of the constraint kernel
@@ -166,7 +173,7 @@ enum Slot : int {
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
     kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
-    kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs,
+    kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs, kWsQv, kWsUP, kWsUQ,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");

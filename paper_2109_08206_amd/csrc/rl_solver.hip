@@ -7,12 +7,16 @@
 //   rod kernel (four lanes per rod): the contact force D gamma' on the rod,
 //     summed over the constraints it takes part in (P side: contiguous range
 //     of the pi-sorted list; Q side: incidence list), and the mobility
-//     applied in registers.  It stores, per rod, V = M_t F_c and
-//     W = Omega_c x dir, so that the velocity of the axis point at arclength
-//     s is V + s W and the constraint side needs no director.
-//   constraint kernel (one lane per constraint, grid-stride): w = e.(V_i +
-//     s_i W_i - V_j - s_j W_j) + q, the projection, the BB dot products and
-//     the natural residual, reduced to one partial per workgroup.
+//     applied in registers: V = M_t F_c and W = Omega_c x dir, so that the
+//     velocity of the axis point at arclength s is V + s W.  It then writes,
+//     for every contact the rod takes part in, that point's velocity along
+//     the contact normal, u = e.(V + s W) (P side in constraint order, Q side
+//     in incidence-list order).
+//   constraint kernel (contiguous chunk per workgroup, two constraints per
+//     lane per round): w = u_P - u_Q + q, the projection, the BB dot products
+//     and the natural residual, reduced to one partial per workgroup.  It
+//     reads no geometry and gathers no rod data, only u_Q through the
+//     constraint's position in the incidence list.
 //
 // No workgroup ever waits for another inside a launch, so there are no
 // device-scope fences in the loop (each one flushes and invalidates the L2
@@ -109,11 +113,12 @@ __global__ void k_qsort(int64_t n, const int32_t *__restrict__ qptr, int32_t *__
     }
 }
 
-// constraint records: (pi, pj), (ex, ey, ez, s_i) and (s_j, q), (gamma, g = 0)
+// constraint records: (pi, pj), (ex, ey, ez, s_i) and (s_j, q), q alone,
+// (gamma, g = 0)
 __global__ void k_pack(int64_t nc, const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
                        const double *__restrict__ e, const double *__restrict__ arm, const double *__restrict__ q,
                        const double *__restrict__ gamma, int2 *__restrict__ pp, double *__restrict__ geo,
-                       double2 *__restrict__ geo2, double2 *__restrict__ st)
+                       double2 *__restrict__ geo2, double *__restrict__ qv, double2 *__restrict__ st)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nc) return;
@@ -121,7 +126,9 @@ __global__ void k_pack(int64_t nc, const int32_t *__restrict__ pi, const int32_t
     double2 *gd = reinterpret_cast<double2 *>(geo + 4 * c);
     gd[0] = make_double2(e[3 * c], e[3 * c + 1]);
     gd[1] = make_double2(e[3 * c + 2], arm[2 * c]);
-    geo2[c] = make_double2(arm[2 * c + 1], q ? q[c] : 0.0);
+    const double qc = q ? q[c] : 0.0;
+    geo2[c] = make_double2(arm[2 * c + 1], qc);
+    qv[c] = qc;
     st[c] = make_double2(gamma[c], 0.0);
 }
 
@@ -152,13 +159,13 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
 
 
 template <int MODE, bool UNI>
-__global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
+__global__ void __launch_bounds__(kRodLoopBlock) k_rod(SolveArgs a, long long k)
 {
-    __shared__ double lds[kRodBlock / 64 + 1][4];
+    __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     double alpha = 0.0;
     const int sub = threadIdx.x & (kRodLanes - 1);
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < a.n;
     // the incidence records depend neither on the step length nor on the stop
     // flag: load them first (after the stop they are read for nothing)
@@ -171,7 +178,7 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
             if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[0] = alpha;
         } else {
             double t[4];
-            sum_partials<kRodBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+            sum_partials<kRodLoopBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
             const Decision d = decide(a.state, a.alpha_buf, k, t);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 if (d.stop) {
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
     }
     double f[3], m[3];
     rod_accumulate<MODE>(a, L, alpha, f, m);
-    if (!active || sub >= 3) return;
+    if (!active) return;
     const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
     double apar, aperp, rperp;
     rod_mob(a, r, UNI, apar, aperp, rperp);
@@ -201,11 +208,11 @@ __global__ void __launch_bounds__(kRodBlock) k_rod(SolveArgs a, long long k)
     // r_perp dir x m (normal to the axis) and Omega x dir = r_perp (m - (d.m) d)
     const double fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
     const double md = dx * m[0] + dy * m[1] + dz * m[2];
-    double2 *out = reinterpret_cast<double2 *>(a.V + 6 * r);
-    if (sub == 0) out[0] = make_double2(aperp * f[0] + fd * dx, aperp * f[1] + fd * dy);
-    else if (sub == 1) out[1] = make_double2(aperp * f[2] + fd * dz, rperp * (m[0] - md * dx));
-    else out[2] = make_double2(rperp * (m[1] - md * dy), rperp * (m[2] - md * dz));
+    const double v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
+    const double w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
+    rod_emit_u(a, L, v, w);
 }
+
 
 // ---------------------------------------------------------------------------
 // constraint kernel
@@ -226,21 +233,21 @@ __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
     // the step length are read (every thread reaches the test)
     const int64_t step = (int64_t)kConCpl * kConBlock;
     int64_t c0 = lo + threadIdx.x;
-    ConLoads L[kConCpl];
+    ConLoadsU L[kConCpl];
 #pragma unroll
     for (int u = 0; u < kConCpl; ++u)
-        if (c0 + u * kConBlock < hi) con_load<MODE>(a, c0 + u * kConBlock, L[u]);
+        if (c0 + u * kConBlock < hi) con_load_u<MODE>(a, c0 + u * kConBlock, L[u]);
     if (MODE != kModeApply && a.state->done) return;
     const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
     for (;;) {
 #pragma unroll
         for (int u = 0; u < kConCpl; ++u)
-            if (c0 + u * kConBlock < hi) con_update<MODE>(a, c0 + u * kConBlock, L[u], alpha, p);
+            if (c0 + u * kConBlock < hi) con_update_u<MODE>(a, c0 + u * kConBlock, L[u], alpha, p);
         c0 += step;
         if (c0 >= hi) break;
 #pragma unroll
         for (int u = 0; u < kConCpl; ++u)
-            if (c0 + u * kConBlock < hi) con_load<MODE>(a, c0 + u * kConBlock, L[u]);
+            if (c0 + u * kConBlock < hi) con_load_u<MODE>(a, c0 + u * kConBlock, L[u]);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<kConBlock / 64>(p, lds);
@@ -436,6 +443,9 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     int2 *pp = (int2 *)ws_get(h, kWsPP, sizeof(int2) * nb, &werr);
     double *geo = (double *)ws_get(h, kWsGeo, sizeof(double) * 4 * nb, &werr);
     double2 *geo2 = (double2 *)ws_get(h, kWsGeo2, sizeof(double2) * nb, &werr);
+    double *qv = (double *)ws_get(h, kWsQv, sizeof(double) * nb, &werr);
+    s.uP = (double *)ws_get(h, kWsUP, sizeof(double) * nb, &werr);
+    s.uQ = (double *)ws_get(h, kWsUQ, sizeof(double) * nb, &werr);
     s.st = (double2 *)ws_get(h, kWsSt, sizeof(double2) * nb, &werr);
     s.stq = (double2 *)ws_get(h, kWsStq, sizeof(double2) * nb, &werr);
     int32_t *qpos = (int32_t *)ws_get(h, kWsQpos, sizeof(int32_t) * nb, &werr);
@@ -452,6 +462,7 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     s.pp = pp;
     s.geo = geo;
     s.geo2 = geo2;
+    s.qv = qv;
     s.qpos = qpos;
     s.qgeo = qgeo;
     s.state = h->state;
@@ -485,7 +496,7 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     }
     if (nc > 0) {
         hipLaunchKernelGGL(k_pack, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pi, pj, e, arm, q,
-                           (const double *)gamma, pp, geo, geo2, s.st);
+                           (const double *)gamma, pp, geo, geo2, qv, s.st);
         RL_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_pack_q, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, (const int32_t *)qidx,
                            (const double *)geo, (const double2 *)geo2, (const double2 *)s.st, qpos, qgeo, s.stq);
@@ -496,7 +507,7 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
 }
 
 // rod kernel grid: a multiple of 8 so that each XCD gets a contiguous range of rods
-static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodBlock / kRodLanes) + 7) / 8 * 8; }
+static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
 
 template <int MODE>
 static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long long k)
@@ -504,9 +515,9 @@ static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long 
     if (a.n <= 0) return hipSuccess;
     const dim3 grid(rod_grid(a.n));
     if (uni)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodBlock), 0, st, a, k);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodLoopBlock), 0, st, a, k);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false>), grid, dim3(kRodBlock), 0, st, a, k);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false>), grid, dim3(kRodLoopBlock), 0, st, a, k);
     return hipGetLastError();
 }
 
@@ -540,11 +551,11 @@ static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs 
     if (a.n > 0) {
         const dim3 grid(rod_grid(a.n));
         if (uni)
-            hipExtLaunchKernelGGL(k_rod<kModeLoop, true>, grid, dim3(kRodBlock), 0, st, h->ev[v][0], h->ev[v][1], 0,
-                                  a, (long long)it);
+            hipExtLaunchKernelGGL(k_rod<kModeLoop, true>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
+                                  h->ev[v][1], 0, a, (long long)it);
         else
-            hipExtLaunchKernelGGL(k_rod<kModeLoop, false>, grid, dim3(kRodBlock), 0, st, h->ev[v][0], h->ev[v][1],
-                                  0, a, (long long)it);
+            hipExtLaunchKernelGGL(k_rod<kModeLoop, false>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
+                                  h->ev[v][1], 0, a, (long long)it);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
