@@ -96,13 +96,13 @@ def _kernel_summary(prof, kb, names):
 
 def kernel_bytes32(n: int, nc: int) -> dict:
     """Algorithmic bytes per launch of the single-precision loop kernels.
-    rod kernel:        per rod pptr+qptr 8, dir 24, V write 24        -> 56 n
-                       per constraint, P and Q side: state 16 + (e, s) 16 -> 64 nc
-    constraint kernel: per constraint (pi, pj) 8, (e, s_i) 16, s_j 4,
-                       state read 16 + write 16, qpos 4, Q-side state
-                       write 16                                       -> 80 nc
-                       per rod V read 24                              -> 24 n"""
-    return {"rod": 56 * n + 64 * nc, "con": 80 * nc + 24 * n}
+    rod kernel:        per rod pptr+qptr 8, dir 24                    -> 32 n
+                       per constraint, P and Q side: state 16 + (e, s) 16
+                       + contact velocity write 4                     -> 72 nc
+    constraint kernel: per constraint qpos 4, u_P 4, u_Q 4,
+                       state read 16 + write 16, Q-side state
+                       write 16                                       -> 60 nc"""
+    return {"rod": 32 * n + 72 * nc, "con": 60 * nc}
 
 
 def form_precision(args, torch, rl, rodsynth) -> dict:

@@ -112,9 +112,9 @@ struct SolveArgs {
     float4 *st32;           // [nc] (delta, h, b, h0): h approximates g, h0 = g at the last refresh
     float4 *stq32;          // [nc] (delta, h, b, 0) in Q-side list order
     const float4 *geo32;    // [nc] (ex, ey, ez, s_i)
-    const float *sj32;      // [nc] s_j
     const float4 *qgeo32;   // [nc] Q-side list order: (ex, ey, ez, s_j)
-    float *V32;             // [n][8] (V, W, pad)
+    float *uP32;            // [nc] contact velocities of the correction, P side
+    float *uQ32;            // [nc] the same, Q side in list order
 };
 
 // --- kernels launchers (implemented in the .hip files) ----------------------
@@ -169,7 +169,7 @@ enum Slot : int {
     kWsCellOf, kWsCellCnt, kWsCellStart, kWsCellCur, kWsSorted, kWsXs, kWsDs, kWsLs, kWsPcnt, kWsPoff,
     kWsStepPi, kWsStepPj, kWsStepImg, kWsStepFlags, kWsStepPhi, kWsStepE, kWsStepArm, kWsStepQ, kWsStepGamma,
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
-    kWsSt32, kWsStq32, kWsGeo32, kWsSj32, kWsQgeo32, kWsV32,
+    kWsSt32, kWsStq32, kWsGeo32, kWsUP32, kWsQgeo32, kWsUQ32,
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
     kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,

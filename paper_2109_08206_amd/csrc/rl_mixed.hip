@@ -15,7 +15,7 @@
 //
 // The kernels mirror the FP64 ones (rl_solver.hip) with single-precision
 // records: 16-byte (delta, h, b, h0) state and 16-byte (e, s) geometry per
-// incidence instead of 16 + 32 bytes, and 32-byte per-rod velocities.
+// incidence instead of 16 + 32 bytes, and 4-byte contact velocities.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -27,20 +27,18 @@
 namespace rl {
 
 static inline unsigned grid_of(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
-static inline unsigned rod_grid32(int64_t n) { return (grid_of(n, kRodBlock / kRodLanes) + 7) / 8 * 8; }
+static inline unsigned rod_grid32(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
 
 constexpr long long kInnerRoundCap = 4000;  // inner iterations before a forced refresh
 
 // single-precision geometry records from the FP64 ones
-__global__ void k_pack32(int64_t nc, const double *__restrict__ geo, const double2 *__restrict__ geo2,
-                         const double *__restrict__ qgeo, float4 *__restrict__ geo32, float *__restrict__ sj32,
-                         float4 *__restrict__ qgeo32)
+__global__ void k_pack32(int64_t nc, const double *__restrict__ geo, const double *__restrict__ qgeo,
+                         float4 *__restrict__ geo32, float4 *__restrict__ qgeo32)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= nc) return;
     const double *g = geo + 4 * c;
     geo32[c] = make_float4((float)g[0], (float)g[1], (float)g[2], (float)g[3]);
-    sj32[c] = (float)geo2[c].x;
     const double *qg = qgeo + 4 * c;  // list order, same length
     qgeo32[c] = make_float4((float)qg[0], (float)qg[1], (float)qg[2], (float)qg[3]);
 }
@@ -51,14 +49,72 @@ __device__ __forceinline__ float delta_prime(float4 s, float alpha)
     return v > s.z ? v : s.z;
 }
 
-template <bool UNI>
-__global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, int first, long long round_start)
+// one incidence record: state (delta, h, b, h0) and geometry (e, s)
+struct Rec32 {
+    float4 s, g;
+};
+
+__device__ __forceinline__ void rec32_load(const float4 *__restrict__ st, const float4 *__restrict__ geo, int c,
+                                           int end, Rec32 &R)
 {
-    __shared__ double lds[kRodBlock / 64 + 1][4];
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    R.s = R.g = z;
+    if (c < end) {
+        R.s = st[c];
+        R.g = geo[c];
+    }
+}
+
+__device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3], float m[3])
+{
+    const float dv = sign * dp, ds = dv * g.w;
+    f[0] += dv * g.x;
+    f[1] += dv * g.y;
+    f[2] += dv * g.z;
+    m[0] += ds * g.x;
+    m[1] += ds * g.y;
+    m[2] += ds * g.z;
+}
+
+__device__ __forceinline__ void side32(float sign, const float4 *__restrict__ st, const float4 *__restrict__ geo,
+                                       int b, int e, const Rec32 &r1, const Rec32 &r2, float a32, float f[3],
+                                       float m[3])
+{
+    if (b >= e) return;
+    add32(sign, delta_prime(r1.s, a32), r1.g, f, m);
+    const int b2 = b + kRodLanes;
+    if (b2 >= e) return;
+    add32(sign, delta_prime(r2.s, a32), r2.g, f, m);
+    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
+}
+
+__device__ __forceinline__ float u32_along(float4 g, const float v[3], const float w[3])
+{
+    return g.x * (v[0] + g.w * w[0]) + g.y * (v[1] + g.w * w[1]) + g.z * (v[2] + g.w * w[2]);
+}
+
+__device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__restrict__ geo, int b, int e,
+                                       const Rec32 &r1, const Rec32 &r2, const float v[3], const float w[3])
+{
+    if (b >= e) return;
+    u[b] = u32_along(r1.g, v, w);
+    const int b2 = b + kRodLanes;
+    if (b2 >= e) return;
+    u[b2] = u32_along(r2.g, v, w);
+    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) u[c] = u32_along(geo[c], v, w);
+}
+
+// Rod kernel of the inner FP32 iteration: the force of delta' on the rod,
+// then the velocity of each of its contact points along e (contact-velocity
+// form, as in the FP64 rod kernel).
+template <bool UNI>
+__global__ void __launch_bounds__(kRodLoopBlock) k_rod32(SolveArgs a, long long k, int first, long long round_start)
+{
+    __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     SolverState *st = a.state;
     const int sub = threadIdx.x & (kRodLanes - 1);
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < a.n;
     int pb = 0, pe = 0, qb = 0, qe = 0;
     if (active) {
@@ -67,17 +123,12 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
         qb = a.qptr[r] + sub;
         qe = a.qptr[r + 1];
     }
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 ps = z, pg = z, qs = z, qg = z;
-    if (pb < pe) {
-        ps = a.st32[pb];
-        pg = a.geo32[pb];
-    }
-    if (qb < qe) {
-        qs = a.stq32[qb];
-        qg = a.qgeo32[qb];
-    }
-    // the first records are in flight; now the stop and refresh flags
+    // two rounds of both sides in flight before the flags are read
+    Rec32 p1, q1, p2, q2;
+    rec32_load(a.st32, a.geo32, pb, pe, p1);
+    rec32_load(a.stq32, a.qgeo32, qb, qe, q1);
+    rec32_load(a.st32, a.geo32, pb + kRodLanes, pe, p2);
+    rec32_load(a.stq32, a.qgeo32, qb + kRodLanes, qe, q2);
     if (st->done || st->refresh) return;
     double alpha;
     if (first) {
@@ -85,7 +136,7 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
         if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[k & 1] = alpha;
     } else {
         double t[4];
-        sum_partials<kRodBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+        sum_partials<kRodLoopBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
         const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
         int done = 0, refresh = 0, status = RL_OK;
         if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
@@ -122,44 +173,8 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
     }
     const float a32 = (float)alpha;
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    if (pb < pe) {
-        const float dp = delta_prime(ps, a32), ds = dp * pg.w;
-        f[0] += dp * pg.x;
-        f[1] += dp * pg.y;
-        f[2] += dp * pg.z;
-        m[0] += ds * pg.x;
-        m[1] += ds * pg.y;
-        m[2] += ds * pg.z;
-        for (int c = pb + kRodLanes; c < pe; c += kRodLanes) {
-            const float4 s4 = a.st32[c], g4 = a.geo32[c];
-            const float d2 = delta_prime(s4, a32), e2 = d2 * g4.w;
-            f[0] += d2 * g4.x;
-            f[1] += d2 * g4.y;
-            f[2] += d2 * g4.z;
-            m[0] += e2 * g4.x;
-            m[1] += e2 * g4.y;
-            m[2] += e2 * g4.z;
-        }
-    }
-    if (qb < qe) {
-        const float dp = delta_prime(qs, a32), ds = dp * qg.w;
-        f[0] -= dp * qg.x;
-        f[1] -= dp * qg.y;
-        f[2] -= dp * qg.z;
-        m[0] -= ds * qg.x;
-        m[1] -= ds * qg.y;
-        m[2] -= ds * qg.z;
-        for (int c = qb + kRodLanes; c < qe; c += kRodLanes) {
-            const float4 s4 = a.stq32[c], g4 = a.qgeo32[c];
-            const float d2 = delta_prime(s4, a32), e2 = d2 * g4.w;
-            f[0] -= d2 * g4.x;
-            f[1] -= d2 * g4.y;
-            f[2] -= d2 * g4.z;
-            m[0] -= e2 * g4.x;
-            m[1] -= e2 * g4.y;
-            m[2] -= e2 * g4.z;
-        }
-    }
+    side32(1.f, a.st32, a.geo32, pb, pe, p1, p2, a32, f, m);
+    side32(-1.f, a.stq32, a.qgeo32, qb, qe, q1, q2, a32, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -168,7 +183,7 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
             m[d] += __shfl_xor(m[d], o, 64);
         }
     }
-    if (!active || sub >= 2) return;
+    if (!active) return;
     const float dx = (float)a.dir[3 * r], dy = (float)a.dir[3 * r + 1], dz = (float)a.dir[3 * r + 2];
     float apar, aperp, rperp;
     if (UNI) {
@@ -182,46 +197,31 @@ __global__ void __launch_bounds__(kRodBlock) k_rod32(SolveArgs a, long long k, i
     }
     const float fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
     const float md = dx * m[0] + dy * m[1] + dz * m[2];
-    float *out = a.V32 + 8 * r;
-    if (sub == 0)
-        *reinterpret_cast<float4 *>(out) =
-            make_float4(aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz, rperp * (m[0] - md * dx));
-    else
-        *reinterpret_cast<float2 *>(out + 4) = make_float2(rperp * (m[1] - md * dy), rperp * (m[2] - md * dz));
+    const float v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
+    const float w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
+    emit32(a.uP32, a.geo32, pb, pe, p1, p2, v, w);
+    emit32(a.uQ32, a.qgeo32, qb, qe, q1, q2, v, w);
 }
 
 struct Con32Loads {
-    float4 g, s;
-    float sj;
+    float4 s;
+    float up, uq;
     int qp;
-    float4 vi, vj;
-    float2 wi, wj;
 };
 
 __device__ __forceinline__ void con32_load(const SolveArgs &a, int64_t c, Con32Loads &L)
 {
-    const int2 ij = a.pp[c];
-    L.g = a.geo32[c];
-    L.sj = a.sj32[c];
-    L.s = a.st32[c];
     L.qp = a.qpos[c];
-    const float *Vi = a.V32 + 8 * (int64_t)ij.x;
-    const float *Vj = a.V32 + 8 * (int64_t)ij.y;
-    L.vi = *reinterpret_cast<const float4 *>(Vi);
-    L.wi = *reinterpret_cast<const float2 *>(Vi + 4);
-    L.vj = *reinterpret_cast<const float4 *>(Vj);
-    L.wj = *reinterpret_cast<const float2 *>(Vj + 4);
+    L.up = a.uP32[c];
+    L.s = a.st32[c];
+    L.uq = a.uQ32[L.qp];
 }
 
 __device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, const Con32Loads &L, float a32,
                                              double p[4])
 {
-    const float si = L.g.w, sj = L.sj;
-    // V = (vx, vy, vz), W = (wx, wy, wz) packed as (vx, vy, vz, wx), (wy, wz)
-    const float ux = (L.vi.x + si * L.vi.w) - (L.vj.x + sj * L.vj.w);
-    const float uy = (L.vi.y + si * L.wi.x) - (L.vj.y + sj * L.wj.x);
-    const float uz = (L.vi.z + si * L.wi.y) - (L.vj.z + sj * L.wj.y);
-    const float h = L.s.w + (L.g.x * ux + L.g.y * uy + L.g.z * uz);
+    // h = h0 + Mc32 delta, the rate being the difference of the two contact velocities
+    const float h = L.s.w + (L.up - L.uq);
     const float dp = delta_prime(L.s, a32);
     a.st32[c] = make_float4(dp, h, L.s.z, L.s.w);
     a.stq32[L.qp] = make_float4(dp, h, L.s.z, 0.f);
@@ -268,20 +268,19 @@ __global__ void __launch_bounds__(kConBlock) k_con32(SolveArgs a, long long k)
 int prepare_mixed(rl_ctx *h, SolveArgs &a)
 {
     int werr = 0;
-    const int64_t nb = a.nc > 0 ? a.nc : 1, rb = a.n > 0 ? a.n : 1;
+    const int64_t nb = a.nc > 0 ? a.nc : 1;
     a.st32 = (float4 *)ws_get(h, kWsSt32, sizeof(float4) * nb, &werr);
     a.stq32 = (float4 *)ws_get(h, kWsStq32, sizeof(float4) * nb, &werr);
     float4 *geo32 = (float4 *)ws_get(h, kWsGeo32, sizeof(float4) * nb, &werr);
-    float *sj32 = (float *)ws_get(h, kWsSj32, sizeof(float) * nb, &werr);
     float4 *qgeo32 = (float4 *)ws_get(h, kWsQgeo32, sizeof(float4) * nb, &werr);
-    a.V32 = (float *)ws_get(h, kWsV32, sizeof(float) * 8 * rb, &werr);
+    a.uP32 = (float *)ws_get(h, kWsUP32, sizeof(float) * nb, &werr);
+    a.uQ32 = (float *)ws_get(h, kWsUQ32, sizeof(float) * nb, &werr);
     if (werr) return werr;
     a.geo32 = geo32;
-    a.sj32 = sj32;
     a.qgeo32 = qgeo32;
     if (a.nc > 0) {
-        hipLaunchKernelGGL(k_pack32, dim3(grid_of(a.nc, kBlock)), dim3(kBlock), 0, h->stream, a.nc, a.geo, a.geo2, a.qgeo,
-                           geo32, sj32, qgeo32);
+        hipLaunchKernelGGL(k_pack32, dim3(grid_of(a.nc, kBlock)), dim3(kBlock), 0, h->stream, a.nc, a.geo, a.qgeo,
+                           geo32, qgeo32);
         RL_HIP(hipGetLastError());
     }
     return RL_OK;
@@ -325,20 +324,20 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                     if (!h->ev[nev][e]) RL_HIP(hipEventCreateWithFlags(&h->ev[nev][e], hipEventDisableSystemFence));
                 h->ev_iter[nev] = k;
                 if (uni)
-                    hipExtLaunchKernelGGL(k_rod32<true>, rgrid, dim3(kRodBlock), 0, st, h->ev[nev][0],
+                    hipExtLaunchKernelGGL(k_rod32<true>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
                                           h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
                 else
-                    hipExtLaunchKernelGGL(k_rod32<false>, rgrid, dim3(kRodBlock), 0, st, h->ev[nev][0],
+                    hipExtLaunchKernelGGL(k_rod32<false>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
                                           h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
                 hipExtLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, h->ev[nev][2], h->ev[nev][3],
                                       0, a, (long long)k);
                 ++nev;
             } else {
                 if (uni)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodLoopBlock), 0, st, a, k, fl,
                                        round_start);
                 else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodBlock), 0, st, a, k, fl,
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodLoopBlock), 0, st, a, k, fl,
                                        round_start);
                 hipLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
             }
