@@ -56,6 +56,7 @@ struct BatchArgs {
 };
 
 static const int kBatchRodBlocks[2] = {256, 1024};
+constexpr int kComputeUnits = 256;  // MI355X
 static const int kBatchConBlocks[2] = {256, 512};
 
 // stop of system s: results for the host, the flag, the count
@@ -541,6 +542,11 @@ int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *
             for (int s = 0; s < S; ++s)
                 if (!done_host[s]) live += tab.sc0[s + 1] - tab.sc0[s];
             if (2 * live < b.ncb) {
+                // Once fewer constraint tiles than compute units are left (the
+                // tail of a few slow systems), tuned rod groups give way to the
+                // smallest, for more workgroups on the little work that remains
+                // (the rod tiling carries no state between iterations).
+                if (h->batch_rb == 0 && live < kComputeUnits) rb = kBatchRodBlocks[0];
                 // carry the last iteration's partials of the live systems to the new tiles
                 BatchTables nt;
                 build_tables(S, rod_off, pair_off, rb, cb, nt, &done_host);

@@ -170,14 +170,14 @@ __device__ __forceinline__ double gamma_prime(double gam, double g, double alpha
 // Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
 // rod r, split over the kRodLanes lanes of the rod and combined by a fixed
 // tree.  The torque on the rod is dir x m.  A lane takes the records sub,
-// sub + kRodLanes, ... of each side.  Its first two rounds of both sides are
-// loaded into registers (the first always before the step-length wait, the
-// second before it too when kRodPreload2 is set); longer lists continue in a
-// loop.  The registers stay live for the contact-velocity emission.
-#ifndef RL_ROD_PRELOAD2
-#define RL_ROD_PRELOAD2 1
+// sub + kRodLanes, ... of each side.  Its first kRodRounds records of both
+// sides are loaded into registers together, before the step-length wait;
+// longer lists continue in a loop.  The registers stay live for the
+// contact-velocity emission.
+#ifndef RL_ROD_ROUNDS
+#define RL_ROD_ROUNDS 2
 #endif
-constexpr bool kRodPreload2 = RL_ROD_PRELOAD2 != 0;
+constexpr int kRodRounds = RL_ROD_ROUNDS;
 
 struct RodRec {
     double2 s, g0, g1;  // (gamma, g), (ex, ey), (ez, s)
@@ -185,7 +185,7 @@ struct RodRec {
 
 struct RodLoads {
     int pb, pe, qb, qe;
-    RodRec p1, q1, p2, q2;  // rounds 1 and 2 of the P and Q sides
+    RodRec p[kRodRounds], q[kRodRounds];  // the first rounds of the P and Q sides
 };
 
 __device__ __forceinline__ void rod_rec_load(const double2 *st, const double *geo, int c, int end, RodRec &R)
@@ -200,12 +200,6 @@ __device__ __forceinline__ void rod_rec_load(const double2 *st, const double *ge
     }
 }
 
-__device__ __forceinline__ void rod_load_round2(const SolveArgs &a, RodLoads &L)
-{
-    rod_rec_load(a.st, a.geo, L.pb + kRodLanes, L.pe, L.p2);
-    rod_rec_load(a.stq, a.qgeo, L.qb + kRodLanes, L.qe, L.q2);
-}
-
 __device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
 {
     L.pb = L.pe = L.qb = L.qe = 0;
@@ -215,9 +209,11 @@ __device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool act
         L.qb = a.qptr[r] + sub;
         L.qe = a.qptr[r + 1];
     }
-    rod_rec_load(a.st, a.geo, L.pb, L.pe, L.p1);
-    rod_rec_load(a.stq, a.qgeo, L.qb, L.qe, L.q1);
-    if (kRodPreload2) rod_load_round2(a, L);
+#pragma unroll
+    for (int i = 0; i < kRodRounds; ++i) {
+        rod_rec_load(a.st, a.geo, L.pb + i * kRodLanes, L.pe, L.p[i]);
+        rod_rec_load(a.stq, a.qgeo, L.qb + i * kRodLanes, L.qe, L.q[i]);
+    }
 }
 
 // f += +-gamma' e, m += +-gamma' s e for one incidence record
@@ -234,14 +230,14 @@ __device__ __forceinline__ void rod_add(double sign, double gm, double2 g0, doub
 
 template <int MODE>
 __device__ __forceinline__ void rod_side(double sign, const double2 *st, const double *geo, int b, int e,
-                                         const RodRec &r1, const RodRec &r2, double alpha, double f[3], double m[3])
+                                         const RodRec *rr, double alpha, double f[3], double m[3])
 {
-    if (b >= e) return;
-    rod_add(sign, gamma_prime<MODE>(r1.s.x, r1.s.y, alpha), r1.g0, r1.g1, f, m);
-    const int b2 = b + kRodLanes;
-    if (b2 >= e) return;
-    rod_add(sign, gamma_prime<MODE>(r2.s.x, r2.s.y, alpha), r2.g0, r2.g1, f, m);
-    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) {
+#pragma unroll
+    for (int i = 0; i < kRodRounds; ++i) {
+        if (b + i * kRodLanes >= e) return;
+        rod_add(sign, gamma_prime<MODE>(rr[i].s.x, rr[i].s.y, alpha), rr[i].g0, rr[i].g1, f, m);
+    }
+    for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
         const double2 sg = st[c];
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
         rod_add(sign, gamma_prime<MODE>(sg.x, sg.y, alpha), gd[0], gd[1], f, m);
@@ -249,13 +245,12 @@ __device__ __forceinline__ void rod_side(double sign, const double2 *st, const d
 }
 
 template <int MODE>
-__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, RodLoads &L, double alpha, double f[3],
+__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads &L, double alpha, double f[3],
                                                double m[3])
 {
     f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    if (!kRodPreload2) rod_load_round2(a, L);
-    rod_side<MODE>(1.0, a.st, a.geo, L.pb, L.pe, L.p1, L.p2, alpha, f, m);
-    rod_side<MODE>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.q1, L.q2, alpha, f, m);
+    rod_side<MODE>(1.0, a.st, a.geo, L.pb, L.pe, L.p, alpha, f, m);
+    rod_side<MODE>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.q, alpha, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -337,17 +332,18 @@ __device__ __forceinline__ double u_along(double2 g0, double2 g1, const double v
     return g0.x * (v[0] + s * w[0]) + g0.y * (v[1] + s * w[1]) + g1.x * (v[2] + s * w[2]);
 }
 
-// The lane's incidences in the same order as rod_accumulate: the first two
-// rounds are still in registers, later ones (rare) are read again.
-__device__ __forceinline__ void emit_side(double *u, const double *geo, int b, int e, const RodRec &r1,
-                                          const RodRec &r2, const double v[3], const double w[3])
+// The lane's incidences in the same order as rod_accumulate: the first
+// rounds are still in registers, later ones are read again (moments after
+// the same lane read them).
+__device__ __forceinline__ void emit_side(double *u, const double *geo, int b, int e, const RodRec *rr,
+                                          const double v[3], const double w[3])
 {
-    if (b >= e) return;
-    u[b] = u_along(r1.g0, r1.g1, v, w);
-    const int b2 = b + kRodLanes;
-    if (b2 >= e) return;
-    u[b2] = u_along(r2.g0, r2.g1, v, w);
-    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) {
+#pragma unroll
+    for (int i = 0; i < kRodRounds; ++i) {
+        if (b + i * kRodLanes >= e) return;
+        u[b + i * kRodLanes] = u_along(rr[i].g0, rr[i].g1, v, w);
+    }
+    for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
         u[c] = u_along(gd[0], gd[1], v, w);
     }
@@ -355,8 +351,8 @@ __device__ __forceinline__ void emit_side(double *u, const double *geo, int b, i
 
 __device__ __forceinline__ void rod_emit_u(const SolveArgs &a, const RodLoads &L, const double v[3], const double w[3])
 {
-    emit_side(a.uP, a.geo, L.pb, L.pe, L.p1, L.p2, v, w);
-    emit_side(a.uQ, a.qgeo, L.qb, L.qe, L.q1, L.q2, v, w);
+    emit_side(a.uP, a.geo, L.pb, L.pe, L.p, v, w);
+    emit_side(a.uQ, a.qgeo, L.qb, L.qe, L.q, v, w);
 }
 
 struct ConLoadsU {
