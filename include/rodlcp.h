@@ -293,6 +293,28 @@ int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat,
 int rl_profile_enable(rl_handle h, int every);
 int rl_profile_read(rl_handle h, double *out);
 
+/* How the FP64 BBPGD loop of rl_solve_lcp / rl_step runs (the iteration of
+ * Section "Instantiation in a massively parallel computing environment"; the
+ * arithmetic per constraint and per rod is the same, only the schedule and
+ * the order of the step-length partial sums differ):
+ *   RL_LOOP_LAUNCH     two kernel launches per iteration (the default);
+ *   RL_LOOP_PERSISTENT one cooperative launch per solve: one workgroup per
+ *                      compute unit owns a block of rods and keeps their
+ *                      incidence geometry in LDS, two grid barriers per
+ *                      iteration.  The solve returns RL_ERR_ARG when the rods
+ *                      do not split into such blocks (the geometry of the
+ *                      largest block must fit 156 KB of LDS).
+ * RL_FP32_MIXED, the batched and the adjoint solves always launch per
+ * iteration.  RL_ERR_ARG on another value. */
+#define RL_LOOP_LAUNCH 0
+#define RL_LOOP_PERSISTENT 1
+int rl_set_loop(rl_handle h, int mode);
+
+/* Timing of the persistent loop, for measurement: writes {ms_total,
+ * iterations_total, launches} of the persistent launches since the last call
+ * (HIP events around each launch) to out[3] (host) and resets them. */
+int rl_profile_read_loop(rl_handle h, double *out);
+
 #ifdef __cplusplus
 }
 #endif

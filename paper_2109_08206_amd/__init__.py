@@ -22,6 +22,7 @@ OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
 ERR_ARG, ERR_CAPACITY, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = -1, -2, -3, -4, -5
 FP64, FP32_MIXED = 0, 1
 TAPE_NONE, TAPE_RECORD, TAPE_REPLAY = 0, 1, 2
+LOOP_LAUNCH, LOOP_PERSISTENT = 0, 1
 IMG_ZERO = 0x888
 
 _lib = None
@@ -54,7 +55,7 @@ class AdjointInfo(C.Structure):
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
-           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint")
+           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_set_loop", "rl_profile_read_loop")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -92,6 +93,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_solve_lcp_adjoint": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, D, P, P, P, P, P,
                                       C.POINTER(AdjointInfo)], C.c_int),
             "rl_step_adjoint": ([H, I64, P, P, P, D, P, P, I64, P, P, P, D, C.POINTER(AdjointInfo)], C.c_int),
+            "rl_set_loop": ([H, C.c_int], C.c_int),
+            "rl_profile_read_loop": ([H, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -163,12 +166,18 @@ class Solver:
     """One library handle: parameters, stream and workspace."""
 
     def __init__(self, box, diam=0.025, cutoff=0.05, eta=0.01, dt=1e-4, tol=1e-8, max_iter=100_000,
-                 precision=FP64, check_every=0):
+                 precision=FP64, check_every=0, loop=None):
         self.lib = load()
         self._h = C.c_void_p()
         self.params = Params()
         self.set_params(box=box, diam=diam, cutoff=cutoff, eta=eta, dt=dt, tol=tol, max_iter=max_iter,
                         precision=precision, check_every=check_every, _create=True)
+        if loop is not None:
+            self.set_loop(loop)
+
+    def set_loop(self, mode: int):
+        """LOOP_LAUNCH (default) or LOOP_PERSISTENT: schedule of the FP64 loop."""
+        self._check(self.lib.rl_set_loop(self._h, int(mode)), "rl_set_loop")
 
     # -- lifecycle ------------------------------------------------------------
     def set_params(self, _create=False, **kw):
@@ -218,6 +227,12 @@ class Solver:
         out = (C.c_double * 4)()
         self._check(self.lib.rl_profile_read(self._h, out), "rl_profile_read")
         return {"rod_ms": out[0], "rod_launches": int(out[1]), "con_ms": out[2], "con_launches": int(out[3])}
+
+    def profile_read_loop(self):
+        """{'ms', 'iterations', 'launches'} of the persistent loop since the last read."""
+        out = (C.c_double * 3)()
+        self._check(self.lib.rl_profile_read_loop(self._h, out), "rl_profile_read_loop")
+        return {"ms": out[0], "iterations": int(out[1]), "launches": int(out[2])}
 
     def reserve(self, max_rods, max_pairs):
         self._check(self.lib.rl_reserve(self._h, int(max_rods), int(max_pairs)), "rl_reserve")

@@ -177,6 +177,8 @@ int rl_destroy(rl_handle h)
     for (int v = 0; v < rl_ctx::kMaxEv; ++v)
         for (int k = 0; k < 4; ++k)
             if (h->ev[v][k]) (void)hipEventDestroy(h->ev[v][k]);
+    for (int k = 0; k < 2; ++k)
+        if (h->pev[k]) (void)hipEventDestroy(h->pev[k]);
     for (int s = 0; s < rl_ctx::kSlots; ++s)
         if (h->buf[s]) (void)hipFree(h->buf[s]);
     if (h->state) (void)hipFree(h->state);
@@ -524,6 +526,25 @@ int rl_profile_enable(rl_handle h, int every)
     RL_CHECK_HANDLE(h);
     RL_REQUIRE(every >= 0, "rl_profile_enable: every < 0");
     h->prof_every = every;
+    return RL_OK;
+}
+
+int rl_set_loop(rl_handle h, int mode)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(mode == RL_LOOP_LAUNCH || mode == RL_LOOP_PERSISTENT, "rl_set_loop: unknown mode");
+    h->loop_mode = mode;
+    return RL_OK;
+}
+
+int rl_profile_read_loop(rl_handle h, double *out)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(out != nullptr, "rl_profile_read_loop: NULL out");
+    out[0] = h->persist_ms;
+    out[1] = h->persist_iters;
+    out[2] = h->persist_launches;
+    h->persist_ms = h->persist_iters = h->persist_launches = 0.0;
     return RL_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/rodlcp.h"
 
@@ -152,6 +153,10 @@ struct rl_ctx {
     long long ev_iter[kMaxEv] = {};
     double prof_ms[2] = {0.0, 0.0};
     double prof_cnt[2] = {0.0, 0.0};
+    // persistent loop: its launch events, time and iterations since the last read
+    hipEvent_t pev[2] = {};
+    double persist_ms = 0.0, persist_iters = 0.0, persist_launches = 0.0;
+    int loop_mode = RL_LOOP_LAUNCH;
     // batched solves: a stream of our own (graph capture), workgroup sizes
     hipStream_t own_stream = nullptr;
     int batch_rb = 0, batch_cb = 0;            // fixed by the caller; 0 = tune
@@ -174,6 +179,7 @@ enum Slot : int {
     kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs, kWsQv, kWsUP, kWsUQ,
+    kWsPersistMap, kWsPersistBar, kWsPersistPart,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -218,6 +224,15 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes);
 // FP64 refresh for the mixed solver: gamma64 += delta (if accum), g64 = Mc gamma64 + q,
 // certified residual, FP32 state reset
 hipError_t launch_refresh64(rl_ctx *h, const SolveArgs &a, bool accum);
+// persistent FP64 loop (rl_persist.hip): the rods' split into one block per
+// compute unit, and the loop itself (after the start phases)
+struct PersistPlan {
+    bool ok = false;
+    int G = 0, cap = 0, rmax = 0;
+    std::vector<int> wr0;  // [G+1] first rod of each block
+};
+int persistent_plan(rl_ctx *h, const SolveArgs &a, PersistPlan *plan);
+int solve_loop_persistent(rl_ctx *h, const SolveArgs &a, const PersistPlan &plan, float *ms);
 hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a);
 hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U);
 hipError_t launch_velocity_on(hipStream_t st, const SolveArgs &a, const double *F, const int *perm, double *U);

@@ -593,8 +593,25 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         RL_HIP(launch_con<kModeAlpha0>(st, a, 0));
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
         RL_HIP(hipGetLastError());
+        PersistPlan plan;
+        if (h->loop_mode == RL_LOOP_PERSISTENT) {
+            int rc = persistent_plan(h, a, &plan);
+            if (rc) return rc;
+            if (!plan.ok) {
+                set_error("rl_solve_lcp: the persistent loop does not fit this problem");
+                return RL_ERR_ARG;
+            }
+        }
         const int every = p.check_every > 0 ? p.check_every : 32;
-        for (long long launched = 0;; launched += every) {
+        if (plan.ok) {
+            float ms = 0.f;
+            int rc = solve_loop_persistent(h, a, plan, &ms);
+            if (rc) return rc;
+            h->persist_ms += ms;
+            h->persist_iters += (double)h->state_host->iter;
+            h->persist_launches += 1.0;
+        }
+        for (long long launched = 0; !plan.ok; launched += every) {
             if (launched > p.max_iter + every) {
                 set_error("rl_solve_lcp: stop flag never raised");
                 return RL_ERR_HIP;
