@@ -179,6 +179,7 @@ int rl_destroy(rl_handle h)
             if (h->ev[v][k]) (void)hipEventDestroy(h->ev[v][k]);
     for (int k = 0; k < 2; ++k)
         if (h->pev[k]) (void)hipEventDestroy(h->pev[k]);
+    if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
     for (int s = 0; s < rl_ctx::kSlots; ++s)
         if (h->buf[s]) (void)hipFree(h->buf[s]);
     if (h->state) (void)hipFree(h->state);

@@ -155,6 +155,7 @@ struct rl_ctx {
     double prof_cnt[2] = {0.0, 0.0};
     // persistent loop: its launch events, time and iterations since the last read
     hipEvent_t pev[2] = {};
+    hipEvent_t chk_ev = nullptr;  // marks the state copy of a stop-flag check
     double persist_ms = 0.0, persist_iters = 0.0, persist_launches = 0.0;
     int loop_mode = RL_LOOP_LAUNCH;
     // batched solves: a stream of our own (graph capture), workgroup sizes

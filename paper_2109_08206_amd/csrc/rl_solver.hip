@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "rl_device.hpp"
 
@@ -578,6 +579,103 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         if (rc) return rc;
         rc = solve_mixed_impl(h, a, &refreshes);
         if (rc) return rc;
+        iters = h->state_host->iter;
+        if (gamma_out) {
+            hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
+                               (const double2 *)a.st, gamma_out);
+            RL_HIP(hipGetLastError());
+        }
+    } else if (a.nc > 0) {
+        RL_HIP(launch_rod<kModeInit>(st, a, uni, 0));
+        RL_HIP(launch_con<kModeInit>(st, a, 0));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeInit>), dim3(1), dim3(kRodBlock), 0, st, a);
+        RL_HIP(hipGetLastError());
+        RL_HIP(launch_rod<kModeAlpha0>(st, a, uni, 0));
+        RL_HIP(launch_con<kModeAlpha0>(st, a, 0));
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
+        RL_HIP(hipGetLastError());
+        PersistPlan plan;
+        if (h->loop_mode == RL_LOOP_PERSISTENT) {
+            int rc = persistent_plan(h, a, &plan);
+            if (rc) return rc;
+            if (!plan.ok) {
+                set_error("rl_solve_lcp: the persistent loop does not fit this problem");
+                return RL_ERR_ARG;
+            }
+        }
+        const int every = p.check_every > 0 ? p.check_every : 32;
+        if (plan.ok) {
+            float ms = 0.f;
+            int rc = solve_loop_persistent(h, a, plan, &ms);
+            if (rc) return rc;
+            h->persist_ms += ms;
+            h->persist_iters += (double)h->state_host->iter;
+            h->persist_launches += 1.0;
+        }
+        // Host checks of the stop flag: after each batch of `every` iterations the
+        // state is copied back while `la` more are already queued, so the GPU does
+        // not wait for the host; iterations queued past the stop exit at once.
+        const int la = std::min(every, 8);
+        long long launched = 0;
+        std::vector<int> pend;  // event slots of sampled iterations not yet read
+        bool used[rl_ctx::kMaxEv] = {};
+        auto enqueue = [&](long long count) -> int {
+            for (long long k = 0; k < count; ++k, ++launched) {
+                int slot = -1;
+                if (h->prof_every > 0 && launched % h->prof_every == 0)
+                    for (int v = 0; v < rl_ctx::kMaxEv && slot < 0; ++v)
+                        if (!used[v]) slot = v;
+                if (slot >= 0) {
+                    RL_HIP(record_sample(h, slot, launched, a, uni));
+                    used[slot] = true;
+                    pend.push_back(slot);
+                } else {
+                    RL_HIP(launch_rod<kModeLoop>(st, a, uni, launched));
+                    RL_HIP(launch_con<kModeLoop>(st, a, launched));
+                }
+            }
+            return RL_OK;
+        };
+        if (!plan.ok) {
+            if (!h->chk_ev) RL_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
+            int rc = enqueue(every);
+            if (rc) return rc;
+            for (;;) {
+                RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+                RL_HIP(hipEventRecord(h->chk_ev, st));
+                const long long checked = launched;
+                if ((rc = enqueue(la))) return rc;
+                RL_HIP(hipEventSynchronize(h->chk_ev));
+                const bool done = h->state_host->done;
+                // samples before the check have run; those at or after the stop
+                // iteration ran kernels that exited at once
+                const long long valid = done ? h->state_host->iter : checked;
+                std::vector<int> keep;
+                for (int v : pend) {
+                    if (h->ev_iter[v] >= checked) {
+                        keep.push_back(v);
+                        continue;
+                    }
+                    if (h->ev_iter[v] < valid) {
+                        float t0 = 0.f, t1 = 0.f;
+                        if (a.n > 0) RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
+                        RL_HIP(hipEventElapsedTime(&t1, h->ev[v][2], h->ev[v][3]));
+                        h->prof_ms[0] += t0;
+                        h->prof_ms[1] += t1;
+                        h->prof_cnt[0] += 1.0;
+                        h->prof_cnt[1] += 1.0;
+                    }
+                    used[v] = false;
+                }
+                pend.swap(keep);
+                if (done) break;
+                if (checked > p.max_iter + every) {
+                    set_error("rl_solve_lcp: stop flag never raised");
+                    return RL_ERR_HIP;
+                }
+                if ((rc = enqueue(every - la))) return rc;
+            }
+        }
         iters = h->state_host->iter;
         if (gamma_out) {
             hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
