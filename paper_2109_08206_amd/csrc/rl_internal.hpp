@@ -82,6 +82,10 @@ constexpr int kRodLoopBlock = RL_ROD_LOOP_BLOCK;  // workgroup of the single-sol
 #endif
 constexpr int kConBlock = RL_CON_BLOCK;     // constraint kernel workgroup
 constexpr int kConGridMax = RL_CON_GRIDMAX; // constraint kernel grid cap (grid-stride beyond)
+#ifndef RL_CON_PER_GROUP
+#define RL_CON_PER_GROUP 2048
+#endif
+constexpr int kConPerGroup = RL_CON_PER_GROUP;  // target constraints per constraint workgroup
 constexpr int kConCpl = RL_CON_CPL;         // constraints per lane per round, loaded together
 
 // Arguments shared by the solver kernels (passed by value).

@@ -433,8 +433,11 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     s.nc = nc;
     s.dir = dir;
     s.mob = mobility_host(len ? 1.0 : len0, p.diam, p.eta);
-    // constraint workgroups: about two constraints per lane, at most kConGridMax, a multiple of 8 (XCDs)
-    int64_t gc = std::min<int64_t>(std::max<int64_t>(grid_of(nc, kConCpl * kConBlock), 1), kConGridMax);
+    // constraint workgroups: about kConPerGroup constraints each (every rod
+    // workgroup of the next iteration sums one partial per constraint
+    // workgroup, so fewer and fuller groups make that sum cheaper), at most
+    // kConGridMax, a multiple of 8 (XCDs)
+    int64_t gc = std::min<int64_t>(std::max<int64_t>(grid_of(nc, kConPerGroup), 1), kConGridMax);
     s.gcon = (int)((gc + 7) / 8 * 8);
     const int64_t nb = nc > 0 ? nc : 1, rb = n > 0 ? n : 1;
     int32_t *pptr = (int32_t *)ws_get(h, kWsPptr, sizeof(int32_t) * (n + 1), &werr);
