@@ -314,14 +314,12 @@ int persistent_plan(rl_ctx *h, const SolveArgs &a, PersistPlan *plan)
     hipDeviceProp_t prop;
     RL_HIP(hipGetDeviceProperties(&prop, dev));
     if (!prop.cooperativeLaunch) return RL_OK;
-    static bool attr_set = false;
-    if (!attr_set) {
-        RL_HIP(hipFuncSetAttribute((const void *)k_persist<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   kPLdsBytes));
-        RL_HIP(hipFuncSetAttribute((const void *)k_persist<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   kPLdsBytes));
-        attr_set = true;
-    }
+    // the kernels may use more than the default 64 KB of dynamic LDS (a
+    // setting of the current device; repeating it is harmless)
+    RL_HIP(hipFuncSetAttribute((const void *)k_persist<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kPLdsBytes));
+    RL_HIP(hipFuncSetAttribute((const void *)k_persist<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kPLdsBytes));
     int per_cu = 0;
     RL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist<true>, kPBlock,
                                                         kPLdsBytes));
