@@ -39,14 +39,13 @@ struct BatchArgs {
     SolveArgs a;             // the concatenated system
     SolverState *sst;        // [S]
     double *alpha_s;         // [S][2]
-    const int *rblk_sys;     // rod tiles: system, first rod, end rod
-    const int *rblk_lo;
-    const int *rblk_hi;
-    const int *cblk_sys;     // constraint tiles: system, first constraint, end
-    const int *cblk_lo;
-    const int *cblk_hi;
+    // Tile records, one load each: rod tile t is rt[2t] = (first rod, end
+    // rod, system, publishes) and rt[2t+1] = (the system's first and end
+    // constraint tile, 0, 0); constraint tile t is ct[t] = (first constraint,
+    // end, system, 0).
+    const int4 *rt;
+    const int4 *ct;
     const int *sys_c0;       // [S+1] first constraint tile of each system
-    const int *sys_r0;       // [S] first rod tile of each system (publishes)
     int nrb, ncb;            // tiles (the grids are padded to multiples of 8)
     int S;
     double *partial;         // [2][ncb][4]
@@ -81,26 +80,28 @@ __global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     if ((int)tile >= b.nrb) return;
     const int sub = threadIdx.x & (kRodLanes - 1);
-    const int64_t r = (int64_t)b.rblk_lo[tile] + threadIdx.x / kRodLanes;
-    const bool active = r < b.rblk_hi[tile];
+    const int4 t0 = b.rt[2 * tile], t1 = b.rt[2 * tile + 1];
+    const int64_t r = (int64_t)t0.x + threadIdx.x / kRodLanes;
+    const bool active = r < t0.y;
     // records first: they depend neither on the system's state nor on its step
     RodLoads L;
     rod_load(b.a, r, active, sub, L);
-    const int s = b.rblk_sys[tile];
+    const int s = t0.z;
     SolverState *st = b.sst + s;
     if (MODE != kModeApply && st->done) return;
     const long long k = MODE == kModeLoop ? *b.kbase + i : 0;
     double alpha = 0.0;
     if (MODE == kModeLoop) {
-        const bool publisher = (int)tile == b.sys_r0[s] && threadIdx.x == 0;
+        const bool publisher = t0.w && threadIdx.x == 0;
         double *abuf = b.alpha_s + 2 * s;
         if (k == 0) {
             alpha = st->alpha;
             if (publisher) abuf[0] = alpha;
         } else {
+            // the counter base is even, so the parity of k is that of i: the
+            // partials' address does not wait for the counter
             double t[4];
-            const int c0 = b.sys_c0[s], c1 = b.sys_c0[s + 1];
-            sum_partials<RB / 64>(b.partial + ((int64_t)((k - 1) & 1) * b.ncb + c0) * 4, c1 - c0, t, lds);
+            sum_partials<RB / 64>(b.partial + ((int64_t)((i - 1) & 1) * b.ncb + t1.x) * 4, t1.y - t1.x, t, lds);
             const Decision d = decide(st, abuf, k, t);
             if (publisher) {
                 if (d.stop) latch(b, s, k, t, d.status);
@@ -131,18 +132,20 @@ __global__ void __launch_bounds__(CB) k_con_b(BatchArgs b, int i)
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     if ((int)tile >= b.ncb) return;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t hi = b.cblk_hi[tile];
+    const int4 tc = b.ct[tile];
+    const int64_t hi = tc.y;
     // first round peeled: its records are in flight before the system's stop
     // flag and step are read (every thread reaches the test)
-    int64_t c0 = b.cblk_lo[tile] + threadIdx.x;
+    int64_t c0 = tc.x + threadIdx.x;
     ConLoadsU A, B;
     if (c0 < hi) con_load_u<MODE>(b.a, c0, A);
     if (c0 + CB < hi) con_load_u<MODE>(b.a, c0 + CB, B);
-    const int s = b.cblk_sys[tile];
+    const int s = tc.z;
     SolverState *st = b.sst + s;
     if (MODE != kModeApply && st->done) return;
-    const long long k = MODE == kModeLoop ? *b.kbase + i : 0;
-    const double alpha = MODE == kModeLoop ? b.alpha_s[2 * s + (k & 1)] : 0.0;
+    // parity of the iteration = parity of i (the counter base is even)
+    const int par = MODE == kModeLoop ? (i & 1) : 0;
+    const double alpha = MODE == kModeLoop ? b.alpha_s[2 * s + par] : 0.0;
     for (;;) {
         if (c0 < hi) con_update_u<MODE>(b.a, c0, A, alpha, p);
         if (c0 + CB < hi) con_update_u<MODE>(b.a, c0 + CB, B, alpha, p);
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(CB) k_con_b(BatchArgs b, int i)
     if (MODE == kModeApply) return;
     block_reduce4_all<CB / 64>(p, lds);
     if (threadIdx.x == 0) {
-        double2 *dst = reinterpret_cast<double2 *>(b.partial + ((int64_t)(k & 1) * b.ncb + tile) * 4);
+        double2 *dst = reinterpret_cast<double2 *>(b.partial + ((int64_t)par * b.ncb + tile) * 4);
         dst[0] = make_double2(p[0], p[1]);
         dst[1] = make_double2(p[2], p[3]);
     }
@@ -339,25 +342,32 @@ static int upload_tables(rl_ctx *h, hipStream_t st, const BatchTables &t, int S,
 {
     int werr = 0;
     const size_t nr = std::max<size_t>(t.rsys.size(), 1), ncb = std::max<size_t>(t.csys.size(), 1);
-    const size_t words = 3 * nr + 3 * ncb + (S + 1) + S;
+    // int4 records first (16-byte aligned), then the per-system tile starts
+    const size_t words = 4 * (2 * nr + ncb) + (S + 1);
     int *tab = (int *)ws_get(h, kWsBatchTab, sizeof(int) * words, &werr);
     int *host = (int *)ws_get_host(h, sizeof(int) * words, &werr);
     if (werr) return werr;
-    size_t o = 0;
-    auto put = [&](const std::vector<int> &v, size_t len) {
-        for (size_t i = 0; i < len; ++i) host[o + i] = i < v.size() ? v[i] : 0;
-        const size_t at = o;
-        o += len;
-        return tab + at;
-    };
-    b.rblk_sys = put(t.rsys, nr);
-    b.rblk_lo = put(t.rlo, nr);
-    b.rblk_hi = put(t.rhi, nr);
-    b.cblk_sys = put(t.csys, ncb);
-    b.cblk_lo = put(t.clo, ncb);
-    b.cblk_hi = put(t.chi, ncb);
-    b.sys_c0 = put(t.sc0, S + 1);
-    b.sys_r0 = put(t.sr0, S);
+    std::fill(host, host + words, 0);
+    for (size_t j = 0; j < t.rsys.size(); ++j) {
+        const int s = t.rsys[j];
+        int *o = host + 8 * j;
+        o[0] = t.rlo[j];
+        o[1] = t.rhi[j];
+        o[2] = s;
+        o[3] = (int)j == t.sr0[s];
+        o[4] = t.sc0[s];
+        o[5] = t.sc0[s + 1];
+    }
+    for (size_t j = 0; j < t.csys.size(); ++j) {
+        int *o = host + 8 * nr + 4 * j;
+        o[0] = t.clo[j];
+        o[1] = t.chi[j];
+        o[2] = t.csys[j];
+    }
+    std::copy(t.sc0.begin(), t.sc0.end(), host + 4 * (2 * nr + ncb));
+    b.rt = reinterpret_cast<const int4 *>(tab);
+    b.ct = reinterpret_cast<const int4 *>(tab + 8 * nr);
+    b.sys_c0 = tab + 4 * (2 * nr + ncb);
     b.nrb = (int)t.rsys.size();
     b.ncb = (int)t.csys.size();
     RL_HIP(hipMemcpyAsync(tab, host, sizeof(int) * words, hipMemcpyHostToDevice, st));
@@ -496,7 +506,8 @@ int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *
     RL_HIP(start_phases(st, b, uni, rb, cb, p));
     // graph of B iterations plus the counter advance; re-captured whenever
     // the tile table is compacted to the systems still iterating
-    const int B = p.check_every > 0 ? p.check_every : 32;
+    // iterations per graph: even, so that every graph starts at an even count
+    const int B = p.check_every > 0 ? (p.check_every + 1) / 2 * 2 : 32;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     auto capture = [&]() -> int {
