@@ -43,7 +43,7 @@
 namespace rl {
 
 static inline unsigned grid_of(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
-static inline unsigned rod_grid8(int64_t n) { return (grid_of(n, kRodBlock / kRodLanes) + 7) / 8 * 8; }
+static inline unsigned rod_grid8(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
 
 // CG state.  P order: cs = (lambda, p, mask, 0), cr = (r, s, w, 0);
 // Q-side list order: cq = (r, s, w, lambda).  s = Mc_AA p, w = Mc_AA r.
@@ -135,19 +135,92 @@ __global__ void __launch_bounds__(kConBlock) k_cg_start(CgArgs g, const double *
     }
 }
 
+// One incidence record of the CG rod kernel: (r, s) and w of the constraint
+// in the side's order, and its geometry (ex, ey), (ez, s).
+struct CgRec {
+    double2 rs, g0, g1;
+    double w;
+};
+
+__device__ __forceinline__ void cg_rec_load(const double *cr, const double *geo, int c, int end, CgRec &R)
+{
+    const double2 z = make_double2(0.0, 0.0);
+    R.rs = R.g0 = R.g1 = z;
+    R.w = 0.0;
+    if (c < end) {
+        const double2 *x = reinterpret_cast<const double2 *>(cr + 4 * (int64_t)c);
+        const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
+        R.rs = x[0];
+        R.w = x[1].x;
+        R.g0 = gd[0];
+        R.g1 = gd[1];
+    }
+}
+
+// f += +-r_{k} e, m += +-r_{k} s e over one side's incidences of the lane
+__device__ __forceinline__ void cg_side(double sign, const double *cr, const double *geo, int b, int e,
+                                        const CgRec *rr, double alpha, double beta, double f[3], double m[3])
+{
+#pragma unroll
+    for (int i = 0; i < kRodRounds; ++i) {
+        if (b + i * kRodLanes >= e) return;
+        rod_add(sign, cg_next_r(rr[i].rs.x, rr[i].rs.y, rr[i].w, alpha, beta), rr[i].g0, rr[i].g1, f, m);
+    }
+    for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
+        CgRec R;
+        cg_rec_load(cr, geo, c, e, R);
+        rod_add(sign, cg_next_r(R.rs.x, R.rs.y, R.w, alpha, beta), R.g0, R.g1, f, m);
+    }
+}
+
+// u = e.(V + s W) at every incidence of the lane, in the same order
+__device__ __forceinline__ void cg_emit(double *u, const double *geo, int b, int e, const CgRec *rr,
+                                        const double v[3], const double w[3])
+{
+#pragma unroll
+    for (int i = 0; i < kRodRounds; ++i) {
+        if (b + i * kRodLanes >= e) return;
+        u[b + i * kRodLanes] = u_along(rr[i].g0, rr[i].g1, v, w);
+    }
+    for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
+        const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
+        u[c] = u_along(gd[0], gd[1], v, w);
+    }
+}
+
 // Rod kernel of CG iteration k: D r_k summed per rod (four lanes per rod),
-// then V = M_t F and W = Omega x dir.  Before that, every workgroup sums the
+// then V = M_t F and W = Omega x dir, projected on e at every incidence of
+// the rod (u = e.(V + s W), the rod's share of w = Mc_AA r).  The first
+// records of each lane are loaded before anything else: they depend on
+// neither the step scalars nor the stop flag.  Every workgroup then sums the
 // partials of iteration k-1 and takes the stop decision; workgroup 0
 // publishes the step scalars and latches the stop.
 template <bool UNI>
-__global__ void __launch_bounds__(kRodBlock) k_cg_rod(CgArgs g, long long k)
+__global__ void __launch_bounds__(kRodLoopBlock) k_cg_rod(CgArgs g, long long k)
 {
-    __shared__ double lds[kRodBlock / 64 + 1][4];
+    __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     const SolveArgs &a = g.a;
     SolverState *st = a.state;
+    const int sub = threadIdx.x & (kRodLanes - 1);
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const bool active = r < a.n;
+    int pb = 0, pe = 0, qb = 0, qe = 0;
+    if (active) {
+        pb = a.pptr[r] + sub;
+        pe = a.pptr[r + 1];
+        qb = a.qptr[r] + sub;
+        qe = a.qptr[r + 1];
+    }
+    CgRec P[kRodRounds], Q[kRodRounds];
+#pragma unroll
+    for (int i = 0; i < kRodRounds; ++i) {
+        cg_rec_load(g.cr, a.geo, pb + i * kRodLanes, pe, P[i]);
+        cg_rec_load(g.cq, a.qgeo, qb + i * kRodLanes, qe, Q[i]);
+    }
     if (st->done) return;
     double t[4];
-    sum_partials<kRodBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+    sum_partials<kRodLoopBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
     double alpha = 0.0, beta = 0.0;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (k == 0) {
@@ -195,54 +268,33 @@ __global__ void __launch_bounds__(kRodBlock) k_cg_rod(CgArgs g, long long k)
         }
         if (stop) return;
     }
-    const int sub = threadIdx.x & (kRodLanes - 1);
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t r = (int64_t)tile * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
-    const bool active = r < a.n;
-    double fm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        const int pe = a.pptr[r + 1];
-        for (int c = a.pptr[r] + sub; c < pe; c += kRodLanes) {
-            const double2 *cr = reinterpret_cast<const double2 *>(g.cr + 4 * (int64_t)c);
-            const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * (int64_t)c);
-            const double2 rs = cr[0], w0 = cr[1], g0 = gd[0], g1 = gd[1];
-            const double v = cg_next_r(rs.x, rs.y, w0.x, alpha, beta), vs = v * g1.y;
-            fm[0] += v * g0.x;
-            fm[1] += v * g0.y;
-            fm[2] += v * g1.x;
-            fm[3] += vs * g0.x;
-            fm[4] += vs * g0.y;
-            fm[5] += vs * g1.x;
-        }
-        const int qe = a.qptr[r + 1];
-        for (int kq = a.qptr[r] + sub; kq < qe; kq += kRodLanes) {
-            const double2 *cq = reinterpret_cast<const double2 *>(g.cq + 4 * (int64_t)kq);
-            const double2 *gd = reinterpret_cast<const double2 *>(a.qgeo + 4 * (int64_t)kq);
-            const double2 rs = cq[0], w0 = cq[1], g0 = gd[0], g1 = gd[1];
-            const double v = cg_next_r(rs.x, rs.y, w0.x, alpha, beta), vs = v * g1.y;
-            fm[0] -= v * g0.x;
-            fm[1] -= v * g0.y;
-            fm[2] -= v * g1.x;
-            fm[3] -= vs * g0.x;
-            fm[4] -= vs * g0.y;
-            fm[5] -= vs * g1.x;
+    double f[3] = {0.0, 0.0, 0.0}, m[3] = {0.0, 0.0, 0.0};
+    cg_side(1.0, g.cr, a.geo, pb, pe, P, alpha, beta, f, m);
+    cg_side(-1.0, g.cq, a.qgeo, qb, qe, Q, alpha, beta, f, m);
+#pragma unroll
+    for (int o = 1; o < kRodLanes; o <<= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[d] += __shfl_xor(f[d], o, 64);
+            m[d] += __shfl_xor(m[d], o, 64);
         }
     }
-    lane_sum(fm, 6);
-    if (!active || sub != 0) return;
-    const V3 d = load3(a.dir + 3 * r), f = v3(fm[0], fm[1], fm[2]), m = v3(fm[3], fm[4], fm[5]);
+    if (!active) return;
+    const V3 d = load3(a.dir + 3 * r);
     double apar, aperp, rperp;
     rod_mob(a, r, UNI, apar, aperp, rperp);
     // translation M_t f; rotation Omega = r_perp d x m and Omega x d = r_perp (m - (d.m) d)
-    const V3 v = aperp * f + ((apar - aperp) * dot(d, f)) * d;
-    const V3 w = rperp * (m - dot(d, m) * d);
-    double *o = a.V + 6 * r;
-    store3(o, v);
-    store3(o + 3, w);
+    const double fd = (apar - aperp) * (d.x * f[0] + d.y * f[1] + d.z * f[2]);
+    const double md = d.x * m[0] + d.y * m[1] + d.z * m[2];
+    const double v[3] = {aperp * f[0] + fd * d.x, aperp * f[1] + fd * d.y, aperp * f[2] + fd * d.z};
+    const double w[3] = {rperp * (m[0] - md * d.x), rperp * (m[1] - md * d.y), rperp * (m[2] - md * d.z)};
+    cg_emit(a.uP, a.geo, pb, pe, P, v, w);
+    cg_emit(a.uQ, a.qgeo, qb, qe, Q, v, w);
 }
 
 // Constraint kernel of CG iteration k: the update of iteration k-1 (lambda,
-// p, s, r), then w_k = Mc_AA r_k on A and the partials (r_k.r_k, r_k.w_k).
+// p, s, r), then w_k = Mc_AA r_k = u_P - u_Q on A and the partials
+// (r_k.r_k, r_k.w_k).
 __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
 {
     __shared__ double lds[kConBlock / 64 + 1][4];
@@ -255,12 +307,12 @@ __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
     const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
     for (int64_t c = lo + threadIdx.x; c < hi; c += kConBlock) {
-        const int2 ij = a.pp[c];
-        const double2 *gd = reinterpret_cast<const double2 *>(a.geo + 4 * c);
         double2 *cs = reinterpret_cast<double2 *>(g.cs + 4 * c);
         double2 *cr = reinterpret_cast<double2 *>(g.cr + 4 * c);
-        const double2 lp = cs[0], mk = cs[1], rs = cr[0], w0 = cr[1];
         const int qp = a.qpos[c];
+        const double up = a.uP[c];
+        const double2 lp = cs[0], mk = cs[1], rs = cr[0], w0 = cr[1];
+        const double uq = a.uQ[qp];
         double lam = lp.x, pv = lp.y, rv = rs.x, sv = rs.y;
         if (k > 0) {
             const double s1 = fma(beta, sv, w0.x);
@@ -270,7 +322,7 @@ __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
             sv = s1;
             pv = p1;
         }
-        const double w = mk.x > 0.0 ? con_rate(a, c, ij, gd[0], gd[1], a.geo2[c]) : 0.0;
+        const double w = mk.x > 0.0 ? up - uq : 0.0;
         cs[0] = make_double2(lam, pv);
         cr[0] = make_double2(rv, sv);
         cr[1] = make_double2(w, 0.0);
@@ -525,24 +577,39 @@ int adjoint_core(rl_ctx *h, SolveArgs &a, bool step, const double *Ubar, const d
         RL_HIP(hipGetLastError());
         const int every = p.check_every > 0 ? p.check_every : 32;
         const dim3 rgrid(rod_grid8(n > 0 ? n : 1));
-        for (long long launched = 0;; launched += every) {
-            if (launched > p.max_iter + every + 1) {
+        long long launched = 0;
+        auto enqueue = [&](int cnt) -> int {
+            for (int k = 0; k < cnt; ++k, ++launched) {
+                if (uni)
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<true>), rgrid, dim3(kRodLoopBlock), 0, st, g,
+                                       launched);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<false>), rgrid, dim3(kRodLoopBlock), 0, st, g,
+                                       launched);
+                RL_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_cg_con, dim3(a.gcon), dim3(kConBlock), 0, st, g, launched);
+                RL_HIP(hipGetLastError());
+            }
+            return RL_OK;
+        };
+        // the state is copied after every `every` iterations; a few more are
+        // queued behind each copy before the host waits for it, so the GPU
+        // never idles on the host (iterations after the stop return at once)
+        const int la = std::min(every, 8);
+        if (!h->chk_ev) RL_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
+        if ((rc = enqueue(every))) return rc;
+        for (;;) {
+            RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+            RL_HIP(hipEventRecord(h->chk_ev, st));
+            const long long checked = launched;
+            if ((rc = enqueue(la))) return rc;
+            RL_HIP(hipEventSynchronize(h->chk_ev));
+            if (h->state_host->done) break;
+            if (checked > p.max_iter + every + 1) {
                 set_error("adjoint: CG stop flag never raised");
                 return RL_ERR_HIP;
             }
-            for (int k = 0; k < every; ++k) {
-                const long long it = launched + k;
-                if (uni)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<true>), rgrid, dim3(kRodBlock), 0, st, g, it);
-                else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<false>), rgrid, dim3(kRodBlock), 0, st, g, it);
-                RL_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_cg_con, dim3(a.gcon), dim3(kConBlock), 0, st, g, it);
-                RL_HIP(hipGetLastError());
-            }
-            RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
-            RL_HIP(hipStreamSynchronize(st));
-            if (h->state_host->done) break;
+            if ((rc = enqueue(every - la))) return rc;
         }
         iters = h->state_host->iter;
         res = h->state_host->res;
