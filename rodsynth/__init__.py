@@ -176,3 +176,43 @@ def cfg_rollout(seed: int = 0, n: int = 50_000) -> RodSystem:
     """50,000 rods of length 1, volume fraction 0.05, isotropic."""
     return make_system(n, seed=seed, phi=0.05, orientation="isotropic",
                        name=f"rods{n // 1000}k_phi0.05_iso")
+
+
+def cfg_hub(seed: int = 0, crossers: int = 36) -> RodSystem:
+    """One long rod (length 4, along x) crossed by ``crossers`` short rods
+    (length 1, along y with small tilts) whose axes pass 0.005-0.06 um above
+    it: the long rod takes part in ``crossers`` constraints, half with a
+    lower and half with a higher index, so both of its incidence lists are
+    long.  Box 10; forces N(0, 1), with 2 pN more along -z on every crosser
+    (pressing it onto the long rod).  Draw order: offsets along z, tilts,
+    forces."""
+    rng = np.random.Generator(np.random.PCG64([seed, 11]))
+    n = crossers + 1
+    hub = crossers // 2
+    x = np.empty((n, 3))
+    quat = np.empty((n, 4))
+    lens = np.ones(n)
+    off = rng.uniform(0.005, 0.06, crossers)
+    tilt = rng.uniform(-0.05, 0.05, (crossers, 2))
+    force = rng.standard_normal((n, 6))
+    h = math.sqrt(0.5)
+    # hub: the rotation by +90 degrees about y (z -> x)
+    x[hub] = (5.0, 5.0, 5.0)
+    quat[hub] = (h, 0.0, h, 0.0)
+    lens[hub] = 4.0
+    k = 0
+    for m in range(crossers):
+        i = m if m < hub else m + 1
+        x[i] = (3.25 + 0.1 * m, 5.0, 5.0 + off[k])
+        # -90 degrees about x (z -> y), then a small extra turn about x and z
+        a, b = tilt[k]
+        qx = np.array([math.cos(-math.pi / 4 + a / 2), math.sin(-math.pi / 4 + a / 2), 0.0, 0.0])
+        qz = np.array([math.cos(b / 2), 0.0, 0.0, math.sin(b / 2)])
+        # Hamilton product qz * qx
+        s1, v1 = qz[0], qz[1:]
+        s2, v2 = qx[0], qx[1:]
+        qv = np.concatenate([[s1 * s2 - v1 @ v2], s1 * v2 + s2 * v1 + np.cross(v1, v2)])
+        quat[i] = qv / np.linalg.norm(qv)
+        force[i, 2] -= 2.0
+        k += 1
+    return RodSystem(x=x, quat=quat, length=lens, force=force, box=10.0, name="hub")

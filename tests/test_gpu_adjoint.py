@@ -25,6 +25,8 @@ SYSTEMS = {
     "fd20": lambda: rodsynth.make_system(20, seed=0, phi=0.05),
     "rods200": lambda: rodsynth.make_system(200, seed=2, phi=0.04),
     "lengths": lambda: rodsynth.make_system(300, seed=1, phi=0.04, length=(0.5, 1.5)),
+    # one rod with 18 contacts on each side of its incidence lists
+    "hub": lambda: rodsynth.cfg_hub(1),
 }
 
 

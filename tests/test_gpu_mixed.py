@@ -40,9 +40,9 @@ def _solve(rl, s, d, pr, cs, precision, **kw):
     return g.cpu().numpy(), U.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("which", ["small", "lengths", "dense10k"])
+@pytest.mark.parametrize("which", ["small", "lengths", "dense10k", "hub"])
 def test_mixed_matches_oracle(gpu_lib, which):
-    s = {"small": lambda: rodsynth.cfg_small(0),
+    s = {"small": lambda: rodsynth.cfg_small(0), "hub": lambda: rodsynth.cfg_hub(1),
          "lengths": lambda: rodsynth.make_system(1000, seed=1, phi=0.04, length=(0.5, 1.5)),
          "dense10k": lambda: rodsynth.cfg_paper_scale(0, n=10_000)}[which]()
     d, pr, cs = _setup(s)

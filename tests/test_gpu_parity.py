@@ -192,9 +192,10 @@ def _gpu_solve(gpu_lib, s, d, pr, cs, **kw):
     return g.cpu().numpy(), U.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("which", ["small0", "small1", "lengths", "dense10k"])
+@pytest.mark.parametrize("which", ["small0", "small1", "lengths", "dense10k", "hub"])
 def test_solve_matches_oracle(gpu_lib, which):
     s = {"small0": lambda: rodsynth.cfg_small(0), "small1": lambda: rodsynth.cfg_small(1),
+         "hub": lambda: rodsynth.cfg_hub(1),
          "lengths": lambda: rodsynth.make_system(1000, seed=1, phi=0.04, length=(0.5, 1.5)),
          "dense10k": lambda: rodsynth.cfg_paper_scale(0, n=10_000)}[which]()
     d, pr, cs = _oracle_setup(s)
@@ -304,9 +305,13 @@ def test_solve_bitwise_repeatable(gpu_lib):
     assert np.array_equal(g1, g2) and np.array_equal(U1, U2)
 
 
-@pytest.mark.parametrize("which", ["small", "lengths"])
+@pytest.mark.parametrize("which", ["small", "lengths", "hub"])
 def test_step_matches_oracle(gpu_lib, which):
-    s = rodsynth.cfg_small(5) if which == "small" else rodsynth.make_system(800, seed=6, phi=0.06, length=(0.5, 1.5))
+    """"hub": one rod 4 long in a box of 10 (two cells per side) with 18
+    contacts on each side of its incidence lists."""
+    s = {"small": lambda: rodsynth.cfg_small(5),
+         "lengths": lambda: rodsynth.make_system(800, seed=6, phi=0.06, length=(0.5, 1.5)),
+         "hub": lambda: rodsynth.cfg_hub(1)}[which]()
     r = oracle.step_solve(s)
     xo, qo = s.x.copy(), s.quat.copy()
     oracle.integrate(s.box, s.dt, r.U, xo, qo)

@@ -55,9 +55,9 @@ def _certify(s, d, pr, cs, g, U):
     assert np.linalg.norm(U - Uo) <= 1e-12 * np.linalg.norm(Uo)
 
 
-@pytest.mark.parametrize("which", ["small", "lengths", "dense10k"])
+@pytest.mark.parametrize("which", ["small", "lengths", "dense10k", "hub"])
 def test_persistent_matches_oracle(gpu_lib, which):
-    s = {"small": lambda: rodsynth.cfg_small(0),
+    s = {"small": lambda: rodsynth.cfg_small(0), "hub": lambda: rodsynth.cfg_hub(1),
          "lengths": lambda: rodsynth.make_system(1000, seed=1, phi=0.04, length=(0.5, 1.5)),
          "dense10k": lambda: rodsynth.cfg_paper_scale(0, n=10_000)}[which]()
     d, pr, cs = _setup(s)

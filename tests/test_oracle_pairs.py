@@ -123,3 +123,25 @@ def test_self_image_contact():
     assert p.n == 1 and p.pi[0] == 0 and p.pj[0] == 0
     assert tuple(oracle.img_unpack(p.img)[0]) == (1, 0, 0)
     assert p.flags[0] & oracle.FLAG_PARALLEL
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_hub_pairs(seed):
+    """A rod of length 4 crossed by 36 rods of length 1 (axes 0.005-0.06
+    apart, closer than diam + cutoff = 0.075): every crosser touches the long
+    rod, the cell list (two cells per side of the box of 10) finds the same
+    pairs as the brute force, and the long rod's lists hold 18 contacts on
+    each side.  The surface gap of each hub pair is within the tilt's reach of
+    the axis offset minus the diameter."""
+    s = rodsynth.cfg_hub(seed)
+    d, a, b = _both(s)
+    assert _same(a, b)
+    hub = 18
+    assert np.sum(a.pi == hub) == 18 and np.sum(a.pj == hub) == 18
+    cs = oracle.assemble(s.x, d, s.length, s.box, s.diam, s.eta, s.dt, a, s.force)
+    for c in np.flatnonzero((a.pi == hub) | (a.pj == hub)):
+        other = a.pj[c] if a.pi[c] == hub else a.pi[c]
+        off = s.x[other, 2] - s.x[hub, 2]
+        # the crosser's axis is tilted by at most 0.05 rad over half a length
+        # of 0.5, but it passes the long rod near its own centre
+        assert off - s.diam - 0.03 <= cs.phi[c] <= off - s.diam + 1e-12
