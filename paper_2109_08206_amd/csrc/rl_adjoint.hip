@@ -191,10 +191,10 @@ __device__ __forceinline__ void cg_emit(double *u, const double *geo, int b, int
 // Rod kernel of CG iteration k: D r_k summed per rod (four lanes per rod),
 // then V = M_t F and W = Omega x dir, projected on e at every incidence of
 // the rod (u = e.(V + s W), the rod's share of w = Mc_AA r).  The first
-// records of each lane are loaded before anything else: they depend on
-// neither the step scalars nor the stop flag.  Every workgroup then sums the
-// partials of iteration k-1 and takes the stop decision; workgroup 0
-// publishes the step scalars and latches the stop.
+// records of each lane and the previous partials are loaded before anything
+// else: they depend on neither the step scalars nor the stop flag.  Every
+// workgroup then sums the partials of iteration k-1 and takes the stop
+// decision; workgroup 0 publishes the step scalars and latches the stop.
 template <bool UNI>
 __global__ void __launch_bounds__(kRodLoopBlock) k_cg_rod(CgArgs g, long long k)
 {
@@ -218,9 +218,12 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_cg_rod(CgArgs g, long long k)
         cg_rec_load(g.cr, a.geo, pb + i * kRodLanes, pe, P[i]);
         cg_rec_load(g.cq, a.qgeo, qb + i * kRodLanes, qe, Q[i]);
     }
+    const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
+    PartFirst pf;
+    partials_first(part, a.gcon, pf);
     if (st->done) return;
     double t[4];
-    sum_partials<kRodLoopBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+    sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
     double alpha = 0.0, beta = 0.0;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (k == 0) {

@@ -86,10 +86,18 @@ __global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
     // records first: they depend neither on the system's state nor on its step
     RodLoads L;
     rod_load(b.a, r, active, sub, L);
+    // the counter and the system's partials are read before the stop flag,
+    // so that the three loads are in flight together.  The counter base is
+    // even, so the parity of k is that of i: the partials' address does not
+    // wait for the counter.
+    const long long kb = MODE == kModeLoop ? *b.kbase : 0;
+    const double *part = b.partial + ((int64_t)((i - 1) & 1) * b.ncb + t1.x) * 4;
+    PartFirst pf;
+    if (MODE == kModeLoop) partials_first(part, t1.y - t1.x, pf);
     const int s = t0.z;
     SolverState *st = b.sst + s;
     if (MODE != kModeApply && st->done) return;
-    const long long k = MODE == kModeLoop ? *b.kbase + i : 0;
+    const long long k = kb + i;
     double alpha = 0.0;
     if (MODE == kModeLoop) {
         const bool publisher = t0.w && threadIdx.x == 0;
@@ -98,10 +106,8 @@ __global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
             alpha = st->alpha;
             if (publisher) abuf[0] = alpha;
         } else {
-            // the counter base is even, so the parity of k is that of i: the
-            // partials' address does not wait for the counter
             double t[4];
-            sum_partials<RB / 64>(b.partial + ((int64_t)((i - 1) & 1) * b.ncb + t1.x) * 4, t1.y - t1.x, t, lds);
+            sum_partials_from<RB / 64>(pf, part, t1.y - t1.x, t, lds);
             const Decision d = decide(st, abuf, k, t);
             if (publisher) {
                 if (d.stop) latch(b, s, k, t, d.status);

@@ -58,16 +58,41 @@ __device__ __forceinline__ void block_reduce4_all(double p[4], double (*lds)[4])
 }
 
 // Totals of the `count` workgroup partials at `P`, identical in every
-// workgroup.  Each thread sums its partials in index order; kPartChunk of its
-// loads are in flight together.
+// workgroup.  Each thread sums its partials in index order: the first one
+// (partials_first, which a kernel may issue early, before it waits on
+// anything else), then the rest with kPartChunk loads in flight together.
 constexpr int kPartChunk = 2;
 
+struct PartFirst {
+    double2 u, v;
+};
+
+// the thread's first partial (clamped: any count >= 1 gives an in-bounds
+// address; with count <= 0 nothing is read)
+__device__ __forceinline__ void partials_first(const double *__restrict__ P, int count, PartFirst &F)
+{
+    F.u = F.v = make_double2(0.0, 0.0);
+    if (count > 0) {
+        const int b = min((int)threadIdx.x, count - 1);
+        const double2 *src = reinterpret_cast<const double2 *>(P + 4 * (int64_t)b);
+        F.u = src[0];
+        F.v = src[1];
+    }
+}
+
 template <int NW>
-__device__ __forceinline__ void sum_partials(const double *__restrict__ P, int count, double p[4], double (*lds)[4])
+__device__ __forceinline__ void sum_partials_from(const PartFirst &F, const double *__restrict__ P, int count,
+                                                  double p[4], double (*lds)[4])
 {
     constexpr int NT = NW * 64;
     p[0] = p[1] = p[2] = p[3] = 0.0;
-    for (int b0 = threadIdx.x; b0 < count; b0 += kPartChunk * NT) {
+    if ((int)threadIdx.x < count) {
+        p[0] += F.u.x;
+        p[1] += F.u.y;
+        p[2] += F.v.x;
+        p[3] = fmax(p[3], F.v.y);
+    }
+    for (int b0 = threadIdx.x + NT; b0 < count; b0 += kPartChunk * NT) {
         double2 u[kPartChunk], v[kPartChunk];
 #pragma unroll
         for (int j = 0; j < kPartChunk; ++j) {
@@ -88,6 +113,14 @@ __device__ __forceinline__ void sum_partials(const double *__restrict__ P, int c
         }
     }
     block_reduce4_all<NW>(p, lds);
+}
+
+template <int NW>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ P, int count, double p[4], double (*lds)[4])
+{
+    PartFirst F;
+    partials_first(P, count, F);
+    sum_partials_from<NW>(F, P, count, p, lds);
 }
 
 // Stop test and step length for iteration k >= 1 from the totals of

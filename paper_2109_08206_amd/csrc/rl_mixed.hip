@@ -129,6 +129,10 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_rod32(SolveArgs a, long long 
     rec32_load(a.stq32, a.qgeo32, qb, qe, q1);
     rec32_load(a.st32, a.geo32, pb + kRodLanes, pe, p2);
     rec32_load(a.stq32, a.qgeo32, qb + kRodLanes, qe, q2);
+    // and the previous iteration's partials (read for nothing on a first iteration)
+    const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
+    PartFirst pf;
+    partials_first(part, a.gcon, pf);
     if (st->done || st->refresh) return;
     double alpha;
     if (first) {
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_rod32(SolveArgs a, long long 
         if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[k & 1] = alpha;
     } else {
         double t[4];
-        sum_partials<kRodLoopBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+        sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
         const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
         int done = 0, refresh = 0, status = RL_OK;
         if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {

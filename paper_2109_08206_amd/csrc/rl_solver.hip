@@ -172,6 +172,10 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_rod(SolveArgs a, long long k)
     // flag: load them first (after the stop they are read for nothing)
     RodLoads L;
     rod_load(a, r, active, sub, L);
+    // so are the previous iteration's partials (read for nothing at k = 0)
+    const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
+    PartFirst pf;
+    if (MODE == kModeLoop) partials_first(part, a.gcon, pf);
     if (MODE != kModeApply && a.state->done) return;
     if (MODE == kModeLoop) {
         if (k == 0) {
@@ -179,7 +183,7 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_rod(SolveArgs a, long long k)
             if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[0] = alpha;
         } else {
             double t[4];
-            sum_partials<kRodLoopBlock / 64>(a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4, a.gcon, t, lds);
+            sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
             const Decision d = decide(a.state, a.alpha_buf, k, t);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 if (d.stop) {
