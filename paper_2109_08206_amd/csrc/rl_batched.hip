@@ -537,28 +537,44 @@ int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *
         return RL_OK;
     };
     if ((rc = capture())) return rc;
+    if (!h->chk_ev) RL_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
     int ndone = 0, last_ndone = 0;
     long long replays = 0;
     std::vector<int> done_host(S, 0);
+    // The count of finished systems is copied after every replay, and the
+    // next replay is queued behind the copy before the host waits for it, so
+    // the GPU never idles on the host.  A replay after the last stop returns
+    // at once in every workgroup.
+    RL_HIP(hipGraphLaunch(exec, st));
+    ++replays;
     for (;;) {
         RL_HIP(hipMemcpyAsync(h->host_scratch, b.ndone, sizeof(int), hipMemcpyDeviceToHost, st));
-        RL_HIP(hipStreamSynchronize(st));
+        RL_HIP(hipEventRecord(h->chk_ev, st));
+        const long long checked = replays;
+        RL_HIP(hipGraphLaunch(exec, st));
+        ++replays;
+        RL_HIP(hipEventSynchronize(h->chk_ev));
         ndone = ((int *)h->host_scratch)[0];
         if (ndone >= S) break;
-        if (replays * B > p.max_iter + 2 * B) {
+        if (checked * B > p.max_iter + 2 * B) {
+            (void)hipStreamSynchronize(st);
             (void)hipGraphExecDestroy(exec);
             (void)hipGraphDestroy(graph);
             set_error("rl_solve_lcp_batched: systems did not all stop");
             return RL_ERR_HIP;
         }
-        if (ndone > last_ndone && replays > 0) {
+        if (ndone > last_ndone) {
             last_ndone = ndone;
+            // every queued replay has ended once the copy of the flags is in
             RL_HIP(hipMemcpyAsync(done_host.data(), b.done_s, sizeof(int) * S, hipMemcpyDeviceToHost, st));
             RL_HIP(hipStreamSynchronize(st));
             int live = 0;
             for (int s = 0; s < S; ++s)
                 if (!done_host[s]) live += tab.sc0[s + 1] - tab.sc0[s];
-            if (2 * live < b.ncb) {
+            // Finished systems' workgroups still read their records before
+            // they see the flag: the table drops them once they are an
+            // eighth of it.
+            if (8 * (b.ncb - live) >= b.ncb) {
                 // Once fewer constraint tiles than compute units are left (the
                 // tail of a few slow systems), tuned rod groups give way to the
                 // smallest, for more workgroups on the little work that remains
@@ -597,10 +613,12 @@ int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *
                 if ((rc = upload_tables(h, st, tab, S, b))) return rc;
                 if ((rc = capture())) return rc;
             }
+            // after a full wait nothing is queued: start the next replay
+            RL_HIP(hipGraphLaunch(exec, st));
+            ++replays;
         }
-        RL_HIP(hipGraphLaunch(exec, st));
-        ++replays;
     }
+    RL_HIP(hipStreamSynchronize(st));
     RL_HIP(hipGraphExecDestroy(exec));
     RL_HIP(hipGraphDestroy(graph));
     if (gamma_out && a.nc > 0) RL_HIP(launch_unpack_gamma(st, a, gamma_out));
