@@ -295,45 +295,82 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_cg_rod(CgArgs g, long long k)
     cg_emit(a.uQ, a.qgeo, qb, qe, Q, v, w);
 }
 
+struct CgConLoads {
+    double2 lp, mk, rs, w0;  // (lambda, p), (mask, 0), (r, s), (w, 0)
+    double up, uq;
+    int qp;
+};
+
+__device__ __forceinline__ void cg_con_load(const CgArgs &g, int64_t c, CgConLoads &L)
+{
+    const SolveArgs &a = g.a;
+    const double2 *cs = reinterpret_cast<const double2 *>(g.cs + 4 * c);
+    const double2 *cr = reinterpret_cast<const double2 *>(g.cr + 4 * c);
+    L.qp = a.qpos[c];
+    L.up = a.uP[c];
+    L.lp = cs[0];
+    L.mk = cs[1];
+    L.rs = cr[0];
+    L.w0 = cr[1];
+    L.uq = a.uQ[L.qp];
+}
+
+__device__ __forceinline__ void cg_con_update(const CgArgs &g, int64_t c, const CgConLoads &L, long long k,
+                                              double alpha, double beta, double p[4])
+{
+    double lam = L.lp.x, pv = L.lp.y, rv = L.rs.x, sv = L.rs.y;
+    if (k > 0) {
+        const double s1 = fma(beta, sv, L.w0.x);
+        const double p1 = fma(beta, pv, rv);
+        lam = fma(alpha, p1, lam);
+        rv = cg_next_r(rv, sv, L.w0.x, alpha, beta);
+        sv = s1;
+        pv = p1;
+    }
+    const double w = L.mk.x > 0.0 ? L.up - L.uq : 0.0;
+    double2 *cs = reinterpret_cast<double2 *>(g.cs + 4 * c);
+    double2 *cr = reinterpret_cast<double2 *>(g.cr + 4 * c);
+    cs[0] = make_double2(lam, pv);
+    cr[0] = make_double2(rv, sv);
+    cr[1] = make_double2(w, 0.0);
+    double2 *cq = reinterpret_cast<double2 *>(g.cq + 4 * (int64_t)L.qp);
+    cq[0] = make_double2(rv, sv);
+    cq[1] = make_double2(w, lam);
+    p[0] += rv * rv;
+    p[1] += rv * w;
+}
+
 // Constraint kernel of CG iteration k: the update of iteration k-1 (lambda,
 // p, s, r), then w_k = Mc_AA r_k = u_P - u_Q on A and the partials
-// (r_k.r_k, r_k.w_k).
+// (r_k.r_k, r_k.w_k).  Like the BBPGD constraint kernel, each lane takes
+// kConCpl constraints per round, and the first round's loads and the step
+// scalars are in flight before the stop flag is read.
 __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
 {
     __shared__ double lds[kConBlock / 64 + 1][4];
     const SolveArgs &a = g.a;
-    if (a.state->done) return;
-    const double alpha = k > 0 ? g.ab[2 * ((k - 1) & 1)] : 0.0;
-    const double beta = k > 0 ? g.ab[2 * ((k - 1) & 1) + 1] : 0.0;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
-    for (int64_t c = lo + threadIdx.x; c < hi; c += kConBlock) {
-        double2 *cs = reinterpret_cast<double2 *>(g.cs + 4 * c);
-        double2 *cr = reinterpret_cast<double2 *>(g.cr + 4 * c);
-        const int qp = a.qpos[c];
-        const double up = a.uP[c];
-        const double2 lp = cs[0], mk = cs[1], rs = cr[0], w0 = cr[1];
-        const double uq = a.uQ[qp];
-        double lam = lp.x, pv = lp.y, rv = rs.x, sv = rs.y;
-        if (k > 0) {
-            const double s1 = fma(beta, sv, w0.x);
-            const double p1 = fma(beta, pv, rv);
-            lam = fma(alpha, p1, lam);
-            rv = cg_next_r(rv, sv, w0.x, alpha, beta);
-            sv = s1;
-            pv = p1;
-        }
-        const double w = mk.x > 0.0 ? up - uq : 0.0;
-        cs[0] = make_double2(lam, pv);
-        cr[0] = make_double2(rv, sv);
-        cr[1] = make_double2(w, 0.0);
-        double2 *cq = reinterpret_cast<double2 *>(g.cq + 4 * (int64_t)qp);
-        cq[0] = make_double2(rv, sv);
-        cq[1] = make_double2(w, lam);
-        p[0] += rv * rv;
-        p[1] += rv * w;
+    const int64_t step = (int64_t)kConCpl * kConBlock;
+    int64_t c0 = lo + threadIdx.x;
+    CgConLoads L[kConCpl];
+#pragma unroll
+    for (int u = 0; u < kConCpl; ++u)
+        if (c0 + u * kConBlock < hi) cg_con_load(g, c0 + u * kConBlock, L[u]);
+    const double alpha = k > 0 ? g.ab[2 * ((k - 1) & 1)] : 0.0;
+    const double beta = k > 0 ? g.ab[2 * ((k - 1) & 1) + 1] : 0.0;
+    if (a.state->done) return;
+    for (;;) {
+#pragma unroll
+        for (int u = 0; u < kConCpl; ++u)
+            if (c0 + u * kConBlock < hi) cg_con_update(g, c0 + u * kConBlock, L[u], k, alpha, beta, p);
+        c0 += step;
+        if (c0 >= hi) break;
+#pragma unroll
+        for (int u = 0; u < kConCpl; ++u)
+            if (c0 + u * kConBlock < hi) cg_con_load(g, c0 + u * kConBlock, L[u]);
     }
     block_reduce4_all<kConBlock / 64>(p, lds);
     if (threadIdx.x == 0) {

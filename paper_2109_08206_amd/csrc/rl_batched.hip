@@ -148,10 +148,11 @@ __global__ void __launch_bounds__(CB) k_con_b(BatchArgs b, int i)
     if (c0 + CB < hi) con_load_u<MODE>(b.a, c0 + CB, B);
     const int s = tc.z;
     SolverState *st = b.sst + s;
-    if (MODE != kModeApply && st->done) return;
-    // parity of the iteration = parity of i (the counter base is even)
+    // parity of the iteration = parity of i (the counter base is even); the
+    // step length is read with the stop flag (for nothing after the stop)
     const int par = MODE == kModeLoop ? (i & 1) : 0;
     const double alpha = MODE == kModeLoop ? b.alpha_s[2 * s + par] : 0.0;
+    if (MODE != kModeApply && st->done) return;
     for (;;) {
         if (c0 < hi) con_update_u<MODE>(b.a, c0, A, alpha, p);
         if (c0 + CB < hi) con_update_u<MODE>(b.a, c0 + CB, B, alpha, p);

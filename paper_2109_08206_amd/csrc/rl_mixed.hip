@@ -250,8 +250,9 @@ __global__ void __launch_bounds__(kConBlock) k_con32(SolveArgs a, long long k)
     Con32Loads A, B;
     if (c0 < hi) con32_load(a, c0, A);
     if (c0 + kConBlock < hi) con32_load(a, c0 + kConBlock, B);
+    const double a64 = a.alpha_buf[k & 1];  // read with the flags (for nothing after a stop)
     if (a.state->done || a.state->refresh) return;
-    const float a32 = (float)a.alpha_buf[k & 1];
+    const float a32 = (float)a64;
     while (c0 < hi) {
         const int64_t c1 = c0 + kConBlock;
         con32_update(a, c0, A, a32, p);

@@ -242,8 +242,9 @@ __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
 #pragma unroll
     for (int u = 0; u < kConCpl; ++u)
         if (c0 + u * kConBlock < hi) con_load_u<MODE>(a, c0 + u * kConBlock, L[u]);
-    if (MODE != kModeApply && a.state->done) return;
+    // the step length too (read for nothing after the stop)
     const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
+    if (MODE != kModeApply && a.state->done) return;
     for (;;) {
 #pragma unroll
         for (int u = 0; u < kConCpl; ++u)
