@@ -27,11 +27,12 @@
 // (1989): one product w = Mc_AA r and one fused reduction (r.r, r.w) per
 // iteration.  It runs as two launches, like the BBPGD loop.  The rod kernel
 // forms the next residual of each incident constraint on the fly, sums
-// D r into V = M_t F and W = Omega x dir, and publishes the step scalars.
-// The constraint kernel applies the update, forms w = D^T (V, W) on A and
-// writes the partial sums.  No workgroup waits for another: every workgroup
-// of the next rod kernel sums the previous partials itself in a fixed
-// order.
+// D r into V = M_t F and W = Omega x dir in registers, writes each contact
+// point's velocity along the normal, u = e.(V + s W), and publishes the step
+// scalars.  The constraint kernel applies the update, takes w = u_P - u_Q on
+// A and writes the partial sums.  No workgroup waits for another: every
+// workgroup of the next rod kernel sums the previous partials itself in a
+// fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
