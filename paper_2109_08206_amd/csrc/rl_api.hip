@@ -271,7 +271,7 @@ int rl_assemble_D(rl_handle h, int64_t n, const double *x, const double *dir, co
                   double *phi, double *e, double *arm, double *q)
 {
     RL_CHECK_HANDLE(h);
-    RL_REQUIRE(n >= 0 && nc >= 0 && nc < 0x7fffffff, "rl_assemble_D: bad sizes");
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff && nc >= 0 && nc < 0x7fffffff, "rl_assemble_D: bad sizes");
     RL_REQUIRE(nc == 0 || (x && dir && pi && pj && img && phi && e && arm && q), "rl_assemble_D: NULL array");
     RL_REQUIRE(len || len0 > 0.0, "rl_assemble_D: len0 must be > 0 when len is NULL");
     return assemble_impl(h, n, x, dir, len, len0, nc, pi, pj, img, F, phi, e, arm, q);
@@ -282,7 +282,7 @@ int rl_apply_M(rl_handle h, int64_t n, const double *dir, const double *len, dou
                const double *gamma, double *w)
 {
     RL_CHECK_HANDLE(h);
-    RL_REQUIRE(n >= 0 && nc >= 0 && nc < 0x7fffffff, "rl_apply_M: bad sizes");
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff && nc >= 0 && nc < 0x7fffffff, "rl_apply_M: bad sizes");
     RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && gamma && w), "rl_apply_M: NULL array");
     RL_REQUIRE(len || len0 > 0.0, "rl_apply_M: len0 must be > 0 when len is NULL");
     SolveArgs a;
@@ -299,7 +299,7 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
                  const double *F, double *gamma, double *U, rl_solve_info *info)
 {
     RL_CHECK_HANDLE(h);
-    RL_REQUIRE(n >= 0 && nc >= 0 && nc < 0x7fffffff, "rl_solve_lcp: bad sizes");
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff && nc >= 0 && nc < 0x7fffffff, "rl_solve_lcp: bad sizes");
     RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && q && gamma), "rl_solve_lcp: NULL array");
     RL_REQUIRE(n == 0 || dir || !U, "rl_solve_lcp: NULL dir");
     RL_REQUIRE(len || len0 > 0.0, "rl_solve_lcp: len0 must be > 0 when len is NULL");

@@ -233,20 +233,30 @@ __device__ __forceinline__ void rod_rec_load(const double2 *st, const double *ge
     }
 }
 
-__device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
+// The arrays come as separate arguments so that a kernel can take them in
+// preloaded registers (leading kernel arguments) instead of from the
+// argument block.
+__device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qptr, const double2 *st,
+                                         const double2 *stq, const double *geo, const double *qgeo, int64_t r,
+                                         bool active, int sub, RodLoads &L)
 {
     L.pb = L.pe = L.qb = L.qe = 0;
     if (active) {
-        L.pb = a.pptr[r] + sub;
-        L.pe = a.pptr[r + 1];
-        L.qb = a.qptr[r] + sub;
-        L.qe = a.qptr[r + 1];
+        L.pb = pptr[r] + sub;
+        L.pe = pptr[r + 1];
+        L.qb = qptr[r] + sub;
+        L.qe = qptr[r + 1];
     }
 #pragma unroll
     for (int i = 0; i < kRodRounds; ++i) {
-        rod_rec_load(a.st, a.geo, L.pb + i * kRodLanes, L.pe, L.p[i]);
-        rod_rec_load(a.stq, a.qgeo, L.qb + i * kRodLanes, L.qe, L.q[i]);
+        rod_rec_load(st, geo, L.pb + i * kRodLanes, L.pe, L.p[i]);
+        rod_rec_load(stq, qgeo, L.qb + i * kRodLanes, L.qe, L.q[i]);
     }
+}
+
+__device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
+{
+    rod_load(a.pptr, a.qptr, a.st, a.stq, a.geo, a.qgeo, r, active, sub, L);
 }
 
 // f += +-gamma' e, m += +-gamma' s e for one incidence record
@@ -394,14 +404,29 @@ struct ConLoadsU {
     int qp;
 };
 
+// The constraint side's inputs; like rod_load, the arrays may come from
+// preloaded kernel arguments.
+struct ConIn {
+    const int32_t *qpos;
+    const double *uP, *qv;
+    const double2 *st;
+    const double *uQ;
+};
+
+template <int MODE>
+__device__ __forceinline__ void con_load_u(const ConIn &in, int64_t c, ConLoadsU &L)
+{
+    L.qp = in.qpos[c];
+    L.up = in.uP[c];
+    L.q = in.qv[c];
+    if (MODE != kModeApply) L.sg = in.st[c];
+    L.uq = in.uQ[L.qp];
+}
+
 template <int MODE>
 __device__ __forceinline__ void con_load_u(const SolveArgs &a, int64_t c, ConLoadsU &L)
 {
-    L.qp = a.qpos[c];
-    L.up = a.uP[c];
-    L.q = a.qv[c];
-    if (MODE != kModeApply) L.sg = a.st[c];
-    L.uq = a.uQ[L.qp];
+    con_load_u<MODE>(ConIn{a.qpos, a.uP, a.qv, a.st, a.uQ}, c, L);
 }
 
 template <int MODE>

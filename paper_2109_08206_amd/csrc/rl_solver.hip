@@ -159,19 +159,26 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
 }
 
 
+// The arrays and sizes that the first loads need lead the argument list
+// (pptr, qptr, st, stq, geo, qgeo, grid size, n: 14 dwords, what the
+// hardware can preload into registers besides the argument block's address),
+// so that the first loads do not wait for the argument block.
 template <int MODE, bool UNI>
-__global__ void __launch_bounds__(kRodLoopBlock) k_rod(SolveArgs a, long long k)
+__global__ void __launch_bounds__(kRodLoopBlock)
+    k_rod(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const double2 *st, const double2 *stq,
+          const double *__restrict__ geo, const double *__restrict__ qgeo, unsigned nblk, int n, SolveArgs a,
+          long long k)
 {
     __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     double alpha = 0.0;
     const int sub = threadIdx.x & (kRodLanes - 1);
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned tile = xcd_tile(blockIdx.x, nblk);
     const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
-    const bool active = r < a.n;
+    const bool active = r < n;
     // the incidence records depend neither on the step length nor on the stop
     // flag: load them first (after the stop they are read for nothing)
     RodLoads L;
-    rod_load(a, r, active, sub, L);
+    rod_load(pptr, qptr, st, stq, geo, qgeo, r, active, sub, L);
     // so are the previous iteration's partials (read for nothing at k = 0)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
@@ -225,15 +232,21 @@ __global__ void __launch_bounds__(kRodLoopBlock) k_rod(SolveArgs a, long long k)
 // ---------------------------------------------------------------------------
 // constraint kernel
 // ---------------------------------------------------------------------------
+// As in k_rod, what the first loads need leads the argument list (qpos, u_P,
+// q, st, u_Q, constraint count, grid size, step lengths: 14 dwords).
 template <int MODE>
-__global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
+__global__ void __launch_bounds__(kConBlock)
+    k_con(const int32_t *__restrict__ qpos, const double *__restrict__ uP, const double *__restrict__ qv,
+          const double2 *st, const double *__restrict__ uQ, int nc, unsigned nblk, const double *alpha_buf,
+          SolveArgs a, long long k)
 {
     __shared__ double lds[kConBlock / 64 + 1][4];
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const ConIn in{qpos, uP, qv, st, uQ};
+    const unsigned tile = xcd_tile(blockIdx.x, nblk);
     // each workgroup takes a contiguous chunk of constraints, two per lane per round
-    const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
+    const int64_t per = (nc + nblk - 1) / nblk;
+    const int64_t lo = (int64_t)tile * per, hi = lo + per < nc ? lo + per : nc;
     // first round peeled: its records are in flight before the stop flag and
     // the step length are read (every thread reaches the test)
     const int64_t step = (int64_t)kConCpl * kConBlock;
@@ -241,9 +254,9 @@ __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
     ConLoadsU L[kConCpl];
 #pragma unroll
     for (int u = 0; u < kConCpl; ++u)
-        if (c0 + u * kConBlock < hi) con_load_u<MODE>(a, c0 + u * kConBlock, L[u]);
+        if (c0 + u * kConBlock < hi) con_load_u<MODE>(in, c0 + u * kConBlock, L[u]);
     // the step length too (read for nothing after the stop)
-    const double alpha = MODE == kModeLoop ? a.alpha_buf[k & 1] : 0.0;
+    const double alpha = MODE == kModeLoop ? alpha_buf[k & 1] : 0.0;
     if (MODE != kModeApply && a.state->done) return;
     for (;;) {
 #pragma unroll
@@ -253,7 +266,7 @@ __global__ void __launch_bounds__(kConBlock) k_con(SolveArgs a, long long k)
         if (c0 >= hi) break;
 #pragma unroll
         for (int u = 0; u < kConCpl; ++u)
-            if (c0 + u * kConBlock < hi) con_load_u<MODE>(a, c0 + u * kConBlock, L[u]);
+            if (c0 + u * kConBlock < hi) con_load_u<MODE>(in, c0 + u * kConBlock, L[u]);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<kConBlock / 64>(p, lds);
@@ -515,6 +528,14 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     return RL_OK;
 }
 
+// the leading arguments of k_rod and k_con
+#define RL_ROD_HOT(a, grid) \
+    (const int32_t *)(a).pptr, (const int32_t *)(a).qptr, (const double2 *)(a).st, (const double2 *)(a).stq, \
+        (const double *)(a).geo, (const double *)(a).qgeo, (unsigned)(grid).x, (int)(a).n
+#define RL_CON_HOT(a) \
+    (const int32_t *)(a).qpos, (const double *)(a).uP, (const double *)(a).qv, (const double2 *)(a).st, \
+        (const double *)(a).uQ, (int)(a).nc, (unsigned)(a).gcon, (const double *)(a).alpha_buf
+
 // rod kernel grid: a multiple of 8 so that each XCD gets a contiguous range of rods
 static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
 
@@ -524,16 +545,18 @@ static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long 
     if (a.n <= 0) return hipSuccess;
     const dim3 grid(rod_grid(a.n));
     if (uni)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodLoopBlock), 0, st, a, k);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodLoopBlock), 0, st, RL_ROD_HOT(a, grid),
+                           a, k);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false>), grid, dim3(kRodLoopBlock), 0, st, a, k);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false>), grid, dim3(kRodLoopBlock), 0, st, RL_ROD_HOT(a, grid),
+                           a, k);
     return hipGetLastError();
 }
 
 template <int MODE>
 static hipError_t launch_con(hipStream_t st, const SolveArgs &a, long long k)
 {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE>), dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE>), dim3(a.gcon), dim3(kConBlock), 0, st, RL_CON_HOT(a), a, k);
     return hipGetLastError();
 }
 
@@ -561,15 +584,15 @@ static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs 
         const dim3 grid(rod_grid(a.n));
         if (uni)
             hipExtLaunchKernelGGL(k_rod<kModeLoop, true>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
-                                  h->ev[v][1], 0, a, (long long)it);
+                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
         else
             hipExtLaunchKernelGGL(k_rod<kModeLoop, false>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
-                                  h->ev[v][1], 0, a, (long long)it);
+                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipExtLaunchKernelGGL(k_con<kModeLoop>, dim3(a.gcon), dim3(kConBlock), 0, st, h->ev[v][2], h->ev[v][3], 0, a,
-                          (long long)it);
+    hipExtLaunchKernelGGL(k_con<kModeLoop>, dim3(a.gcon), dim3(kConBlock), 0, st, h->ev[v][2], h->ev[v][3], 0,
+                          RL_CON_HOT(a), a, (long long)it);
     return hipGetLastError();
 }
 
