@@ -39,10 +39,12 @@ struct BatchArgs {
     SolveArgs a;             // the concatenated system
     SolverState *sst;        // [S]
     double *alpha_s;         // [S][2]
-    // Tile records, one load each: rod tile t is rt[2t] = (first rod, end
-    // rod, system, publishes) and rt[2t+1] = (the system's first and end
-    // constraint tile, 0, 0); constraint tile t is ct[t] = (first constraint,
-    // end, system, 0).
+    // Tile records by workgroup (the host has applied the XCD-aware tile map
+    // and padded the grid to a multiple of 8 with records of system -1), one
+    // load each: the rod tile of workgroup w is rt[2w] = (first rod, end rod,
+    // system, publishes) and rt[2w+1] = (the system's first and end
+    // constraint tile, 0, 0); the constraint tile of workgroup w is ct[w] =
+    // (first constraint, end, system, tile number).
     const int4 *rt;
     const int4 *ct;
     const int *sys_c0;       // [S+1] first constraint tile of each system
@@ -73,19 +75,23 @@ __device__ __forceinline__ void latch(const BatchArgs &b, int s, long long k, co
     atomicAdd(b.ndone, 1);
 }
 
+// The tile table and the arrays of the first loads lead the argument list
+// (14 dwords, preloaded into registers).
 template <int MODE, bool UNI, int RB>
-__global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
+__global__ void __launch_bounds__(RB)
+    k_rod_b(const int4 *__restrict__ rt, const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr,
+            const double2 *sg, const double2 *sgq, const double *__restrict__ geo, const double *__restrict__ qgeo,
+            BatchArgs b, int i)
 {
     __shared__ double lds[RB / 64 + 1][4];
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    if ((int)tile >= b.nrb) return;
     const int sub = threadIdx.x & (kRodLanes - 1);
-    const int4 t0 = b.rt[2 * tile], t1 = b.rt[2 * tile + 1];
+    const int4 t0 = rt[2 * blockIdx.x], t1 = rt[2 * blockIdx.x + 1];
+    if (t0.z < 0) return;  // padding
     const int64_t r = (int64_t)t0.x + threadIdx.x / kRodLanes;
     const bool active = r < t0.y;
     // records first: they depend neither on the system's state nor on its step
     RodLoads L;
-    rod_load(b.a, r, active, sub, L);
+    rod_load(pptr, qptr, sg, sgq, geo, qgeo, r, active, sub, L);
     // the counter and the system's partials are read before the stop flag,
     // so that the three loads are in flight together.  The counter base is
     // even, so the parity of k is that of i: the partials' address does not
@@ -132,39 +138,42 @@ __global__ void __launch_bounds__(RB) k_rod_b(BatchArgs b, int i)
 }
 
 template <int MODE, int CB>
-__global__ void __launch_bounds__(CB) k_con_b(BatchArgs b, int i)
+__global__ void __launch_bounds__(CB)
+    k_con_b(const int4 *__restrict__ ct, const int32_t *__restrict__ qpos, const double *__restrict__ uP,
+            const double *__restrict__ qv, const double2 *sg, const double *__restrict__ uQ, const double *alpha_s,
+            BatchArgs b, int i)
 {
     __shared__ double lds[CB / 64 + 1][4];
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    if ((int)tile >= b.ncb) return;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const int4 tc = b.ct[tile];
+    const int4 tc = ct[blockIdx.x];
+    if (tc.z < 0) return;  // padding
+    const ConIn in{qpos, uP, qv, sg, uQ};
     const int64_t hi = tc.y;
     // first round peeled: its records are in flight before the system's stop
     // flag and step are read (every thread reaches the test)
     int64_t c0 = tc.x + threadIdx.x;
     ConLoadsU A, B;
-    if (c0 < hi) con_load_u<MODE>(b.a, c0, A);
-    if (c0 + CB < hi) con_load_u<MODE>(b.a, c0 + CB, B);
+    if (c0 < hi) con_load_u<MODE>(in, c0, A);
+    if (c0 + CB < hi) con_load_u<MODE>(in, c0 + CB, B);
     const int s = tc.z;
     SolverState *st = b.sst + s;
     // parity of the iteration = parity of i (the counter base is even); the
     // step length is read with the stop flag (for nothing after the stop)
     const int par = MODE == kModeLoop ? (i & 1) : 0;
-    const double alpha = MODE == kModeLoop ? b.alpha_s[2 * s + par] : 0.0;
+    const double alpha = MODE == kModeLoop ? alpha_s[2 * s + par] : 0.0;
     if (MODE != kModeApply && st->done) return;
     for (;;) {
         if (c0 < hi) con_update_u<MODE>(b.a, c0, A, alpha, p);
         if (c0 + CB < hi) con_update_u<MODE>(b.a, c0 + CB, B, alpha, p);
         c0 += 2 * CB;
         if (c0 >= hi) break;
-        con_load_u<MODE>(b.a, c0, A);
-        if (c0 + CB < hi) con_load_u<MODE>(b.a, c0 + CB, B);
+        con_load_u<MODE>(in, c0, A);
+        if (c0 + CB < hi) con_load_u<MODE>(in, c0 + CB, B);
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<CB / 64>(p, lds);
     if (threadIdx.x == 0) {
-        double2 *dst = reinterpret_cast<double2 *>(b.partial + ((int64_t)par * b.ncb + tile) * 4);
+        double2 *dst = reinterpret_cast<double2 *>(b.partial + ((int64_t)par * b.ncb + tc.w) * 4);
         dst[0] = make_double2(p[0], p[1]);
         dst[1] = make_double2(p[2], p[3]);
     }
@@ -303,14 +312,24 @@ static void build_tables(int S, const int64_t *rod_off, const int64_t *pair_off,
 
 static inline unsigned pad8(int n) { return (unsigned)((std::max(n, 1) + 7) / 8 * 8); }
 
+// the device's xcd_tile on the host
+static inline unsigned xcd_tile_host(unsigned b, unsigned nblocks)
+{
+    if (nblocks % 8 != 0) return b;
+    return (b % 8) * (nblocks / 8) + b / 8;
+}
+
 template <int MODE, int RB>
 static hipError_t launch_rod_b(hipStream_t st, const BatchArgs &b, bool uni, int i)
 {
     if (b.nrb == 0) return hipSuccess;
+    const SolveArgs &a = b.a;
     if (uni)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, true, RB>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b, i);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, true, RB>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b.rt,
+                           a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, false, RB>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b, i);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, false, RB>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b.rt,
+                           a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
     return hipGetLastError();
 }
 
@@ -318,7 +337,10 @@ template <int MODE, int CB>
 static hipError_t launch_con_b(hipStream_t st, const BatchArgs &b, int i)
 {
     if (b.ncb == 0) return hipSuccess;
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con_b<MODE, CB>), dim3(pad8(b.ncb)), dim3(CB), 0, st, b, i);
+    const SolveArgs &a = b.a;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con_b<MODE, CB>), dim3(pad8(b.ncb)), dim3(CB), 0, st, b.ct, a.qpos,
+                       (const double *)a.uP, a.qv, (const double2 *)a.st, (const double *)a.uQ,
+                       (const double *)b.alpha_s, b, i);
     return hipGetLastError();
 }
 
@@ -348,35 +370,48 @@ static hipError_t start_phases(hipStream_t st, const BatchArgs &b, bool uni, int
 static int upload_tables(rl_ctx *h, hipStream_t st, const BatchTables &t, int S, BatchArgs &b)
 {
     int werr = 0;
-    const size_t nr = std::max<size_t>(t.rsys.size(), 1), ncb = std::max<size_t>(t.csys.size(), 1);
+    const int nrt = (int)t.rsys.size(), nct = (int)t.csys.size();
+    const size_t nr = pad8(nrt), ncb = pad8(nct);  // workgroups of the two grids
     // int4 records first (16-byte aligned), then the per-system tile starts
     const size_t words = 4 * (2 * nr + ncb) + (S + 1);
     int *tab = (int *)ws_get(h, kWsBatchTab, sizeof(int) * words, &werr);
     int *host = (int *)ws_get_host(h, sizeof(int) * words, &werr);
     if (werr) return werr;
     std::fill(host, host + words, 0);
-    for (size_t j = 0; j < t.rsys.size(); ++j) {
+    // workgroup w takes tile xcd_tile(w): each XCD a contiguous range of tiles
+    for (size_t w = 0; w < nr; ++w) {
+        const int j = (int)xcd_tile_host((unsigned)w, (unsigned)nr);
+        int *o = host + 8 * w;
+        if (j >= nrt) {
+            o[2] = -1;
+            continue;
+        }
         const int s = t.rsys[j];
-        int *o = host + 8 * j;
         o[0] = t.rlo[j];
         o[1] = t.rhi[j];
         o[2] = s;
-        o[3] = (int)j == t.sr0[s];
+        o[3] = j == t.sr0[s];
         o[4] = t.sc0[s];
         o[5] = t.sc0[s + 1];
     }
-    for (size_t j = 0; j < t.csys.size(); ++j) {
-        int *o = host + 8 * nr + 4 * j;
+    for (size_t w = 0; w < ncb; ++w) {
+        const int j = (int)xcd_tile_host((unsigned)w, (unsigned)ncb);
+        int *o = host + 8 * nr + 4 * w;
+        if (j >= nct) {
+            o[2] = -1;
+            continue;
+        }
         o[0] = t.clo[j];
         o[1] = t.chi[j];
         o[2] = t.csys[j];
+        o[3] = j;
     }
     std::copy(t.sc0.begin(), t.sc0.end(), host + 4 * (2 * nr + ncb));
     b.rt = reinterpret_cast<const int4 *>(tab);
     b.ct = reinterpret_cast<const int4 *>(tab + 8 * nr);
     b.sys_c0 = tab + 4 * (2 * nr + ncb);
-    b.nrb = (int)t.rsys.size();
-    b.ncb = (int)t.csys.size();
+    b.nrb = nrt;
+    b.ncb = nct;
     RL_HIP(hipMemcpyAsync(tab, host, sizeof(int) * words, hipMemcpyHostToDevice, st));
     RL_HIP(hipStreamSynchronize(st));
     return RL_OK;
