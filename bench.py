@@ -46,6 +46,20 @@ def kernel_bytes(n: int, nc: int) -> dict:
     return {"rod": 32 * n + 112 * nc, "con": 76 * nc}
 
 
+def con_kernel_name(nc: int, fp32: bool = False) -> str:
+    """The constraint kernel's instantiation for nc constraints: the library
+    sizes its grid at about 2,048 constraints per workgroup (at least one, at
+    most 512, a multiple of 8) and takes 256 threads with 8 constraints each
+    once a workgroup's share exceeds 2,048, else 512 threads with 4 (FP64) or
+    2 (FP32)."""
+    g = min(max((nc + 2047) // 2048, 1), 512)
+    g = (g + 7) // 8 * 8
+    wide = (nc + g - 1) // g > 2048
+    if fp32:
+        return "k_con32<256,8>" if wide else "k_con32<512,2>"
+    return "k_con<2,256,8>" if wide else "k_con<2,512,4>"
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -139,8 +153,8 @@ def form_precision(args, torch, rl, rodsynth) -> dict:
         prof = slv.profile_read()
         slv.close()
         kb = (kernel_bytes if prec == rl.FP64 else kernel_bytes32)(s.n, npairs)
-        names = {"rod": "k_rod<2,false>", "con": "k_con<2>"} if prec == rl.FP64 else \
-            {"rod": "k_rod32<false>", "con": "k_con32"}
+        names = {"rod": "k_rod<2,false>", "con": con_kernel_name(npairs)} if prec == rl.FP64 else \
+            {"rod": "k_rod32<false>", "con": con_kernel_name(npairs, fp32=True)}
         avg, kern = _kernel_summary(prof, kb, names)
         dom = max(avg, key=avg.get)
         ach = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
@@ -393,7 +407,7 @@ def main() -> int:
     kb = kernel_bytes(s.n, npairs)
     avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
            "con": prof["con_ms"] / max(1, prof["con_launches"])}
-    names = {"rod": "k_rod<2,true>", "con": "k_con<2>"}
+    names = {"rod": "k_rod<2,true>", "con": con_kernel_name(npairs)}
     dom = max(avg, key=avg.get)
     achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     traffic = measured_traffic(dom)

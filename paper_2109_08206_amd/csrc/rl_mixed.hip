@@ -237,38 +237,47 @@ __device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, cons
     p[3] = fmax(p[3], fabs(gam < (double)h ? gam : (double)h));
 }
 
-__global__ void __launch_bounds__(kConBlock) k_con32(SolveArgs a, long long k)
+// CB threads per workgroup take CPL constraints each per round; the shape is
+// chosen per launch like that of the FP64 constraint kernel.
+template <int CB, int CPL>
+__global__ void __launch_bounds__(CB) k_con32(SolveArgs a, long long k)
 {
-    __shared__ double lds[kConBlock / 64 + 1][4];
+    __shared__ double lds[CB / 64 + 1][4];
     double p[4] = {0.0, 0.0, 0.0, 0.0};
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
-    // the first two records go out before the flags are read; nothing in this
+    // the first round goes out before the flags are read; nothing in this
     // launch writes the flags, so the early return is uniform
     int64_t c0 = lo + threadIdx.x;
-    Con32Loads A, B;
-    if (c0 < hi) con32_load(a, c0, A);
-    if (c0 + kConBlock < hi) con32_load(a, c0 + kConBlock, B);
+    Con32Loads L[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+        if (c0 + u * CB < hi) con32_load(a, c0 + u * CB, L[u]);
     const double a64 = a.alpha_buf[k & 1];  // read with the flags (for nothing after a stop)
     if (a.state->done || a.state->refresh) return;
     const float a32 = (float)a64;
-    while (c0 < hi) {
-        const int64_t c1 = c0 + kConBlock;
-        con32_update(a, c0, A, a32, p);
-        if (c1 < hi) con32_update(a, c1, B, a32, p);
-        c0 += 2 * kConBlock;
+    for (;;) {
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+            if (c0 + u * CB < hi) con32_update(a, c0 + u * CB, L[u], a32, p);
+        c0 += (int64_t)CPL * CB;
         if (c0 >= hi) break;
-        con32_load(a, c0, A);
-        if (c0 + kConBlock < hi) con32_load(a, c0 + kConBlock, B);
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+            if (c0 + u * CB < hi) con32_load(a, c0 + u * CB, L[u]);
     }
-    block_reduce4_all<kConBlock / 64>(p, lds);
+    block_reduce4_all<CB / 64>(p, lds);
     if (threadIdx.x == 0) {
         double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)(k & 1) * a.gcon * 4 + 4 * blockIdx.x);
         dst[0] = make_double2(p[0], p[1]);
         dst[1] = make_double2(p[2], p[3]);
     }
 }
+
+// more than 2,048 constraints per workgroup: 256 threads with 8 each, else
+// 512 threads with 2 each
+static inline bool con32_wide(const SolveArgs &a) { return (a.nc + a.gcon - 1) / a.gcon > 2048; }
 
 int prepare_mixed(rl_ctx *h, SolveArgs &a)
 {
@@ -312,6 +321,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
     long long k = 0, round_start = 0, launched = 0;
     bool first = true;
     const dim3 rgrid(rod_grid32(a.n));
+    const bool wide = con32_wide(a);
     while (!h->state_host->done) {
         if (launched > p.max_iter + 4 * every + 64) {
             set_error("rl_solve_lcp: mixed-precision loop did not stop");
@@ -334,8 +344,12 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                 else
                     hipExtLaunchKernelGGL(k_rod32<false>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
                                           h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
-                hipExtLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, h->ev[nev][2], h->ev[nev][3],
-                                      0, a, (long long)k);
+                if (wide)
+                    hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
+                                          h->ev[nev][2], h->ev[nev][3], 0, a, (long long)k);
+                else
+                    hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<512, 2>), dim3(a.gcon), dim3(512), 0, st,
+                                          h->ev[nev][2], h->ev[nev][3], 0, a, (long long)k);
                 ++nev;
             } else {
                 if (uni)
@@ -344,7 +358,10 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                 else
                     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodLoopBlock), 0, st, a, k, fl,
                                        round_start);
-                hipLaunchKernelGGL(k_con32, dim3(a.gcon), dim3(kConBlock), 0, st, a, k);
+                if (wide)
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st, a, k);
+                else
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<512, 2>), dim3(a.gcon), dim3(512), 0, st, a, k);
             }
             RL_HIP(hipGetLastError());
         }
