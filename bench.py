@@ -329,7 +329,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rods", type=int, default=100_000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--profile-every", type=int, default=8, help="sample kernel events every k-th iteration")
+    ap.add_argument("--profile-every", type=int, default=32, help="sample kernel events every k-th iteration (each sample costs a few us of launch overhead)")
     ap.add_argument("--cpu-iters", type=int, default=800, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=["step", "precision", "batched", "adjoint"], default="step",
