@@ -368,23 +368,33 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
                 stage_cell<INTERNAL>(Nb, b0, nn, shift, sorted, xs, ds, ls);
                 __syncthreads();
                 const int total = na * nn;
+                // (a, b) of entry e = a nn + b, advanced by kPairBlock entries
+                // per step without a division
+                const int step_a = kPairBlock / nn, step_b = kPairBlock % nn;
                 for (int base = 0; base < total; base += kQueue) {
                     if (threadIdx.x == 0) qn = 0;
                     __syncthreads();
                     const int lim = total - base < kQueue ? total - base : kQueue;
+                    int a = (base + (int)threadIdx.x) / nn, b = (base + (int)threadIdx.x) - a * nn;
                     for (int e = threadIdx.x; e < lim; e += kPairBlock) {
-                        const int a = (base + e) / nn, b = (base + e) % nn;
-                        const int i = H.idx[a], j = Nb.idx[b];
+                        const int ca = a, cb = b;
+                        a += step_a;
+                        b += step_b;
+                        if (b >= nn) {
+                            b -= nn;
+                            ++a;
+                        }
+                        const int i = H.idx[ca], j = Nb.idx[cb];
                         if (j < i || (j == i && !selfok)) continue;
-                        const V3 r0 = v3(H.p[0][a] - Nb.p[0][b], H.p[1][a] - Nb.p[1][b], H.p[2][a] - Nb.p[2][b]);
-                        const double reach = 0.5 * (H.p[6][a] + Nb.p[6][b]) + diam + cutoff;
+                        const V3 r0 = v3(H.p[0][ca] - Nb.p[0][cb], H.p[1][ca] - Nb.p[1][cb], H.p[2][ca] - Nb.p[2][cb]);
+                        const double reach = 0.5 * (H.p[6][ca] + Nb.p[6][cb]) + diam + cutoff;
                         if (dot(r0, r0) >= reach * reach) continue;
                         // two segments are never closer than their axis lines (margin
                         // far above rounding; near-parallel lines go through)
-                        const V3 nrm = cross(v3(H.p[3][a], H.p[4][a], H.p[5][a]), v3(Nb.p[3][b], Nb.p[4][b], Nb.p[5][b]));
+                        const V3 nrm = cross(v3(H.p[3][ca], H.p[4][ca], H.p[5][ca]), v3(Nb.p[3][cb], Nb.p[4][cb], Nb.p[5][cb]));
                         const double nn2 = dot(nrm, nrm), rn = dot(r0, nrm);
                         if (nn2 > 1e-6 && rn * rn > gap2 * nn2) continue;
-                        queue[atomicAdd(&qn, 1)] = (a << 16) | b;
+                        queue[atomicAdd(&qn, 1)] = (ca << 16) | cb;
                     }
                     __syncthreads();
                     const int nq = qn;
