@@ -50,3 +50,15 @@ def test_status_strings_without_gpu():
     # a NULL handle is rejected before any device work
     assert lib.rl_reserve(None, 10, 10) == rl.ERR_ARG
     assert lib.rl_create(None, None) == rl.ERR_ARG
+
+
+def test_missing_library_fails_loudly():
+    """No CPU fallback: without the built library the binding raises."""
+    import sys
+    code = ("import paper_2109_08206_amd as rl\n"
+            "try:\n"
+            "    rl.load('/nonexistent/librodlcp.so')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
+    assert out.returncode == 0 and out.stdout.startswith("raised") and "not built" in out.stdout
