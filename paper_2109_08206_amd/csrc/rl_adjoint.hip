@@ -196,28 +196,33 @@ __device__ __forceinline__ void cg_emit(double *u, const double *geo, int b, int
 // else: they depend on neither the step scalars nor the stop flag.  Every
 // workgroup then sums the partials of iteration k-1 and takes the stop
 // decision; workgroup 0 publishes the step scalars and latches the stop.
+// The arrays of the first loads, the grid size and n lead the argument list
+// (14 dwords, preloaded into registers).
 template <bool UNI>
-__global__ void __launch_bounds__(kRodLoopBlock) k_cg_rod(CgArgs g, long long k)
+__global__ void __launch_bounds__(kRodLoopBlock)
+    k_cg_rod(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const double *cr0,
+             const double *cq0, const double *__restrict__ geo, const double *__restrict__ qgeo, unsigned nblk, int n,
+             CgArgs g, long long k)
 {
     __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     const SolveArgs &a = g.a;
     SolverState *st = a.state;
     const int sub = threadIdx.x & (kRodLanes - 1);
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned tile = xcd_tile(blockIdx.x, nblk);
     const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
-    const bool active = r < a.n;
+    const bool active = r < n;
     int pb = 0, pe = 0, qb = 0, qe = 0;
     if (active) {
-        pb = a.pptr[r] + sub;
-        pe = a.pptr[r + 1];
-        qb = a.qptr[r] + sub;
-        qe = a.qptr[r + 1];
+        pb = pptr[r] + sub;
+        pe = pptr[r + 1];
+        qb = qptr[r] + sub;
+        qe = qptr[r + 1];
     }
     CgRec P[kRodRounds], Q[kRodRounds];
 #pragma unroll
     for (int i = 0; i < kRodRounds; ++i) {
-        cg_rec_load(g.cr, a.geo, pb + i * kRodLanes, pe, P[i]);
-        cg_rec_load(g.cq, a.qgeo, qb + i * kRodLanes, qe, Q[i]);
+        cg_rec_load(cr0, geo, pb + i * kRodLanes, pe, P[i]);
+        cg_rec_load(cq0, qgeo, qb + i * kRodLanes, qe, Q[i]);
     }
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
@@ -302,18 +307,23 @@ struct CgConLoads {
     int qp;
 };
 
-__device__ __forceinline__ void cg_con_load(const CgArgs &g, int64_t c, CgConLoads &L)
+// the CG constraint kernel's inputs (preloaded leading arguments)
+struct CgConIn {
+    const int32_t *qpos;
+    const double *uP, *uQ, *cs, *cr;
+};
+
+__device__ __forceinline__ void cg_con_load(const CgConIn &in, int64_t c, CgConLoads &L)
 {
-    const SolveArgs &a = g.a;
-    const double2 *cs = reinterpret_cast<const double2 *>(g.cs + 4 * c);
-    const double2 *cr = reinterpret_cast<const double2 *>(g.cr + 4 * c);
-    L.qp = a.qpos[c];
-    L.up = a.uP[c];
+    const double2 *cs = reinterpret_cast<const double2 *>(in.cs + 4 * c);
+    const double2 *cr = reinterpret_cast<const double2 *>(in.cr + 4 * c);
+    L.qp = in.qpos[c];
+    L.up = in.uP[c];
     L.lp = cs[0];
     L.mk = cs[1];
     L.rs = cr[0];
     L.w0 = cr[1];
-    L.uq = a.uQ[L.qp];
+    L.uq = in.uQ[L.qp];
 }
 
 __device__ __forceinline__ void cg_con_update(const CgArgs &g, int64_t c, const CgConLoads &L, long long k,
@@ -346,22 +356,25 @@ __device__ __forceinline__ void cg_con_update(const CgArgs &g, int64_t c, const 
 // (r_k.r_k, r_k.w_k).  Like the BBPGD constraint kernel, each lane takes
 // kConCpl constraints per round, and the first round's loads and the step
 // scalars are in flight before the stop flag is read.
-__global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
+__global__ void __launch_bounds__(kConBlock)
+    k_cg_con(const int32_t *__restrict__ qpos, const double *__restrict__ uP, const double *__restrict__ uQ,
+             const double *cs0, const double *cr0, int nc, unsigned nblk, const double *ab, CgArgs g, long long k)
 {
     __shared__ double lds[kConBlock / 64 + 1][4];
     const SolveArgs &a = g.a;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
+    const CgConIn in{qpos, uP, uQ, cs0, cr0};
+    const unsigned tile = xcd_tile(blockIdx.x, nblk);
+    const int64_t per = (nc + nblk - 1) / nblk;
+    const int64_t lo = (int64_t)tile * per, hi = lo + per < nc ? lo + per : nc;
     const int64_t step = (int64_t)kConCpl * kConBlock;
     int64_t c0 = lo + threadIdx.x;
     CgConLoads L[kConCpl];
 #pragma unroll
     for (int u = 0; u < kConCpl; ++u)
-        if (c0 + u * kConBlock < hi) cg_con_load(g, c0 + u * kConBlock, L[u]);
-    const double alpha = k > 0 ? g.ab[2 * ((k - 1) & 1)] : 0.0;
-    const double beta = k > 0 ? g.ab[2 * ((k - 1) & 1) + 1] : 0.0;
+        if (c0 + u * kConBlock < hi) cg_con_load(in, c0 + u * kConBlock, L[u]);
+    const double alpha = k > 0 ? ab[2 * ((k - 1) & 1)] : 0.0;
+    const double beta = k > 0 ? ab[2 * ((k - 1) & 1) + 1] : 0.0;
     if (a.state->done) return;
     for (;;) {
 #pragma unroll
@@ -371,7 +384,7 @@ __global__ void __launch_bounds__(kConBlock) k_cg_con(CgArgs g, long long k)
         if (c0 >= hi) break;
 #pragma unroll
         for (int u = 0; u < kConCpl; ++u)
-            if (c0 + u * kConBlock < hi) cg_con_load(g, c0 + u * kConBlock, L[u]);
+            if (c0 + u * kConBlock < hi) cg_con_load(in, c0 + u * kConBlock, L[u]);
     }
     block_reduce4_all<kConBlock / 64>(p, lds);
     if (threadIdx.x == 0) {
@@ -622,13 +635,18 @@ int adjoint_core(rl_ctx *h, SolveArgs &a, bool step, const double *Ubar, const d
         auto enqueue = [&](int cnt) -> int {
             for (int k = 0; k < cnt; ++k, ++launched) {
                 if (uni)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<true>), rgrid, dim3(kRodLoopBlock), 0, st, g,
-                                       launched);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<true>), rgrid, dim3(kRodLoopBlock), 0, st,
+                                       (const int32_t *)a.pptr, (const int32_t *)a.qptr, (const double *)g.cr,
+                                       (const double *)g.cq, a.geo, a.qgeo, (unsigned)rgrid.x, (int)a.n, g, launched);
                 else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<false>), rgrid, dim3(kRodLoopBlock), 0, st, g,
-                                       launched);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_cg_rod<false>), rgrid, dim3(kRodLoopBlock), 0, st,
+                                       (const int32_t *)a.pptr, (const int32_t *)a.qptr, (const double *)g.cr,
+                                       (const double *)g.cq, a.geo, a.qgeo, (unsigned)rgrid.x, (int)a.n, g, launched);
                 RL_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_cg_con, dim3(a.gcon), dim3(kConBlock), 0, st, g, launched);
+                hipLaunchKernelGGL(k_cg_con, dim3(a.gcon), dim3(kConBlock), 0, st, (const int32_t *)a.qpos,
+                                   (const double *)a.uP, (const double *)a.uQ, (const double *)g.cs,
+                                   (const double *)g.cr, (int)a.nc, (unsigned)a.gcon, (const double *)g.ab, g,
+                                   launched);
                 RL_HIP(hipGetLastError());
             }
             return RL_OK;

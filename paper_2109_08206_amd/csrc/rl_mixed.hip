@@ -107,28 +107,33 @@ __device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__re
 // Rod kernel of the inner FP32 iteration: the force of delta' on the rod,
 // then the velocity of each of its contact points along e (contact-velocity
 // form, as in the FP64 rod kernel).
+// The arrays of the first loads, the grid size and n lead the argument list
+// (14 dwords), so that they arrive in preloaded registers.
 template <bool UNI>
-__global__ void __launch_bounds__(kRodLoopBlock) k_rod32(SolveArgs a, long long k, int first, long long round_start)
+__global__ void __launch_bounds__(kRodLoopBlock)
+    k_rod32(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const float4 *s32, const float4 *sq32,
+            const float4 *__restrict__ g32, const float4 *__restrict__ gq32, unsigned nblk, int n, SolveArgs a,
+            long long k, int first, long long round_start)
 {
     __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     SolverState *st = a.state;
     const int sub = threadIdx.x & (kRodLanes - 1);
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned tile = xcd_tile(blockIdx.x, nblk);
     const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
-    const bool active = r < a.n;
+    const bool active = r < n;
     int pb = 0, pe = 0, qb = 0, qe = 0;
     if (active) {
-        pb = a.pptr[r] + sub;
-        pe = a.pptr[r + 1];
-        qb = a.qptr[r] + sub;
-        qe = a.qptr[r + 1];
+        pb = pptr[r] + sub;
+        pe = pptr[r + 1];
+        qb = qptr[r] + sub;
+        qe = qptr[r + 1];
     }
     // two rounds of both sides in flight before the flags are read
     Rec32 p1, q1, p2, q2;
-    rec32_load(a.st32, a.geo32, pb, pe, p1);
-    rec32_load(a.stq32, a.qgeo32, qb, qe, q1);
-    rec32_load(a.st32, a.geo32, pb + kRodLanes, pe, p2);
-    rec32_load(a.stq32, a.qgeo32, qb + kRodLanes, qe, q2);
+    rec32_load(s32, g32, pb, pe, p1);
+    rec32_load(sq32, gq32, qb, qe, q1);
+    rec32_load(s32, g32, pb + kRodLanes, pe, p2);
+    rec32_load(sq32, gq32, qb + kRodLanes, qe, q2);
     // and the previous iteration's partials (read for nothing on a first iteration)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
@@ -213,12 +218,13 @@ struct Con32Loads {
     int qp;
 };
 
-__device__ __forceinline__ void con32_load(const SolveArgs &a, int64_t c, Con32Loads &L)
+__device__ __forceinline__ void con32_load(const int32_t *qpos, const float *uP32, const float4 *st32,
+                                           const float *uQ32, int64_t c, Con32Loads &L)
 {
-    L.qp = a.qpos[c];
-    L.up = a.uP32[c];
-    L.s = a.st32[c];
-    L.uq = a.uQ32[L.qp];
+    L.qp = qpos[c];
+    L.up = uP32[c];
+    L.s = st32[c];
+    L.uq = uQ32[L.qp];
 }
 
 __device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, const Con32Loads &L, float a32,
@@ -239,22 +245,25 @@ __device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, cons
 
 // CB threads per workgroup take CPL constraints each per round; the shape is
 // chosen per launch like that of the FP64 constraint kernel.
+// As in k_rod32, what the first loads need leads the argument list.
 template <int CB, int CPL>
-__global__ void __launch_bounds__(CB) k_con32(SolveArgs a, long long k)
+__global__ void __launch_bounds__(CB)
+    k_con32(const int32_t *__restrict__ qpos, const float *__restrict__ uP32, const float4 *s32,
+            const float *__restrict__ uQ32, int nc, unsigned nblk, const double *alpha_buf, SolveArgs a, long long k)
 {
     __shared__ double lds[CB / 64 + 1][4];
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t per = (a.nc + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)tile * per, hi = lo + per < a.nc ? lo + per : a.nc;
+    const unsigned tile = xcd_tile(blockIdx.x, nblk);
+    const int64_t per = (nc + nblk - 1) / nblk;
+    const int64_t lo = (int64_t)tile * per, hi = lo + per < nc ? lo + per : nc;
     // the first round goes out before the flags are read; nothing in this
     // launch writes the flags, so the early return is uniform
     int64_t c0 = lo + threadIdx.x;
     Con32Loads L[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u)
-        if (c0 + u * CB < hi) con32_load(a, c0 + u * CB, L[u]);
-    const double a64 = a.alpha_buf[k & 1];  // read with the flags (for nothing after a stop)
+        if (c0 + u * CB < hi) con32_load(qpos, uP32, s32, uQ32, c0 + u * CB, L[u]);
+    const double a64 = alpha_buf[k & 1];  // read with the flags (for nothing after a stop)
     if (a.state->done || a.state->refresh) return;
     const float a32 = (float)a64;
     for (;;) {
@@ -265,7 +274,7 @@ __global__ void __launch_bounds__(CB) k_con32(SolveArgs a, long long k)
         if (c0 >= hi) break;
 #pragma unroll
         for (int u = 0; u < CPL; ++u)
-            if (c0 + u * CB < hi) con32_load(a, c0 + u * CB, L[u]);
+            if (c0 + u * CB < hi) con32_load(qpos, uP32, s32, uQ32, c0 + u * CB, L[u]);
     }
     block_reduce4_all<CB / 64>(p, lds);
     if (threadIdx.x == 0) {
@@ -274,6 +283,14 @@ __global__ void __launch_bounds__(CB) k_con32(SolveArgs a, long long k)
         dst[1] = make_double2(p[2], p[3]);
     }
 }
+
+// the leading arguments of k_rod32 and k_con32
+#define RL_ROD32_HOT(a, grid)                                                                              \
+    (const int32_t *)(a).pptr, (const int32_t *)(a).qptr, (const float4 *)(a).st32, (const float4 *)(a).stq32, \
+        (const float4 *)(a).geo32, (const float4 *)(a).qgeo32, (unsigned)(grid).x, (int)(a).n
+#define RL_CON32_HOT(a)                                                                                   \
+    (const int32_t *)(a).qpos, (const float *)(a).uP32, (const float4 *)(a).st32, (const float *)(a).uQ32, \
+        (int)(a).nc, (unsigned)(a).gcon, (const double *)(a).alpha_buf
 
 // more than 2,048 constraints per workgroup: 256 threads with 8 each, else
 // 512 threads with 2 each
@@ -340,28 +357,32 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                 h->ev_iter[nev] = k;
                 if (uni)
                     hipExtLaunchKernelGGL(k_rod32<true>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
-                                          h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
+                                          h->ev[nev][1], 0, RL_ROD32_HOT(a, rgrid), a, (long long)k, fl,
+                                          (long long)round_start);
                 else
                     hipExtLaunchKernelGGL(k_rod32<false>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
-                                          h->ev[nev][1], 0, a, (long long)k, fl, (long long)round_start);
+                                          h->ev[nev][1], 0, RL_ROD32_HOT(a, rgrid), a, (long long)k, fl,
+                                          (long long)round_start);
                 if (wide)
                     hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
-                                          h->ev[nev][2], h->ev[nev][3], 0, a, (long long)k);
+                                          h->ev[nev][2], h->ev[nev][3], 0, RL_CON32_HOT(a), a, (long long)k);
                 else
                     hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<512, 2>), dim3(a.gcon), dim3(512), 0, st,
-                                          h->ev[nev][2], h->ev[nev][3], 0, a, (long long)k);
+                                          h->ev[nev][2], h->ev[nev][3], 0, RL_CON32_HOT(a), a, (long long)k);
                 ++nev;
             } else {
                 if (uni)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodLoopBlock), 0, st, a, k, fl,
-                                       round_start);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodLoopBlock), 0, st,
+                                       RL_ROD32_HOT(a, rgrid), a, k, fl, round_start);
                 else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodLoopBlock), 0, st, a, k, fl,
-                                       round_start);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodLoopBlock), 0, st,
+                                       RL_ROD32_HOT(a, rgrid), a, k, fl, round_start);
                 if (wide)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st, a, k);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
+                                       RL_CON32_HOT(a), a, k);
                 else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<512, 2>), dim3(a.gcon), dim3(512), 0, st, a, k);
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<512, 2>), dim3(a.gcon), dim3(512), 0, st,
+                                       RL_CON32_HOT(a), a, k);
             }
             RL_HIP(hipGetLastError());
         }
