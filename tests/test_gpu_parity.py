@@ -87,6 +87,20 @@ def test_pairs_small_boxes_and_lengths(gpu_lib, n, phi, length):
     _assert_pairs_match(got, want)
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pairs_hub(gpu_lib, seed):
+    """One rod of length 4 among 36 crossing rods in a box of 10 (two cells
+    per side, so the stencil wraps onto the same cells): the pair list is the
+    brute force's, bit for bit."""
+    s = rodsynth.cfg_hub(seed)
+    d = oracle.directors(s.quat)
+    want = oracle.pairs(s.x, d, s.length, s.box, s.diam, s.cutoff, method="brute")
+    assert np.sum(want.pi == 18) == 18 and np.sum(want.pj == 18) == 18
+    with _solver(gpu_lib, s) as slv:
+        got = _gpu_pairs(gpu_lib, slv, s, _t(d))
+    _assert_pairs_match(got, want)
+
+
 def test_pairs_hand_cases(gpu_lib):
     def q_for(v):
         v = np.asarray(v, float) / np.linalg.norm(v)
