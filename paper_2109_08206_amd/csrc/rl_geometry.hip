@@ -262,9 +262,14 @@ constexpr int kPairBlock = 256;
 constexpr int kCellChunk = 256;  // rods of one cell staged at a time
 constexpr int kQueue = 4096;     // candidate (home, neighbour) pairs per flush
 
+// The staged copies are FP32, with the centres relative to the home cell's
+// corner (so they stay within a few cells of 0 and round finely): the cheap
+// tests run on them with margins that cover FP32 rounding, so that they
+// never drop a pair the FP64 tests would keep; the exact test of a survivor
+// reads the FP64 values from the cell-order arrays.
 struct CellStage {
-    double p[7][kCellChunk];  // x, y, z, dx, dy, dz, length
-    int idx[kCellChunk];      // rod index (the caller's or the cell order's)
+    float p[7][kCellChunk];  // x, y, z (shifted by image - corner), dx, dy, dz, length
+    int idx[kCellChunk];     // rod index (the caller's or the cell order's)
 };
 
 template <bool INTERNAL>
@@ -273,13 +278,13 @@ __device__ __forceinline__ void stage_cell(CellStage &S, int q0, int m, V3 shift
 {
     for (int u = threadIdx.x; u < m; u += kPairBlock) {
         const int64_t q = q0 + u;
-        S.p[0][u] = xs[3 * q] + shift.x;
-        S.p[1][u] = xs[3 * q + 1] + shift.y;
-        S.p[2][u] = xs[3 * q + 2] + shift.z;
-        S.p[3][u] = ds[3 * q];
-        S.p[4][u] = ds[3 * q + 1];
-        S.p[5][u] = ds[3 * q + 2];
-        S.p[6][u] = ls[q];
+        S.p[0][u] = (float)(xs[3 * q] + shift.x);
+        S.p[1][u] = (float)(xs[3 * q + 1] + shift.y);
+        S.p[2][u] = (float)(xs[3 * q + 2] + shift.z);
+        S.p[3][u] = (float)ds[3 * q];
+        S.p[4][u] = (float)ds[3 * q + 1];
+        S.p[5][u] = (float)ds[3 * q + 2];
+        S.p[6][u] = (float)ls[q];
         S.idx[u] = INTERNAL ? (int)q : sorted[q];
     }
 }
@@ -336,11 +341,19 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
     const int h = blockIdx.x;
     const int hz = h % g.nc[2], hy = (h / g.nc[2]) % g.nc[1], hx = h / (g.nc[2] * g.nc[1]);
     const int hb = cell_start[h], he = cell_start[h + 1];
-    const double gap = diam + cutoff + 1e-9, gap2 = gap * gap;
+    // FP32 margins.  Staged centres lie within S + 1 cells of the corner (S <=
+    // 7), so a component of r0 carries at most 1e-6 x cell of rounding, and
+    // directions 6e-8 per component.  The reach test gets 1e-3 + 1e-5 x reach
+    // more.  The axis-line test runs only where |d_i x d_j|^2 > 1e-5 (|n| >
+    // 3.1e-3) and gets 1e-2 x (1 + reach) on the gap: the rounding of r0 . n,
+    // below 2.2e-6 x reach (cell <= reach), is then under a tenth of
+    // margin x |n|.
+    const float greach = (float)(diam + cutoff), fgap0 = (float)(diam + cutoff) + 1e-2f;
+    const V3 corner = v3(hx * g.cell[0], hy * g.cell[1], hz * g.cell[2]);
     const int NY = 2 * g.S[1] + 1, NZ = 2 * g.S[2] + 1, NS = (2 * g.S[0] + 1) * NY * NZ;
     for (int a0 = hb; a0 < he; a0 += kCellChunk) {
         const int na = he - a0 < kCellChunk ? he - a0 : kCellChunk;
-        stage_cell<INTERNAL>(H, a0, na, v3(0.0, 0.0, 0.0), sorted, xs, ds, ls);
+        stage_cell<INTERNAL>(H, a0, na, v3(-corner.x, -corner.y, -corner.z), sorted, xs, ds, ls);
         for (int u = threadIdx.x; u < na; u += kPairBlock) {
             hcnt[u] = 0;
             if (PASS == kPairFill) hoff[u] = poff[INTERNAL ? a0 + u : sorted[a0 + u]];
@@ -365,7 +378,8 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
                 // chunk holds no j >= i
                 if (INTERNAL && b0 + nn <= a0) continue;
                 __syncthreads();
-                stage_cell<INTERNAL>(Nb, b0, nn, shift, sorted, xs, ds, ls);
+                stage_cell<INTERNAL>(Nb, b0, nn, v3(shift.x - corner.x, shift.y - corner.y, shift.z - corner.z),
+                                     sorted, xs, ds, ls);
                 __syncthreads();
                 const int total = na * nn;
                 // (a, b) of entry e = a nn + b, advanced by kPairBlock entries
@@ -386,14 +400,19 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
                         }
                         const int i = H.idx[ca], j = Nb.idx[cb];
                         if (j < i || (j == i && !selfok)) continue;
-                        const V3 r0 = v3(H.p[0][ca] - Nb.p[0][cb], H.p[1][ca] - Nb.p[1][cb], H.p[2][ca] - Nb.p[2][cb]);
-                        const double reach = 0.5 * (H.p[6][ca] + Nb.p[6][cb]) + diam + cutoff;
-                        if (dot(r0, r0) >= reach * reach) continue;
-                        // two segments are never closer than their axis lines (margin
-                        // far above rounding; near-parallel lines go through)
-                        const V3 nrm = cross(v3(H.p[3][ca], H.p[4][ca], H.p[5][ca]), v3(Nb.p[3][cb], Nb.p[4][cb], Nb.p[5][cb]));
-                        const double nn2 = dot(nrm, nrm), rn = dot(r0, nrm);
-                        if (nn2 > 1e-6 && rn * rn > gap2 * nn2) continue;
+                        const float rx = H.p[0][ca] - Nb.p[0][cb], ry = H.p[1][ca] - Nb.p[1][cb],
+                                    rz = H.p[2][ca] - Nb.p[2][cb];
+                        const float reach0 = 0.5f * (H.p[6][ca] + Nb.p[6][cb]) + greach;
+                        const float reach = reach0 * (1.0f + 1e-5f) + 1e-3f;
+                        if (rx * rx + ry * ry + rz * rz >= reach * reach) continue;
+                        // two segments are never closer than their axis lines
+                        // (near-parallel lines go through)
+                        const float ax = H.p[3][ca], ay = H.p[4][ca], az = H.p[5][ca];
+                        const float bx = Nb.p[3][cb], by = Nb.p[4][cb], bz = Nb.p[5][cb];
+                        const float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+                        const float nn2 = nx * nx + ny * ny + nz * nz, rn = rx * nx + ry * ny + rz * nz;
+                        const float fgap = fgap0 + 1e-2f * reach0;
+                        if (nn2 > 1e-5f && rn * rn > fgap * fgap * nn2) continue;
                         queue[atomicAdd(&qn, 1)] = (ca << 16) | cb;
                     }
                     __syncthreads();
@@ -401,9 +420,11 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
                     int mine = 0;
                     for (int u = threadIdx.x; u < nq; u += kPairBlock) {
                         const int a = (queue[u] >> 16) & 0xff, b = queue[u] & 0xff;
-                        const V3 xi = v3(H.p[0][a], H.p[1][a], H.p[2][a]), di = v3(H.p[3][a], H.p[4][a], H.p[5][a]);
-                        const V3 xj = v3(Nb.p[0][b], Nb.p[1][b], Nb.p[2][b]), dj = v3(Nb.p[3][b], Nb.p[4][b], Nb.p[5][b]);
-                        const Contact c = closest_point(xi, di, 0.5 * H.p[6][a], xj, dj, 0.5 * Nb.p[6][b]);
+                        const int64_t qa = a0 + a, qb = b0 + b;
+                        const V3 xi = load3(xs + 3 * qa), di = load3(ds + 3 * qa);
+                        const V3 xq = load3(xs + 3 * qb), dj = load3(ds + 3 * qb);
+                        const V3 xj = v3(xq.x + shift.x, xq.y + shift.y, xq.z + shift.z);
+                        const Contact c = closest_point(xi, di, 0.5 * ls[qa], xj, dj, 0.5 * ls[qb]);
                         const double phi = c.dist - diam;
                         if (!(phi < cutoff)) continue;
                         const unsigned fl = c.flags | (fabs(phi - cutoff) <= kCutoffBand ? 1u : 0u);
