@@ -108,3 +108,37 @@ def test_batched_rejects_cross_system_pairs(gpu_lib, batch):
     with pytest.raises(gpu_lib.RodLCPError) as ei:
         _run(gpu_lib, systems, bad, rods, pairs, 256, 256)
     assert ei.value.status == gpu_lib.ERR_ARG
+
+
+def test_batched_varied_lengths(gpu_lib):
+    """Per-rod lengths (the kernels' per-rod mobility path), with the hub
+    system (one rod 4 long with 18 incidences on each side) among rods of
+    lengths in [0.5, 1.5]: each system matches the oracle."""
+    systems = [rodsynth.make_system(300, seed=1, phi=0.04, length=(0.5, 1.5)), rodsynth.cfg_hub(1),
+               rodsynth.make_system(500, seed=5, phi=0.05, length=(0.5, 1.5))]
+    per, rods, pairs = [], [0], [0]
+    cat = {k: [] for k in ("dir", "len", "pi", "pj", "e", "arm", "q", "F")}
+    for s in systems:
+        d = oracle.directors(s.quat)
+        pr = oracle.pairs(s.x, d, s.length, s.box, s.diam, s.cutoff)
+        cs = oracle.assemble(s.x, d, s.length, s.box, s.diam, s.eta, s.dt, pr, s.force)
+        per.append((s, d, pr, cs))
+        for k, v in (("dir", d), ("len", s.length), ("pi", pr.pi + rods[-1]), ("pj", pr.pj + rods[-1]),
+                     ("e", cs.e), ("arm", cs.arm), ("q", cs.q), ("F", s.force)):
+            cat[k].append(v)
+        rods.append(rods[-1] + s.n)
+        pairs.append(pairs[-1] + pr.n)
+    arr = {k: np.concatenate(v) for k, v in cat.items()}
+    with gpu_lib.Solver(box=1.0, tol=1e-8, max_iter=100_000) as slv:
+        g, U, infos = slv.solve_lcp_batched(
+            np.array(rods), np.array(pairs), _t(arr["dir"]), _t(arr["len"]), _t(arr["pi"], torch.int32),
+            _t(arr["pj"], torch.int32), _t(arr["e"]), _t(arr["arm"]), _t(arr["q"]), F=_t(arr["F"]))
+    g, U = g.cpu().numpy(), U.cpu().numpy()
+    for k, (s, d, pr, cs) in enumerate(per):
+        assert infos[k].status == gpu_lib.OK and infos[k].residual <= 1e-8, (k, infos[k])
+        gk, Uk = g[pairs[k]:pairs[k + 1]], U[rods[k]:rods[k + 1]]
+        w = oracle.apply_Mc(d, s.length, s.diam, s.eta, pr, cs, gk)
+        assert np.abs(np.minimum(gk, w)).max(initial=0.0) <= 1e-8 + 1e-12 * np.abs(cs.q).max(initial=1.0)
+        ref = oracle.bbpgd(d, s.length, s.diam, s.eta, pr, cs, tol=1e-8)
+        Uref = oracle.velocity(d, s.length, s.diam, s.eta, pr, cs, ref.gamma, s.force)
+        assert np.linalg.norm(Uk - Uref) <= 1e-6 * np.linalg.norm(Uref), k
