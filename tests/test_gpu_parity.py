@@ -5,6 +5,7 @@ flagged within 1e-9 of the threshold; phi, e, arm and q agree to 1e-12
 (relative to the magnitude of q for q); Mc gamma + q to 1e-12 relative;
 velocities U = M(D gamma + F) to 1e-6 relative (2-norm over all rods) with
 both residuals <= 1e-8, because gamma need not be unique while U is."""
+import ctypes
 import math
 
 import numpy as np
@@ -350,3 +351,26 @@ def test_step_empty(gpu_lib):
         q = torch.zeros((0, 4), dtype=torch.float64, device=DEV)
         U, info, npairs = slv.step(x, q, 1.0, F=torch.zeros((0, 6), dtype=torch.float64, device=DEV))
     assert npairs == 0 and info.status == gpu_lib.OK
+
+
+def test_reserve_and_params(gpu_lib):
+    """rl_reserve pre-sizes the workspace without changing any result, and
+    rl_set_params / rl_get_params round-trip (a changed tolerance is used)."""
+    s = rodsynth.cfg_small(2)
+    outs = []
+    for reserve in (False, True):
+        with _solver(gpu_lib, s) as slv:
+            if reserve:
+                slv.reserve(20_000, 200_000)
+            U, info, npairs = slv.step(_t(s.x), _t(s.quat), 1.0, F=_t(s.force))
+            outs.append((U.cpu().numpy(), info.iterations, npairs))
+    assert outs[0][2] == outs[1][2] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+    with _solver(gpu_lib, s) as slv:
+        slv.set_params(tol=1e-4)
+        got = type(slv.params)()
+        assert gpu_lib.load().rl_get_params(slv._h, ctypes.byref(got)) == 0
+        assert got.tol == 1e-4 and got.diam == s.diam
+        _, info, _ = slv.step(_t(s.x), _t(s.quat), 1.0, F=_t(s.force))
+    # the same iterates as with 1e-8, stopped at the first one within 1e-4
+    assert info.status == gpu_lib.OK and info.residual <= 1e-4 and info.iterations <= outs[0][1]
