@@ -102,6 +102,15 @@ __global__ void __launch_bounds__(RB)
     if (MODE == kModeLoop) partials_first(part, t1.y - t1.x, pf);
     const int s = t0.z;
     SolverState *st = b.sst + s;
+    // the rod's direction and mobility and the system's step-rule inputs
+    // (the parity of i is that of k) are read before the flag too
+    const SolveArgs &a = b.a;
+    const int64_t rr = active ? r : 0;
+    const double dx = a.dir[3 * rr], dy = a.dir[3 * rr + 1], dz = a.dir[3 * rr + 2];
+    double apar, aperp, rperp;
+    rod_mob(a, rr, UNI, apar, aperp, rperp);
+    DecideIn din{};
+    if (MODE == kModeLoop) din = decide_in(st, b.alpha_s + 2 * s, (long long)i);
     if (MODE != kModeApply && st->done) return;
     const long long k = kb + i;
     double alpha = 0.0;
@@ -114,7 +123,7 @@ __global__ void __launch_bounds__(RB)
         } else {
             double t[4];
             sum_partials_from<RB / 64>(pf, part, t1.y - t1.x, t, lds);
-            const Decision d = decide(st, abuf, k, t);
+            const Decision d = decide_from(din, k, t);
             if (publisher) {
                 if (d.stop) latch(b, s, k, t, d.status);
                 else abuf[k & 1] = d.alpha;
@@ -126,10 +135,6 @@ __global__ void __launch_bounds__(RB)
     double f[3], m[3];
     rod_accumulate<MODE>(b.a, L, alpha, f, m);
     if (!active) return;
-    const SolveArgs &a = b.a;
-    const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
-    double apar, aperp, rperp;
-    rod_mob(a, r, UNI, apar, aperp, rperp);
     const double fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
     const double md = dx * m[0] + dy * m[1] + dz * m[2];
     const double v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};

@@ -183,6 +183,14 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
     if (MODE == kModeLoop) partials_first(part, a.gcon, pf);
+    // and the rod's direction and mobility and the inputs of the step rule,
+    // which do not depend on the partials either
+    const int64_t rr = active ? r : 0;
+    const double dx = a.dir[3 * rr], dy = a.dir[3 * rr + 1], dz = a.dir[3 * rr + 2];
+    double apar, aperp, rperp;
+    rod_mob(a, rr, UNI, apar, aperp, rperp);
+    DecideIn din{};
+    if (MODE == kModeLoop) din = decide_in(a.state, a.alpha_buf, k);
     if (MODE != kModeApply && a.state->done) return;
     if (MODE == kModeLoop) {
         if (k == 0) {
@@ -191,7 +199,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
         } else {
             double t[4];
             sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
-            const Decision d = decide(a.state, a.alpha_buf, k, t);
+            const Decision d = decide_from(din, k, t);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 if (d.stop) {
                     SolverState *st = a.state;
@@ -213,9 +221,6 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     double f[3], m[3];
     rod_accumulate<MODE>(a, L, alpha, f, m);
     if (!active) return;
-    const double dx = a.dir[3 * r], dy = a.dir[3 * r + 1], dz = a.dir[3 * r + 2];
-    double apar, aperp, rperp;
-    rod_mob(a, r, UNI, apar, aperp, rperp);
     // translation a_perp f + (a_par - a_perp)(d.f) d; rotation Omega =
     // r_perp dir x m (normal to the axis) and Omega x dir = r_perp (m - (d.m) d)
     const double fd = (apar - aperp) * (dx * f[0] + dy * f[1] + dz * f[2]);
@@ -226,9 +231,6 @@ __global__ void __launch_bounds__(kRodLoopBlock)
 }
 
 
-// ---------------------------------------------------------------------------
-// constraint kernel
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // constraint kernel
 // ---------------------------------------------------------------------------
