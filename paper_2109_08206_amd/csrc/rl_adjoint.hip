@@ -227,6 +227,16 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
     partials_first(part, a.gcon, pf);
+    // the recurrence's other inputs and the rod's direction and mobility do
+    // not depend on the partials either
+    const double bb0 = st->alpha0, tol = st->tol;
+    const long long max_iter = st->max_iter;
+    const int ps = 2 * (int)((k - 2) & 1);  // (rho, alpha) of iteration k - 2
+    const double rho_prev = g.sc[ps], a_prev = g.sc[ps + 1];
+    const int64_t rr = active ? r : 0;
+    const V3 d = load3(a.dir + 3 * rr);
+    double apar, aperp, rperp;
+    rod_mob(a, rr, UNI, apar, aperp, rperp);
     if (st->done) return;
     double t[4];
     sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
@@ -248,18 +258,17 @@ __global__ void __launch_bounds__(kRodLoopBlock)
         if (stop) return;
     } else {
         const long long j = k - 1;
-        const double rho = t[0], del = t[1], bb = st->alpha0;
+        const double rho = t[0], del = t[1], bb = bb0;
         if (j == 0) {
             alpha = rho / del;
         } else {
-            const double rho0 = g.sc[2 * ((j - 1) & 1)], a0 = g.sc[2 * ((j - 1) & 1) + 1];
-            beta = rho / rho0;
-            alpha = rho / (del - beta * rho / a0);
+            beta = rho / rho_prev;
+            alpha = rho / (del - beta * rho / a_prev);
         }
         int status = 1000;
         if (!isfinite(rho) || !isfinite(del)) status = RL_ERR_NONFINITE;
-        else if (rho <= st->tol * st->tol * bb) status = RL_OK;
-        else if (j >= st->max_iter) status = RL_NOT_CONVERGED;
+        else if (rho <= tol * tol * bb) status = RL_OK;
+        else if (j >= max_iter) status = RL_NOT_CONVERGED;
         else if (!(alpha > 0.0) || !isfinite(alpha)) status = RL_STAGNATED;
         const bool stop = status != 1000;
         if (lead) {
@@ -283,15 +292,12 @@ __global__ void __launch_bounds__(kRodLoopBlock)
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            f[d] += __shfl_xor(f[d], o, 64);
-            m[d] += __shfl_xor(m[d], o, 64);
+        for (int c = 0; c < 3; ++c) {
+            f[c] += __shfl_xor(f[c], o, 64);
+            m[c] += __shfl_xor(m[c], o, 64);
         }
     }
     if (!active) return;
-    const V3 d = load3(a.dir + 3 * r);
-    double apar, aperp, rperp;
-    rod_mob(a, r, UNI, apar, aperp, rperp);
     // translation M_t f; rotation Omega = r_perp d x m and Omega x d = r_perp (m - (d.m) d)
     const double fd = (apar - aperp) * (d.x * f[0] + d.y * f[1] + d.z * f[2]);
     const double md = d.x * m[0] + d.y * m[1] + d.z * m[2];
