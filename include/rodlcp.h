@@ -97,7 +97,9 @@ typedef struct {
     double tol;         /* BBPGD stops when max_c |min(gamma_c, w_c)| <= tol */
     int64_t max_iter;   /* BBPGD iteration cap, >= 0 */
     int32_t precision;  /* RL_FP64 or RL_FP32_MIXED */
-    int32_t check_every;/* iterations between host checks of the stop flag; 0 = default */
+    int32_t check_every;/* iterations between host checks of the stop flag; 0 = default (32).  Up to 8
+                           more iterations are queued behind each check; after the stop they
+                           return at once without touching the result */
 } rl_params;
 
 typedef struct {
@@ -214,8 +216,9 @@ int rl_solve_lcp_batched(rl_handle h, int32_t S, const int64_t *rod_off, const i
                          rl_solve_info *infos);
 /* Workgroup sizes of the batched kernels: rod_block in {256, 1024} and
  * con_block in {256, 512}, or both 0 to time the candidates on the first
- * solve of each problem size (the default; cached in the handle and appended
- * to the file named by the environment variable RODLCP_TUNE_CACHE if set).
+ * solve of each problem size (the default; (256, 256) is kept unless another
+ * pair is at least 3% faster; cached in the handle and appended to the file
+ * named by the environment variable RODLCP_TUNE_CACHE if set).
  * chosen (host, may be NULL) receives the sizes the last solve used. */
 int rl_batch_tuning(rl_handle h, int rod_block, int con_block, int *chosen);
 
