@@ -341,9 +341,6 @@ def main() -> int:
     ap.add_argument("--no-tape", action="store_true",
                     help="adjoint form: re-solve each step cold in the backward pass instead of replaying gamma")
     ap.add_argument("--phi", type=float, default=None, help="volume fraction override (precision form)")
-    ap.add_argument("--loop", choices=["launch", "persistent"], default="launch",
-                    help="step form: schedule of the FP64 loop (two launches per iteration, or one "
-                         "persistent cooperative launch per solve)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 1 GiB device buffer once (reference for HBM counters)")
     args = ap.parse_args()
@@ -376,8 +373,7 @@ def main() -> int:
     F = torch.as_tensor(s.force, device=dev)
     x, q = torch.empty_like(x0), torch.empty_like(q0)
     U = torch.empty((s.n, 6), dtype=torch.float64, device=dev)
-    slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8, max_iter=200_000,
-                    loop={"launch": rl.LOOP_LAUNCH, "persistent": rl.LOOP_PERSISTENT}[args.loop])
+    slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8, max_iter=200_000)
 
     def one_step():
         x.copy_(x0)
@@ -388,7 +384,6 @@ def main() -> int:
         one_step()
     slv.profile_enable(args.profile_every)
     slv.profile_read()
-    slv.profile_read_loop()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters, npairs, res, status = 0, 0, 0.0, 0
@@ -400,7 +395,6 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = slv.profile_read()
-    ploop = slv.profile_read_loop()
     slv.profile_enable(0)
 
     elapsed = t1 - t0
@@ -439,8 +433,6 @@ def main() -> int:
         "kernels": {names[k]: {"avg_us": 1e3 * avg[k], "alg_bytes": kb[k],
                                "alg_gbps": kb[k] / (avg[k] * 1e-3) / 1e9 if avg[k] > 0 else 0.0,
                                "samples": prof[f"{k}_launches"]} for k in ("rod", "con")},
-        "persistent_loop": {"launches": ploop["launches"], "iterations": ploop["iterations"],
-                            "us_per_iteration": 1e3 * ploop["ms"] / max(1, ploop["iterations"])},
     }
     slv.close()
     if args.copy_calibration:

@@ -174,6 +174,9 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
  * first line; Psi of Appendix "Filament dynamics").  x and quat are updated
  * in place; U (may be NULL) receives the velocities; *n_pairs (host, may be
  * NULL) the constraint count.  Pair and constraint storage is the handle's.
+ * The step synchronises its stream: the pair count sizes the constraint
+ * arrays and the BBPGD loop's length is decided by its stop test, both read
+ * on the host (a whole step is therefore not capturable in a graph).
  *
  * Tape (for differentiating rollouts): the step's constraint forces gamma,
  * in the step's own constraint order (the canonical pair order of the rods
@@ -193,9 +196,16 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
 #define RL_TAPE_NONE 0
 #define RL_TAPE_RECORD 1
 #define RL_TAPE_REPLAY 2
+/* Optional parts of a step (extra may be NULL: none of them).
+ *   x_unwrapped[n][3]  device, in/out: the centres without periodic
+ *                      wrapping; the step adds h U_t to them (the same
+ *                      increment as x, eq. constrainedeom_euler, first line). */
+typedef struct {
+    double *x_unwrapped;
+} rl_step_extra;
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
             double *U, rl_solve_info *info, int64_t *n_pairs, double *gamma_tape, int64_t tape_len,
-            int32_t tape_mode);
+            int32_t tape_mode, const rl_step_extra *extra);
 
 /* Batching form: S independent periodic systems solved together (one set
  * of launches per BBPGD phase for all of them, iterations replayed from a
@@ -296,27 +306,6 @@ int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat,
 int rl_profile_enable(rl_handle h, int every);
 int rl_profile_read(rl_handle h, double *out);
 
-/* How the FP64 BBPGD loop of rl_solve_lcp / rl_step runs (the iteration of
- * Section "Instantiation in a massively parallel computing environment"; the
- * arithmetic per constraint and per rod is the same, only the schedule and
- * the order of the step-length partial sums differ):
- *   RL_LOOP_LAUNCH     two kernel launches per iteration (the default);
- *   RL_LOOP_PERSISTENT one cooperative launch per solve: one workgroup per
- *                      compute unit owns a block of rods and keeps their
- *                      incidence geometry in LDS, two grid barriers per
- *                      iteration.  The solve returns RL_ERR_ARG when the rods
- *                      do not split into such blocks (the geometry of the
- *                      largest block must fit 156 KB of LDS).
- * RL_FP32_MIXED, the batched and the adjoint solves always launch per
- * iteration.  RL_ERR_ARG on another value. */
-#define RL_LOOP_LAUNCH 0
-#define RL_LOOP_PERSISTENT 1
-int rl_set_loop(rl_handle h, int mode);
-
-/* Timing of the persistent loop, for measurement: writes {ms_total,
- * iterations_total, launches} of the persistent launches since the last call
- * (HIP events around each launch) to out[3] (host) and resets them. */
-int rl_profile_read_loop(rl_handle h, double *out);
 
 #ifdef __cplusplus
 }

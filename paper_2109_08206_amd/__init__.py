@@ -22,7 +22,6 @@ OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
 ERR_ARG, ERR_CAPACITY, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = -1, -2, -3, -4, -5
 FP64, FP32_MIXED = 0, 1
 TAPE_NONE, TAPE_RECORD, TAPE_REPLAY = 0, 1, 2
-LOOP_LAUNCH, LOOP_PERSISTENT = 0, 1
 IMG_ZERO = 0x888
 
 _lib = None
@@ -46,6 +45,10 @@ class SolveInfo(C.Structure):
                 ("status", C.c_int32), ("fp64_refreshes", C.c_int32)]
 
 
+class StepExtra(C.Structure):
+    _fields_ = [("x_unwrapped", C.c_void_p)]
+
+
 class AdjointInfo(C.Structure):
     _fields_ = [("cg_iterations", C.c_int64), ("cg_residual", C.c_double), ("n_active", C.c_int64),
                 ("status", C.c_int32), ("solve_status", C.c_int32), ("solve_iterations", C.c_int64),
@@ -55,7 +58,7 @@ class AdjointInfo(C.Structure):
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
-           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_set_loop", "rl_profile_read_loop")
+           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -84,8 +87,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_assemble_D": ([H, I64, P, P, P, D, I64, P, P, P, P, P, P, P, P], C.c_int),
             "rl_apply_M": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P], C.c_int),
             "rl_solve_lcp": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)], C.c_int),
-            "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64), P, I64, I32],
-                        C.c_int),
+            "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64), P, I64, I32,
+                         C.POINTER(StepExtra)], C.c_int),
             "rl_profile_enable": ([H, C.c_int], C.c_int),
             "rl_solve_lcp_batched": ([H, I32, P, P, P, P, D, P, P, P, P, P, P, P, P, P], C.c_int),
             "rl_batch_tuning": ([H, C.c_int, C.c_int, P], C.c_int),
@@ -93,8 +96,6 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_solve_lcp_adjoint": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, D, P, P, P, P, P,
                                       C.POINTER(AdjointInfo)], C.c_int),
             "rl_step_adjoint": ([H, I64, P, P, P, D, P, P, I64, P, P, P, D, C.POINTER(AdjointInfo)], C.c_int),
-            "rl_set_loop": ([H, C.c_int], C.c_int),
-            "rl_profile_read_loop": ([H, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -166,18 +167,12 @@ class Solver:
     """One library handle: parameters, stream and workspace."""
 
     def __init__(self, box, diam=0.025, cutoff=0.05, eta=0.01, dt=1e-4, tol=1e-8, max_iter=100_000,
-                 precision=FP64, check_every=0, loop=None):
+                 precision=FP64, check_every=0):
         self.lib = load()
         self._h = C.c_void_p()
         self.params = Params()
         self.set_params(box=box, diam=diam, cutoff=cutoff, eta=eta, dt=dt, tol=tol, max_iter=max_iter,
                         precision=precision, check_every=check_every, _create=True)
-        if loop is not None:
-            self.set_loop(loop)
-
-    def set_loop(self, mode: int):
-        """LOOP_LAUNCH (default) or LOOP_PERSISTENT: schedule of the FP64 loop."""
-        self._check(self.lib.rl_set_loop(self._h, int(mode)), "rl_set_loop")
 
     # -- lifecycle ------------------------------------------------------------
     def set_params(self, _create=False, **kw):
@@ -227,12 +222,6 @@ class Solver:
         out = (C.c_double * 4)()
         self._check(self.lib.rl_profile_read(self._h, out), "rl_profile_read")
         return {"rod_ms": out[0], "rod_launches": int(out[1]), "con_ms": out[2], "con_launches": int(out[3])}
-
-    def profile_read_loop(self):
-        """{'ms', 'iterations', 'launches'} of the persistent loop since the last read."""
-        out = (C.c_double * 3)()
-        self._check(self.lib.rl_profile_read_loop(self._h, out), "rl_profile_read_loop")
-        return {"ms": out[0], "iterations": int(out[1]), "launches": int(out[2])}
 
     def reserve(self, max_rods, max_pairs):
         self._check(self.lib.rl_reserve(self._h, int(max_rods), int(max_pairs)), "rl_reserve")
@@ -353,10 +342,11 @@ class Solver:
         self._check(self.lib.rl_batch_tuning(self._h, int(rod_block), int(con_block), out), "rl_batch_tuning")
         return int(out[0]), int(out[1])
 
-    def step(self, x, quat, length, F=None, U=None, tape=None, tape_mode=TAPE_NONE):
+    def step(self, x, quat, length, F=None, U=None, tape=None, tape_mode=TAPE_NONE, x_unwrapped=None):
         """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs).
         tape: float64 device tensor for the step's constraint forces
-        (TAPE_RECORD writes them, TAPE_REPLAY starts from them)."""
+        (TAPE_RECORD writes them, TAPE_REPLAY starts from them).
+        x_unwrapped: [n, 3] centres without wrapping, advanced in place."""
         torch = _torch()
         n = x.shape[0]
         la, l0 = _len_args(length, n)
@@ -364,12 +354,13 @@ class Solver:
         info = SolveInfo()
         npairs = C.c_int64(0)
         tlen = 0 if tape is None else int(tape.shape[0])
+        extra = StepExtra(_ptr(x_unwrapped, torch.float64, (n, 3), "x_unwrapped"))
         self._stream()
         rc = self.lib.rl_step(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
                               _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
                               _ptr(F, torch.float64, (n, 6), "F"), _ptr(U, torch.float64, (n, 6), "U"),
                               C.byref(info), C.byref(npairs), _ptr(tape, torch.float64, None, "tape"), tlen,
-                              int(tape_mode))
+                              int(tape_mode), C.byref(extra))
         if rc == ERR_CAPACITY and tape_mode == TAPE_RECORD:
             err = RodLCPError(rc, "rl_step", f"tape too short for {int(npairs.value)} constraints")
             err.count = int(npairs.value)
@@ -377,14 +368,15 @@ class Solver:
         self._check(rc, "rl_step")
         return U, _result(info), int(npairs.value)
 
-    def step_recording(self, x, quat, length, F=None, U=None, capacity=None):
+    def step_recording(self, x, quat, length, F=None, U=None, capacity=None, x_unwrapped=None):
         """step() that records its tape; returns (U, SolveResult, tape)."""
         torch = _torch()
         cap = int(capacity) if capacity is not None else 16 * x.shape[0] + 64
         for _ in range(2):
             tape = torch.empty(max(cap, 1), dtype=torch.float64, device=x.device)
             try:
-                U, info, npairs = self.step(x, quat, length, F=F, U=U, tape=tape, tape_mode=TAPE_RECORD)
+                U, info, npairs = self.step(x, quat, length, F=F, U=U, tape=tape, tape_mode=TAPE_RECORD,
+                                            x_unwrapped=x_unwrapped)
                 return U, info, tape[:npairs]
             except RodLCPError as err:
                 if err.status != ERR_CAPACITY:

@@ -177,8 +177,6 @@ int rl_destroy(rl_handle h)
     for (int v = 0; v < rl_ctx::kMaxEv; ++v)
         for (int k = 0; k < 4; ++k)
             if (h->ev[v][k]) (void)hipEventDestroy(h->ev[v][k]);
-    for (int k = 0; k < 2; ++k)
-        if (h->pev[k]) (void)hipEventDestroy(h->pev[k]);
     if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
     for (int s = 0; s < rl_ctx::kSlots; ++s)
         if (h->buf[s]) (void)hipFree(h->buf[s]);
@@ -311,7 +309,7 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
 
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
             double *U, rl_solve_info *info, int64_t *n_pairs, double *gamma_tape, int64_t tape_len,
-            int32_t tape_mode)
+            int32_t tape_mode, const rl_step_extra *extra)
 {
     RL_CHECK_HANDLE(h);
     RL_REQUIRE(n >= 0 && n < 0x7fffffff, "rl_step: bad n");
@@ -368,11 +366,11 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     else
         RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, h->stream));
     SolveArgs a;
-    rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a);
+    rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a, true);
     if (rc) return rc;
     rc = solve_impl(h, a, F, Uw, tape_mode != RL_TAPE_NONE && np > 0 ? gamma_tape : gamma, info, perm);
     if (rc < 0) return rc;
-    const int rc2 = integrate_impl(h, n, Uw, x, quat);
+    const int rc2 = integrate_impl(h, n, Uw, x, quat, extra ? extra->x_unwrapped : nullptr);
     if (rc2) return rc2;
     RL_HIP(hipStreamSynchronize(h->stream));
     return rc;
@@ -462,7 +460,7 @@ int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat,
     else
         RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, st));
     SolveArgs a;
-    rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a);
+    rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a, true);
     if (rc) return rc;
     rl_solve_info si{0, 0.0, 0.0, RL_OK, 0};
     const int src = solve_impl(h, a, F, Uc, nullptr, &si, perm);
@@ -527,25 +525,6 @@ int rl_profile_enable(rl_handle h, int every)
     RL_CHECK_HANDLE(h);
     RL_REQUIRE(every >= 0, "rl_profile_enable: every < 0");
     h->prof_every = every;
-    return RL_OK;
-}
-
-int rl_set_loop(rl_handle h, int mode)
-{
-    RL_CHECK_HANDLE(h);
-    RL_REQUIRE(mode == RL_LOOP_LAUNCH || mode == RL_LOOP_PERSISTENT, "rl_set_loop: unknown mode");
-    h->loop_mode = mode;
-    return RL_OK;
-}
-
-int rl_profile_read_loop(rl_handle h, double *out)
-{
-    RL_CHECK_HANDLE(h);
-    RL_REQUIRE(out != nullptr, "rl_profile_read_loop: NULL out");
-    out[0] = h->persist_ms;
-    out[1] = h->persist_iters;
-    out[2] = h->persist_launches;
-    h->persist_ms = h->persist_iters = h->persist_launches = 0.0;
     return RL_OK;
 }
 

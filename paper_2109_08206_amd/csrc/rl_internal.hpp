@@ -157,11 +157,7 @@ struct rl_ctx {
     long long ev_iter[kMaxEv] = {};
     double prof_ms[2] = {0.0, 0.0};
     double prof_cnt[2] = {0.0, 0.0};
-    // persistent loop: its launch events, time and iterations since the last read
-    hipEvent_t pev[2] = {};
     hipEvent_t chk_ev = nullptr;  // marks the state copy of a stop-flag check
-    double persist_ms = 0.0, persist_iters = 0.0, persist_launches = 0.0;
-    int loop_mode = RL_LOOP_LAUNCH;
     // batched solves: a stream of our own (graph capture), workgroup sizes
     hipStream_t own_stream = nullptr;
     int batch_rb = 0, batch_cb = 0;            // fixed by the caller; 0 = tune
@@ -184,7 +180,6 @@ enum Slot : int {
     kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs, kWsQv, kWsUP, kWsUQ,
-    kWsPersistMap, kWsPersistBar, kWsPersistPart,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -216,28 +211,22 @@ int build_pairs_sorted(rl_ctx *h, int64_t n, const double *x, const double *dir,
 int assemble_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                   int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
                   double *phi, double *e, double *arm, double *q);
+// trusted: the pair list was built by the library itself (rl_step), so the
+// index checks and their host sync are skipped
 int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
                   const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
-                  double *gamma, SolveArgs *a);
+                  double *gamma, SolveArgs *a, bool trusted = false);
 int apply_impl(rl_ctx *h, SolveArgs &a, double *w);
 int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamma_out, rl_solve_info *info,
                const int *perm = nullptr);
-int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat);
+// xu (may be null): unwrapped centres, += h U_t without wrapping
+int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat, double *xu = nullptr);
 // mixed precision: FP32 copies of the geometry, then the refinement loop
 int prepare_mixed(rl_ctx *h, SolveArgs &a);
 int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes);
 // FP64 refresh for the mixed solver: gamma64 += delta (if accum), g64 = Mc gamma64 + q,
 // certified residual, FP32 state reset
 hipError_t launch_refresh64(rl_ctx *h, const SolveArgs &a, bool accum);
-// persistent FP64 loop (rl_persist.hip): the rods' split into one block per
-// compute unit, and the loop itself (after the start phases)
-struct PersistPlan {
-    bool ok = false;
-    int G = 0, cap = 0, rmax = 0;
-    std::vector<int> wr0;  // [G+1] first rod of each block
-};
-int persistent_plan(rl_ctx *h, const SolveArgs &a, PersistPlan *plan);
-int solve_loop_persistent(rl_ctx *h, const SolveArgs &a, const PersistPlan &plan, float *ms);
 hipError_t launch_alpha0_64(rl_ctx *h, const SolveArgs &a);
 hipError_t launch_velocity64(rl_ctx *h, const SolveArgs &a, const double *F, const int *perm, double *U);
 hipError_t launch_velocity_on(hipStream_t st, const SolveArgs &a, const double *F, const int *perm, double *U);

@@ -408,18 +408,21 @@ __global__ void k_mix_accum(int64_t nc, const float4 *__restrict__ st32, const i
     stq[qpos[c]].x = g;
 }
 
-// x += h U_t wrapped into [0, box); theta += h Psi(theta) Omega, renormalised.
+// x += h U_t wrapped into [0, box); theta += h Psi(theta) Omega, renormalised;
+// xu (may be null) += h U_t without wrapping.
 __global__ void k_integrate(int64_t n, const double *__restrict__ U, double *__restrict__ x, double *__restrict__ quat,
-                            double dt, double b0, double b1, double b2)
+                            double *__restrict__ xu, double dt, double b0, double b1, double b2)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double box[3] = {b0, b1, b2};
     for (int a = 0; a < 3; ++a) {
-        double v = x[3 * i + a] + dt * U[6 * i + a];
+        const double dx = dt * U[6 * i + a];
+        double v = x[3 * i + a] + dx;
         v -= box[a] * floor(v / box[a]);
         if (v >= box[a]) v -= box[a];
         x[3 * i + a] = v;
+        if (xu) xu[3 * i + a] += dx;
     }
     const double wx = U[6 * i + 3], wy = U[6 * i + 4], wz = U[6 * i + 5];
     double s = quat[4 * i], px = quat[4 * i + 1], py = quat[4 * i + 2], pz = quat[4 * i + 3];
@@ -444,7 +447,7 @@ __global__ void k_integrate(int64_t n, const double *__restrict__ U, double *__r
 // ---------------------------------------------------------------------------
 int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
                   const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
-                  double *gamma, SolveArgs *out)
+                  double *gamma, SolveArgs *out, bool trusted)
 {
     hipStream_t st = h->stream;
     const rl_params &p = h->prm;
@@ -495,12 +498,15 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     RL_HIP(hipMemsetAsync(h->flag_dev, 0, sizeof(int), st));
     hipLaunchKernelGGL(k_check_pairs, dim3(grid_of(nc + 1)), dim3(kBlock), 0, st, n, nc, pi, pj, pptr, h->flag_dev);
     RL_HIP(hipGetLastError());
-    RL_HIP(hipMemcpyAsync(h->host_scratch, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
-    RL_HIP(hipStreamSynchronize(st));
-    const int ferr = ((int *)h->host_scratch)[0];
-    if (ferr) {
-        set_error(ferr & 1 ? "pair indices must satisfy 0 <= pi <= pj < n" : "pi must be non-decreasing");
-        return RL_ERR_ARG;
+    if (!trusted) {
+        // a caller's list: its indices must be valid before k_qcount scatters through pj
+        RL_HIP(hipMemcpyAsync(h->host_scratch, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipStreamSynchronize(st));
+        const int ferr = ((int *)h->host_scratch)[0];
+        if (ferr) {
+            set_error(ferr & 1 ? "pair indices must satisfy 0 <= pi <= pj < n" : "pi must be non-decreasing");
+            return RL_ERR_ARG;
+        }
     }
     if (n > 0) {
         RL_HIP(hipMemsetAsync(qcnt, 0, sizeof(int) * n, st));
@@ -647,24 +653,7 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         RL_HIP(launch_con<kModeAlpha0>(st, a, 0));
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
         RL_HIP(hipGetLastError());
-        PersistPlan plan;
-        if (h->loop_mode == RL_LOOP_PERSISTENT) {
-            int rc = persistent_plan(h, a, &plan);
-            if (rc) return rc;
-            if (!plan.ok) {
-                set_error("rl_solve_lcp: the persistent loop does not fit this problem");
-                return RL_ERR_ARG;
-            }
-        }
         const int every = p.check_every > 0 ? p.check_every : 32;
-        if (plan.ok) {
-            float ms = 0.f;
-            int rc = solve_loop_persistent(h, a, plan, &ms);
-            if (rc) return rc;
-            h->persist_ms += ms;
-            h->persist_iters += (double)h->state_host->iter;
-            h->persist_launches += 1.0;
-        }
         // Host checks of the stop flag: after each batch of `every` iterations the
         // state is copied back while `la` more are already queued, so the GPU does
         // not wait for the host; iterations queued past the stop exit at once.
@@ -689,7 +678,7 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
             }
             return RL_OK;
         };
-        if (!plan.ok) {
+        {
             if (!h->chk_ev) RL_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
             int rc = enqueue(every);
             if (rc) return rc;
@@ -728,73 +717,6 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
                 }
                 if ((rc = enqueue(every - la))) return rc;
             }
-        }
-        iters = h->state_host->iter;
-        if (gamma_out) {
-            hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
-                               (const double2 *)a.st, gamma_out);
-            RL_HIP(hipGetLastError());
-        }
-    } else if (a.nc > 0) {
-        RL_HIP(launch_rod<kModeInit>(st, a, uni, 0));
-        RL_HIP(launch_con<kModeInit>(st, a, 0));
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeInit>), dim3(1), dim3(kRodBlock), 0, st, a);
-        RL_HIP(hipGetLastError());
-        RL_HIP(launch_rod<kModeAlpha0>(st, a, uni, 0));
-        RL_HIP(launch_con<kModeAlpha0>(st, a, 0));
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
-        RL_HIP(hipGetLastError());
-        PersistPlan plan;
-        if (h->loop_mode == RL_LOOP_PERSISTENT) {
-            int rc = persistent_plan(h, a, &plan);
-            if (rc) return rc;
-            if (!plan.ok) {
-                set_error("rl_solve_lcp: the persistent loop does not fit this problem");
-                return RL_ERR_ARG;
-            }
-        }
-        const int every = p.check_every > 0 ? p.check_every : 32;
-        if (plan.ok) {
-            float ms = 0.f;
-            int rc = solve_loop_persistent(h, a, plan, &ms);
-            if (rc) return rc;
-            h->persist_ms += ms;
-            h->persist_iters += (double)h->state_host->iter;
-            h->persist_launches += 1.0;
-        }
-        for (long long launched = 0; !plan.ok; launched += every) {
-            if (launched > p.max_iter + every) {
-                set_error("rl_solve_lcp: stop flag never raised");
-                return RL_ERR_HIP;
-            }
-            int nev = 0;
-            for (int k = 0; k < every; ++k) {
-                const long long it = launched + k;
-                const bool samp = h->prof_every > 0 && it % h->prof_every == 0 && nev < rl_ctx::kMaxEv;
-                if (samp) {
-                    RL_HIP(record_sample(h, nev, it, a, uni));
-                    ++nev;
-                } else {
-                    RL_HIP(launch_rod<kModeLoop>(st, a, uni, it));
-                    RL_HIP(launch_con<kModeLoop>(st, a, it));
-                }
-            }
-            RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
-            RL_HIP(hipStreamSynchronize(st));
-            const bool done = h->state_host->done;
-            // samples at or after the stop iteration ran kernels that exited at once
-            const long long valid = done ? h->state_host->iter : launched + every;
-            for (int v = 0; v < nev; ++v) {
-                if (h->ev_iter[v] >= valid) continue;
-                float t0 = 0.f, t1 = 0.f;
-                if (a.n > 0) RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
-                RL_HIP(hipEventElapsedTime(&t1, h->ev[v][2], h->ev[v][3]));
-                h->prof_ms[0] += t0;
-                h->prof_ms[1] += t1;
-                h->prof_cnt[0] += 1.0;
-                h->prof_cnt[1] += 1.0;
-            }
-            if (done) break;
         }
         iters = h->state_host->iter;
         if (gamma_out) {
@@ -888,12 +810,12 @@ __global__ void k_restore_start(int64_t nc, const double *__restrict__ gamma_in,
     stq[qpos[c]] = v;
 }
 
-int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat)
+int integrate_impl(rl_ctx *h, int64_t n, const double *U, double *x, double *quat, double *xu)
 {
     if (n <= 0) return RL_OK;
     const rl_params &p = h->prm;
-    hipLaunchKernelGGL(k_integrate, dim3(grid_of(n)), dim3(kBlock), 0, h->stream, n, U, x, quat, p.dt, p.box[0],
-                       p.box[1], p.box[2]);
+    hipLaunchKernelGGL(k_integrate, dim3(grid_of(n)), dim3(kBlock), 0, h->stream, n, U, x, quat, xu, p.dt,
+                       p.box[0], p.box[1], p.box[2]);
     RL_HIP(hipGetLastError());
     return RL_OK;
 }

@@ -12,7 +12,8 @@
     of those solves at its own solution, so they stop at once.  The results
     are bitwise those of cold solves: every sum runs in a fixed order, and
     the recomputed states equal the forward ones.
-The output is the unwrapped centres x0 + h sum_t U_t (plus theta_T).
+The output is the unwrapped centres x0 + h sum_t U_t (plus theta_T), which
+``rl_step`` advances beside the wrapped ones.
 Wrapping into the periodic box shifts by whole box lengths and does not
 change the derivative.  Marshalling only: every step runs in the HIP
 kernels.
@@ -29,7 +30,6 @@ class Rollout(torch.autograd.Function):
     def forward(ctx, x0, quat0, F, solver, length, checkpoint_every, cg_tol, tape):
         T, n = F.shape[0], x0.shape[0]
         k = max(1, int(checkpoint_every))
-        dt = solver.params.dt
         x = x0.detach().clone()
         quat = quat0.detach().clone()
         xu = x0.detach().clone()
@@ -40,16 +40,15 @@ class Rollout(torch.autograd.Function):
             if t % k == 0:
                 ckpt.append((x.clone(), quat.clone()))
             if tape:
-                _, info, g = solver.step_recording(x, quat, length, F[t], U=U, capacity=cap)
+                _, info, g = solver.step_recording(x, quat, length, F[t], U=U, capacity=cap, x_unwrapped=xu)
                 tapes.append(g)
                 npairs = g.shape[0]
                 cap = npairs + npairs // 4 + 1024
             else:
-                _, info, npairs = solver.step(x, quat, length, F[t], U=U)
+                _, info, npairs = solver.step(x, quat, length, F[t], U=U, x_unwrapped=xu)
             if info.status in (NOT_CONVERGED, STAGNATED):
                 raise RodLCPError(info.status, "Rollout.forward", f"step {t} did not converge")
             infos.append((info.iterations, npairs))
-            xu.add_(U[:, :3], alpha=dt)
         ctx.solver, ctx.length, ctx.k, ctx.cg_tol = solver, length, k, cg_tol
         ctx.ckpt, ctx.tapes, ctx.infos = ckpt, tapes, infos
         ctx.save_for_backward(F)
