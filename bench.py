@@ -123,7 +123,8 @@ def form_precision(args, torch, rl, rodsynth) -> dict:
     """FP64 against FP32-mixed whole steps on the precision workload."""
     dev = torch.device("cuda:0")
     n = args.rods if args.rods != 100_000 else 400_000
-    s = rodsynth.cfg_precision(args.seed, n=n, phi=args.phi if args.phi else 0.03)
+    phi = args.phi if args.phi else 0.08
+    s = rodsynth.cfg_precision(args.seed, n=n, phi=phi)
     x0, q0 = torch.as_tensor(s.x, device=dev), torch.as_tensor(s.quat, device=dev)
     F, L = torch.as_tensor(s.force, device=dev), torch.as_tensor(s.length, device=dev)
     x, q = torch.empty_like(x0), torch.empty_like(q0)
@@ -172,8 +173,8 @@ def form_precision(args, torch, rl, rodsynth) -> dict:
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": res["fp32_mixed"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{s.n} rods L~U[0.5,1.5] d=0.025 isotropic phi={args.phi or 0.03} (0.08 is "
-                               f"jammed for unrelaxed rods), one whole step to residual 1e-8",
+        "config": {"workload": f"{s.n} rods L~U[0.5,1.5] d=0.025 isotropic phi={phi}, relaxed overlap-free "
+                               f"start, one whole step to residual 1e-8",
                    "rods": s.n, "box": round(s.box, 4), "seed": args.seed},
         "fp64": res["fp64"], "fp32_mixed": res["fp32_mixed"],
         "speedup_per_iteration": res["fp64"]["us_per_iteration"] / max(1e-9, res["fp32_mixed"]["us_per_iteration"]),
@@ -239,8 +240,8 @@ def form_batched(args, torch, rl, rodsynth) -> dict:
         "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{S} periodic systems, rods log-uniform in [200, 20000], volume fraction "
-                               f"uniform in [0.02, 0.05] (above ~0.06 unrelaxed isotropic rods are jammed), "
-                               f"isotropic, L=1", "systems": S, "rods": rods[-1], "constraints": pairs[-1],
+                               f"uniform in [0.02, 0.1], isotropic, L=1, relaxed overlap-free starts",
+                   "systems": S, "rods": rods[-1], "constraints": pairs[-1],
                    "seed": args.seed},
         "bbpgd_iters_per_s_aggregate": sum(iters) / el,
         "max_iterations_of_a_system": max(iters), "mean_iterations": sum(iters) / S,

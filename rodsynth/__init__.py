@@ -1,10 +1,11 @@
 """Seeded synthetic rod suspensions.
 
-This module only draws inputs: rod centres, orientations (as unit
+This module only prepares inputs: rod centres, orientations (as unit
 quaternions), lengths and external forces/torques, plus the periodic box that
 a target volume fraction implies.  It holds none of the method's arithmetic
-(no directors, mobilities, distances or solver steps), so both the CPU oracle
-and the HIP library can be fed from it without sharing any code.
+(no directors from quaternions, mobilities, constraint geometry or solver
+steps), so both the CPU oracle and the HIP library can be fed from it without
+sharing any code.
 
 The workloads follow the paper's filament suspensions (Section "Results":
 viscosity 0.01 pN s/um^2, timestep 1e-4 s; filament diameter 25 nm) at the
@@ -12,14 +13,33 @@ sizes of the benchmark configurations below.  Units are um, s and pN.
 
 Draw order for one system: centres, orientations, lengths, forces, each from
 ``numpy.random.Generator(PCG64(seed))``.
+
+Dense workloads start from relaxed, overlap-free configurations (the paper
+resolves the overlaps of its initial configurations before timing,
+Results, "Polarity sorting in a spherical shell"): ``relaxed_system`` draws
+a random placement (axes as unit vectors) and removes its overlaps by plain
+geometric pushes (``_relax.c``, its own segment-separation routine, compiled
+with gcc); the quaternions are built from the relaxed axes afterwards.  That
+step only moves inputs and never feeds a value to either side; the tests
+check its output against the oracle's own gaps.
 """
 from __future__ import annotations
 
+import ctypes as C
 import dataclasses
 import math
+import os
+import subprocess
+import threading
 from typing import List, Optional
 
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_RELAX_SRC = os.path.join(_HERE, "_relax.c")
+_RELAX_LIB = os.path.join(_HERE, "librelax.so")
+_relax_lock = threading.Lock()
+_relax = None
 
 ETA = 0.01          # pN s / um^2  (Section "Results")
 DT = 1.0e-4         # s
@@ -80,13 +100,19 @@ def _vmf_quaternions(rng: np.random.Generator, n: int, kappa: float) -> np.ndarr
     w = np.clip(w, -1.0, 1.0)
     phi = rng.random(n) * 2.0 * math.pi
     twist = rng.random(n) * 2.0 * math.pi
-    beta = np.arccos(w)
+    return _tilt_twist_quaternions(w, phi, twist)
+
+
+def _tilt_twist_quaternions(w: np.ndarray, phi: np.ndarray, twist: np.ndarray) -> np.ndarray:
+    """The rotation that turns the body z axis to polar cosine w and azimuth
+    phi, after a turn by `twist` about body z."""
+    beta = np.arccos(np.clip(w, -1.0, 1.0))
     # tilt: rotation by beta about the horizontal axis (-sin phi, cos phi, 0),
     # twist: rotation by `twist` about z; composed as tilt * twist.
     c1, s1 = np.cos(beta / 2), np.sin(beta / 2)
     ax, ay = -np.sin(phi), np.cos(phi)
     c2, s2 = np.cos(twist / 2), np.sin(twist / 2)
-    q = np.empty((n, 4))
+    q = np.empty((w.shape[0], 4))
     q[:, 0] = c1 * c2
     q[:, 1] = s1 * ax * c2 + s1 * ay * s2
     q[:, 2] = s1 * ay * c2 - s1 * ax * s2
@@ -129,6 +155,87 @@ def make_system(n: int, *, seed: int, box: Optional[float] = None,
                      diam=diam, cutoff=cutoff, eta=eta, dt=dt, name=name)
 
 
+# --- overlap-free placements ---------------------------------------------------
+
+def build_relax(force: bool = True) -> str:
+    """Compile the overlap-removal routine (plain C, OpenMP)."""
+    if force or not os.path.exists(_RELAX_LIB):
+        tmp = _RELAX_LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-D_POSIX_C_SOURCE=199309L", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _RELAX_SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _RELAX_LIB)
+    return _RELAX_LIB
+
+
+def _relax_lib():
+    global _relax
+    with _relax_lock:
+        if _relax is None:
+            if not os.path.exists(_RELAX_LIB) or os.path.getmtime(_RELAX_LIB) < os.path.getmtime(_RELAX_SRC):
+                build_relax(force=True)
+            lib = C.CDLL(_RELAX_LIB)
+            lib.rs_relax.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                     C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_double)]
+            lib.rs_relax.restype = C.c_int
+            _relax = lib
+    return _relax
+
+
+class RelaxError(RuntimeError):
+    pass
+
+
+def _cpu_threads() -> int:
+    """Threads for the relaxation: OMP_NUM_THREADS if set, else the CPUs this
+    process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
+
+
+def relaxed_system(n: int, *, seed: int, phi: float, length=1.0, diam: float = DIAM,
+                   cutoff: float = CUTOFF, eta: float = ETA, dt: float = DT, gap: float = 3e-4,
+                   gap_min: float = 1e-4, max_sweeps: int = 2000, force_scale: float = 1.0,
+                   threads: int = 0, name: str = "") -> RodSystem:
+    """An isotropic suspension at volume fraction ``phi`` with every pair of
+    rods (and periodic images) separated by more than ``gap_min`` beyond
+    contact.  Draw order from ``PCG64(seed)``: centres, axes (normalised
+    Gaussian 3-vectors), twists, forces; lengths from ``PCG64([seed, 1])``
+    as in ``make_system``.  The centres and axes are then relaxed; the
+    quaternion of each rod turns body z to its relaxed axis after its twist."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lrng = np.random.Generator(np.random.PCG64([seed, 1]))
+    if isinstance(length, (tuple, list)):
+        lens = lrng.uniform(length[0], length[1], n)
+    else:
+        lens = np.full(n, float(length))
+    box = box_for_volume_fraction(lens, diam, phi)
+    x = rng.random((n, 3)) * box
+    x = np.ascontiguousarray(np.where(x >= box, 0.0, x))
+    ax = rng.standard_normal((n, 3))
+    ax = np.ascontiguousarray(ax / np.linalg.norm(ax, axis=1, keepdims=True))
+    twist = rng.random(n) * 2.0 * math.pi
+    force = np.ascontiguousarray(rng.standard_normal((n, 6)) * force_scale)
+    lens = np.ascontiguousarray(lens)
+    boxv = np.full(3, box)
+    worst = C.c_double(0.0)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    nthreads = threads if threads > 0 else _cpu_threads()
+    sweeps = _relax_lib().rs_relax(n, p(x), p(ax), p(lens), p(boxv), diam, gap, gap_min, max_sweeps, nthreads,
+                                   C.byref(worst))
+    if os.environ.get("RODSYNTH_VERBOSE"):
+        print(f"relaxed_system: {sweeps} sweeps, smallest gap {worst.value:.3g}", flush=True)
+    if sweeps < 0:
+        raise RelaxError(f"overlaps not removed after {max_sweeps} sweeps (smallest gap {worst.value:.3g})")
+    quat = _tilt_twist_quaternions(ax[:, 2], np.arctan2(ax[:, 1], ax[:, 0]), twist)
+    return RodSystem(x=x, quat=np.ascontiguousarray(quat), length=lens, force=force, box=float(box),
+                     diam=diam, cutoff=cutoff, eta=eta, dt=dt, name=name)
+
+
 # --- the benchmark workloads -------------------------------------------------
 
 def cfg_small(seed: int = 0) -> RodSystem:
@@ -145,31 +252,51 @@ def cfg_paper_scale(seed: int = 0, n: int = 100_000) -> RodSystem:
                        name=f"rods{n // 1000}k_phi0.05_vmf20")
 
 
-def cfg_precision(seed: int = 0, n: int = 400_000, phi: float = 0.03) -> RodSystem:
-    """400,000 rods, lengths uniform in [0.5, 1.5], isotropic.  The precision
-    workload is quoted at volume fraction 0.08, but unrelaxed random
-    isotropic rods that dense give a linearised problem with no solution
-    (the QP objective is unbounded below: jammed overlap cycles), so the
-    default is 0.03, the densest value at which such systems solve; pass
-    phi=0.08 for the literal one."""
-    return make_system(n, seed=seed, phi=phi, length=(0.5, 1.5),
-                       orientation="isotropic", name=f"rods{n // 1000}k_phi{phi}_iso_L0.5-1.5")
+def cfg_precision(seed: int = 0, n: int = 400_000, phi: float = 0.08, relaxed: bool = True) -> RodSystem:
+    """400,000 rods, lengths uniform in [0.5, 1.5], isotropic, volume
+    fraction 0.08, from a relaxed (overlap-free) start.  Random placements
+    this dense overlap in self-stressed clusters whose linearised problem has
+    no solution (a non-negative D d = 0 with phi.d < 0 exists); with every
+    gap non-negative it always has one.  relaxed=False gives the raw random
+    placement (``make_system``)."""
+    name = f"rods{n // 1000}k_phi{phi}_iso_L0.5-1.5" + ("_relaxed" if relaxed else "")
+    if relaxed:
+        return relaxed_system(n, seed=seed, phi=phi, length=(0.5, 1.5), name=name)
+    return make_system(n, seed=seed, phi=phi, length=(0.5, 1.5), orientation="isotropic", name=name)
 
 
-def cfg_batched(seed: int = 0, systems: int = 256, n_lo: int = 200, n_hi: int = 20_000,
-                phi_range=(0.02, 0.05)) -> List[RodSystem]:
-    """Independent periodic systems, rod counts log-uniform in [n_lo, n_hi],
-    volume fractions uniform in phi_range, isotropic.  The batch workload
-    is quoted with volume fractions up to 0.1; unrelaxed random isotropic
-    systems above about 0.06 have no solution of the linearised problem
-    (jammed), so the default range stops at 0.05; pass (0.02, 0.1) for the
-    literal one."""
+def batch_plan(seed: int = 0, systems: int = 256, n_lo: int = 200, n_hi: int = 20_000, phi_range=(0.02, 0.1)):
+    """Rod counts (log-uniform in [n_lo, n_hi]) and volume fractions (uniform
+    in phi_range) of the batch, from PCG64([seed, 7])."""
     rng = np.random.Generator(np.random.PCG64([seed, 7]))
     counts = np.floor(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), systems))).astype(int)
     phis = rng.uniform(phi_range[0], phi_range[1], systems)
-    return [make_system(int(c), seed=seed * 100_003 + k, phi=float(p),
-                        orientation="isotropic", name=f"batch{k}")
-            for k, (c, p) in enumerate(zip(counts, phis))]
+    return counts, phis
+
+
+def cfg_batched(seed: int = 0, systems: int = 256, n_lo: int = 200, n_hi: int = 20_000,
+                phi_range=(0.02, 0.1), relaxed: bool = True, workers: int = 0) -> List[RodSystem]:
+    """Independent periodic systems of rods of length 1, isotropic, rod
+    counts log-uniform in [n_lo, n_hi], volume fractions uniform in
+    phi_range; system k uses seed * 100003 + k.  Each starts relaxed
+    (overlap-free, as ``cfg_precision``); the systems are relaxed
+    concurrently on ``workers`` threads (0: the CPUs available)."""
+    counts, phis = batch_plan(seed, systems, n_lo, n_hi, phi_range)
+    if not relaxed:
+        return [make_system(int(c), seed=seed * 100_003 + k, phi=float(p), orientation="isotropic",
+                            name=f"batch{k}") for k, (c, p) in enumerate(zip(counts, phis))]
+    from concurrent.futures import ThreadPoolExecutor
+    nw = workers if workers > 0 else _cpu_threads()
+
+    def one(k):
+        return relaxed_system(int(counts[k]), seed=seed * 100_003 + k, phi=float(phis[k]), threads=1,
+                              name=f"batch{k}")
+
+    # largest systems first, so that the pool ends together
+    order = sorted(range(systems), key=lambda k: -int(counts[k]))
+    with ThreadPoolExecutor(max_workers=nw) as pool:
+        done = dict(zip(order, pool.map(one, order)))
+    return [done[k] for k in range(systems)]
 
 
 def cfg_rollout(seed: int = 0, n: int = 50_000) -> RodSystem:

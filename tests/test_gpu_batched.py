@@ -17,15 +17,16 @@ def _t(a, dtype=torch.float64):
 
 
 def _batch(systems):
-    """Oracle solutions per system and the concatenated inputs."""
+    """Oracle inputs per system and the concatenated inputs (per-rod lengths)."""
     per, rods, pairs = [], [0], [0]
-    cat = {k: [] for k in ("dir", "pi", "pj", "e", "arm", "q", "F")}
+    cat = {k: [] for k in ("dir", "len", "pi", "pj", "e", "arm", "q", "F")}
     for s in systems:
         d = oracle.directors(s.quat)
-        pr = oracle.pairs(s.x, d, 1.0, s.box, s.diam, s.cutoff)
-        cs = oracle.assemble(s.x, d, 1.0, s.box, s.diam, s.eta, s.dt, pr, s.force)
+        pr = oracle.pairs(s.x, d, s.length, s.box, s.diam, s.cutoff)
+        cs = oracle.assemble(s.x, d, s.length, s.box, s.diam, s.eta, s.dt, pr, s.force)
         per.append((s, d, pr, cs))
         cat["dir"].append(d)
+        cat["len"].append(s.length)
         cat["pi"].append(pr.pi + rods[-1])
         cat["pj"].append(pr.pj + rods[-1])
         cat["e"].append(cs.e)
@@ -39,10 +40,12 @@ def _batch(systems):
 
 
 def _run(rl, systems, arrays, rods, pairs, rb=0, cb=0, max_iter=100_000):
+    lens = arrays["len"]
+    length = float(lens[0]) if lens.size and np.all(lens == lens[0]) else _t(lens)
     with rl.Solver(box=1.0, tol=1e-8, max_iter=max_iter) as slv:
         slv.batch_tuning(rb, cb)
         g, U, infos = slv.solve_lcp_batched(
-            rods, pairs, _t(arrays["dir"]), 1.0, _t(arrays["pi"], torch.int32), _t(arrays["pj"], torch.int32),
+            rods, pairs, _t(arrays["dir"]), length, _t(arrays["pi"], torch.int32), _t(arrays["pj"], torch.int32),
             _t(arrays["e"]), _t(arrays["arm"]), _t(arrays["q"]), F=_t(arrays["F"]))
         used = slv.batch_tuning(rb, cb)
     return g.cpu().numpy(), U.cpu().numpy(), infos, used
@@ -50,6 +53,7 @@ def _run(rl, systems, arrays, rods, pairs, rb=0, cb=0, max_iter=100_000):
 
 @pytest.fixture(scope="module")
 def batch():
+    # relaxed starts, volume fractions in [0.02, 0.1] as in the full batch
     systems = rodsynth.cfg_batched(3, systems=10, n_lo=100, n_hi=1500)
     systems.append(rodsynth.make_system(150, seed=9, box=40.0))            # no contacts at all
     systems.append(rodsynth.make_system(120, seed=2, phi=0.03))
@@ -65,10 +69,10 @@ def test_batched_matches_oracle_per_system(gpu_lib, batch):
         assert info.status == gpu_lib.OK and info.residual <= 1e-8, (k, info)
         gk = g[pairs[k]:pairs[k + 1]]
         Uk = U[rods[k]:rods[k + 1]]
-        w = oracle.apply_Mc(d, 1.0, s.diam, s.eta, pr, cs, gk)
+        w = oracle.apply_Mc(d, s.length, s.diam, s.eta, pr, cs, gk)
         assert np.abs(np.minimum(gk, w)).max(initial=0.0) <= 1e-8 + 1e-12 * np.abs(cs.q).max(initial=1.0)
-        ref = oracle.bbpgd(d, 1.0, s.diam, s.eta, pr, cs, tol=1e-8)
-        Uref = oracle.velocity(d, 1.0, s.diam, s.eta, pr, cs, ref.gamma, s.force)
+        ref = oracle.bbpgd(d, s.length, s.diam, s.eta, pr, cs, tol=1e-8)
+        Uref = oracle.velocity(d, s.length, s.diam, s.eta, pr, cs, ref.gamma, s.force)
         assert np.linalg.norm(Uk - Uref) <= 1e-6 * np.linalg.norm(Uref), k
     assert infos[10].iterations == 0 and pairs[11] == pairs[10]
 
@@ -84,20 +88,43 @@ def test_batched_every_workgroup_size(gpu_lib, batch, rb, cb):
 
 
 def test_batched_infeasible_system_does_not_disturb_others(gpu_lib):
-    systems = [rodsynth.make_system(400, seed=5, phi=0.03),
-               rodsynth.make_system(900, seed=4, phi=0.08, length=1.0),
-               rodsynth.make_system(300, seed=6, phi=0.04)]
+    """The middle system is the unrelaxed 300-rod system at volume fraction
+    0.08 for which the CPU tests hold an infeasibility certificate (a
+    non-negative z with D z = 0 and phi.z < 0): no solver can reach the
+    tolerance on it.  It must be reported, and its neighbours must still
+    match the oracle."""
+    systems = [rodsynth.relaxed_system(400, seed=5, phi=0.05),
+               rodsynth.make_system(300, seed=0, phi=0.08, length=(0.5, 1.5), orientation="isotropic"),
+               rodsynth.relaxed_system(300, seed=6, phi=0.04)]
     per, rods, pairs, arrays = _batch(systems)
-    ref_bad = oracle.bbpgd(per[1][1], 1.0, 0.025, 0.01, per[1][2], per[1][3], tol=1e-8, max_iter=2000)
     g, U, infos, _ = _run(gpu_lib, systems, arrays, rods, pairs, max_iter=2000)
     assert infos[0].status == gpu_lib.OK and infos[2].status == gpu_lib.OK
-    if ref_bad.status == oracle.NOT_CONVERGED:
-        assert infos[1].status == gpu_lib.NOT_CONVERGED and infos[1].iterations == 2000
+    assert infos[1].status in (gpu_lib.NOT_CONVERGED, gpu_lib.STAGNATED) and infos[1].residual > 1e-8
+    if infos[1].status == gpu_lib.NOT_CONVERGED:
+        assert infos[1].iterations == 2000
     for k in (0, 2):
         s, d, pr, cs = per[k]
-        ref = oracle.bbpgd(d, 1.0, s.diam, s.eta, pr, cs, tol=1e-8)
-        Uref = oracle.velocity(d, 1.0, s.diam, s.eta, pr, cs, ref.gamma, s.force)
+        ref = oracle.bbpgd(d, s.length, s.diam, s.eta, pr, cs, tol=1e-8)
+        Uref = oracle.velocity(d, s.length, s.diam, s.eta, pr, cs, ref.gamma, s.force)
         assert np.linalg.norm(U[rods[k]:rods[k + 1]] - Uref) <= 1e-6 * np.linalg.norm(Uref)
+
+
+def test_batched_system_is_bitwise_the_same_alone(gpu_lib, batch):
+    """A system's tiles, partial sums and step lengths depend on that system
+    alone (with the workgroup sizes fixed), so its answer in the batch is
+    bitwise the answer of a batch holding only it.  (Against rl_solve_lcp it
+    agrees to the certificate, not bitwise: the single solve splits the
+    step-length sums into other workgroup partials, and BB steps amplify the
+    last-bit differences into other iterate paths.)"""
+    systems, (per, rods, pairs, arrays) = batch
+    g, U, infos, _ = _run(gpu_lib, systems, arrays, rods, pairs, 256, 256)
+    for k in (1, 4, 7):
+        s1 = [systems[k]]
+        p1, r1, q1, a1 = _batch(s1)
+        g1, U1, i1, _ = _run(gpu_lib, s1, a1, r1, q1, 256, 256)
+        assert np.array_equal(g1, g[pairs[k]:pairs[k + 1]]), k
+        assert np.array_equal(U1, U[rods[k]:rods[k + 1]]), k
+        assert i1[0].iterations == infos[k].iterations
 
 
 def test_batched_rejects_cross_system_pairs(gpu_lib, batch):
