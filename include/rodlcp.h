@@ -168,6 +168,25 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
                  const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
                  const double *F, double *gamma, double *U, rl_solve_info *info);
 
+/* rl_solve_lcp without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): the same problem, kernels and result as rl_solve_lcp
+ * (bitwise), with every workspace piece taken from a scratch array of
+ * RL_NOALLOC_SCRATCH_BYTES that the library keeps on each device for the
+ * life of the process.  The call makes no hipMalloc, hipFree or other
+ * allocating call; the handle (rl_create) must already exist.  RL_FP64 only;
+ * kernel-event sampling (rl_profile_enable) is ignored.
+ * Workspace: 152 bytes per constraint and 12 bytes per rod (36 with per-rod
+ * lengths) plus a few KB (e.g. 100,000 rods with 468,687 constraints take
+ * 73 MB); a larger problem returns RL_ERR_ARG with nothing enqueued.
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on the same GPU (other threads, other handles, other streams) race and must
+ * be serialised by the caller.  Synchronises, like rl_solve_lcp. */
+#define RL_NOALLOC_SCRATCH_BYTES (96ull << 20)
+int rl_solve_lcp_noalloc(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                         const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                         const double *F, double *gamma, double *U, rl_solve_info *info);
+
 /* One whole timestep: directors, pairs, geometry, solve, then the
  * linearised Euler update x += h U_t (wrapped into the box) and
  * theta += h Psi(theta) Omega, renormalised (eq. constrainedeom_euler,

@@ -58,7 +58,7 @@ class AdjointInfo(C.Structure):
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
-           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint")
+           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_solve_lcp_noalloc")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -87,6 +87,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_assemble_D": ([H, I64, P, P, P, D, I64, P, P, P, P, P, P, P, P], C.c_int),
             "rl_apply_M": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P], C.c_int),
             "rl_solve_lcp": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)], C.c_int),
+            "rl_solve_lcp_noalloc": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)],
+                                     C.c_int),
             "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64), P, I64, I32,
                          C.POINTER(StepExtra)], C.c_int),
             "rl_profile_enable": ([H, C.c_int], C.c_int),
@@ -308,6 +310,23 @@ class Solver:
             _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
             _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
         self._check(rc, "rl_solve_lcp")
+        return gamma, U, _result(info)
+
+    def solve_lcp_noalloc(self, dir_, length, pi, pj, e, arm, q, gamma, U, F=None):
+        """solve_lcp without device allocation (workspace in the library's
+        scratch array): gamma (start, updated in place) and U must be given."""
+        torch = _torch()
+        n, nc = dir_.shape[0], pi.shape[0]
+        la, l0 = _len_args(length, n)
+        info = SolveInfo()
+        self._stream()
+        rc = self.lib.rl_solve_lcp_noalloc(
+            self._h, n, _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, nc, _ptr(pi, torch.int32, (nc,), "pi"),
+            _ptr(pj, torch.int32, (nc,), "pj"), _ptr(e, torch.float64, (nc, 3), "e"),
+            _ptr(arm, torch.float64, (nc, 2), "arm"), _ptr(q, torch.float64, (nc,), "q"),
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
+            _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
+        self._check(rc, "rl_solve_lcp_noalloc")
         return gamma, U, _result(info)
 
     def solve_lcp_batched(self, rod_off, pair_off, dir_, length, pi, pj, e, arm, q, F=None, gamma=None, U=None):

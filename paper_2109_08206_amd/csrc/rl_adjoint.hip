@@ -611,6 +611,7 @@ int adjoint_core(rl_ctx *h, SolveArgs &a, bool step, const double *Ubar, const d
     g.cq = (double *)ws_get(h, kWsAdjCq, sizeof(double) * 4 * nb, &err);
     g.sc = (double *)ws_get(h, kWsAdjSc, sizeof(double) * 8, &err);
     double *PQ = (double *)ws_get(h, kWsAdjPQ, sizeof(double) * 12 * rb, &err);
+    a.V = (double *)ws_get(h, kWsV, sizeof(double) * 6 * rb, &err);
     if (err) return err;
     g.ab = g.sc + 4;
     if (!(cg_tol > 0.0)) cg_tol = 1e-10;

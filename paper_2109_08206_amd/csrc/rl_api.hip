@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "rl_internal.hpp"
@@ -10,6 +11,38 @@
 namespace rl {
 
 static thread_local char g_last_error[512] = "";
+
+// The scratch array of the allocation-free entry point (rl_solve_lcp_noalloc).
+// Every device the library runs on holds one copy of it, at its own address,
+// for the life of the process.  In host code `scratch` names a host-side
+// stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, taken once per device (scratch_of) with that device
+// current, and is the only one host code passes on.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};
+
+// the device address of the current device's scratch array (dev is current)
+static int scratch_of(int dev, char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the scratch table", dev);
+        return RL_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+            return RL_ERR_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = (char *)g_scratch_dev[dev];
+    return RL_OK;
+}
 
 void set_error(const char *fmt, ...)
 {
@@ -27,6 +60,18 @@ void *ws_get(rl_ctx *h, int s, size_t bytes, int *err)
         return nullptr;
     }
     if (bytes == 0) bytes = 8;
+    if (h->arena_on) {
+        // allocation-free call: the next 256-byte aligned piece of the scratch array
+        const size_t off = (h->arena_used + 255) & ~(size_t)255;
+        if (off > kScratchBytes || bytes > kScratchBytes - off) {
+            set_error("the problem needs more than the %zu bytes of the allocation-free scratch array",
+                      kScratchBytes);
+            *err = RL_ERR_ARG;
+            return nullptr;
+        }
+        h->arena_used = off + bytes;
+        return h->scratch + off;
+    }
     if (h->cap[s] >= bytes) return h->buf[s];
     if (h->buf[s]) {
         (void)hipStreamSynchronize(h->stream);
@@ -158,10 +203,18 @@ int rl_create(rl_handle *out, const rl_params *prm)
     if (hipMalloc(&h->state, sizeof(SolverState)) != hipSuccess ||
         hipMalloc(&h->flag_dev, sizeof(int) * 4) != hipSuccess ||
         hipHostMalloc(&h->state_host, sizeof(SolverState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(&h->host_scratch, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&h->host_scratch, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming) != hipSuccess) {
         set_error("rl_create: allocation failed");
         rl_destroy(h);
         return RL_ERR_NOMEM;
+    }
+    rc = scratch_of(h->device, &h->scratch);
+    if (rc) {
+        const std::string msg = rl_last_error();
+        rl_destroy(h);
+        set_error("%s", msg.c_str());
+        return rc;
     }
     memset(h->state_host, 0, sizeof(SolverState));
     *out = h;
@@ -301,6 +354,31 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
     RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && q && gamma), "rl_solve_lcp: NULL array");
     RL_REQUIRE(n == 0 || dir || !U, "rl_solve_lcp: NULL dir");
     RL_REQUIRE(len || len0 > 0.0, "rl_solve_lcp: len0 must be > 0 when len is NULL");
+    SolveArgs a;
+    int rc = prepare_solve(h, n, dir, len, len0, nc, pi, pj, e, arm, q, gamma, &a);
+    if (rc) return rc;
+    return solve_impl(h, a, F, U, gamma, info);
+}
+
+int rl_solve_lcp_noalloc(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                         const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                         const double *F, double *gamma, double *U, rl_solve_info *info)
+{
+    RL_CHECK_HANDLE(h);
+    RL_REQUIRE(n >= 0 && n < 0x7fffffff && nc >= 0 && nc < 0x7fffffff, "rl_solve_lcp_noalloc: bad sizes");
+    RL_REQUIRE(nc == 0 || (dir && pi && pj && e && arm && q && gamma), "rl_solve_lcp_noalloc: NULL array");
+    RL_REQUIRE(n == 0 || dir || !U, "rl_solve_lcp_noalloc: NULL dir");
+    RL_REQUIRE(len || len0 > 0.0, "rl_solve_lcp_noalloc: len0 must be > 0 when len is NULL");
+    RL_REQUIRE(h->prm.precision == RL_FP64, "rl_solve_lcp_noalloc: RL_FP64 only");
+    RL_REQUIRE(h->scratch != nullptr, "rl_solve_lcp_noalloc: no scratch array on this device");
+    // every workspace piece comes from the scratch array (prepare_solve takes
+    // them all before it launches anything, so an oversized problem fails
+    // with nothing enqueued)
+    struct Arena {
+        rl_ctx *h;
+        explicit Arena(rl_ctx *c) : h(c) { h->arena_on = true; h->arena_used = 0; }
+        ~Arena() { h->arena_on = false; }
+    } arena(h);
     SolveArgs a;
     int rc = prepare_solve(h, n, dir, len, len0, nc, pi, pj, e, arm, q, gamma, &a);
     if (rc) return rc;

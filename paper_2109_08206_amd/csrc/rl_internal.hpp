@@ -166,6 +166,11 @@ struct rl_ctx {
     int tune_rb[64] = {}, tune_cb[64] = {};    // per log2(constraints) bucket
     void *host_buf = nullptr;                  // pinned staging for tables
     size_t host_cap = 0;
+    // allocation-free calls: while arena_on, ws_get hands out consecutive
+    // pieces of the device's scratch array instead of allocating
+    char *scratch = nullptr;                   // this device's scratch array
+    size_t arena_used = 0;
+    bool arena_on = false;
 };
 
 namespace rl {
@@ -197,8 +202,12 @@ int build_pairs_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, c
 hipError_t launch_gather6(hipStream_t st, int64_t n, const int *perm, const double *src, double *dst);
 int stable_sort_by_key(rl_ctx *h, int64_t n, const int *keys, int bits, int *keys_out, int *perm);
 // out[0..m] = exclusive prefix sums of in[0..m-1] (out[m] = the total, also
-// written to *total when given), on the handle's stream
-int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total);
+// written to *total when given), on the handle's stream.  tmp (may be null:
+// taken from the workspace) holds scan_tmp_bytes(m) bytes.
+int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total, void *tmp = nullptr);
+int scan_tmp_bytes(int64_t m, size_t *bytes);
+// bytes of the allocation-free scratch array on each device
+constexpr size_t kScratchBytes = (size_t)RL_NOALLOC_SCRATCH_BYTES;
 // sorts m pair keys ((pi << (ibits + 12)) | (pj << 12) | shift, `bits` wide)
 // with their flags and writes the canonical pi, pj, img, flags lists
 int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *keys, const uint8_t *kflags, int ibits,

@@ -478,10 +478,15 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     s.stq = (double2 *)ws_get(h, kWsStq, sizeof(double2) * nb, &werr);
     int32_t *qpos = (int32_t *)ws_get(h, kWsQpos, sizeof(int32_t) * nb, &werr);
     double *qgeo = (double *)ws_get(h, kWsQgeo, sizeof(double) * 4 * nb, &werr);
-    s.V = (double *)ws_get(h, kWsV, sizeof(double) * 6 * rb, &werr);
     s.partial = (double *)ws_get(h, kWsPartial, sizeof(double) * 8 * s.gcon, &werr);
     s.alpha_buf = (double *)ws_get(h, kWsAlpha, sizeof(double) * 2, &werr);
     double *coef = len ? (double *)ws_get(h, kWsCoef, sizeof(double) * 3 * rb, &werr) : nullptr;
+    size_t scan_bytes = 0;
+    {
+        const int rc = scan_tmp_bytes(n, &scan_bytes);
+        if (rc) return rc;
+    }
+    void *scan_tmp = n > 0 ? ws_get(h, kWsScanTmp, scan_bytes, &werr) : nullptr;
     if (werr) return werr;
     s.coef = coef;
     s.pptr = pptr;
@@ -514,7 +519,7 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
             hipLaunchKernelGGL(k_qcount, dim3(grid_of(nc)), dim3(kBlock), 0, st, nc, pj, qcnt);
             RL_HIP(hipGetLastError());
         }
-        const int rc = device_scan(h, qcnt, n, qptr, nullptr);
+        const int rc = device_scan(h, qcnt, n, qptr, nullptr, scan_tmp);
         if (rc) return rc;
         if (nc > 0) {
             RL_HIP(hipMemsetAsync(qcnt, 0, sizeof(int) * n, st));
@@ -659,18 +664,21 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         // not wait for the host; iterations queued past the stop exit at once.
         const int la = std::min(every, 8);
         long long launched = 0;
-        std::vector<int> pend;  // event slots of sampled iterations not yet read
+        // event slots of sampled iterations not yet read (no sampling in an
+        // allocation-free call: its events would be created on first use)
+        int pend[rl_ctx::kMaxEv], npend = 0;
         bool used[rl_ctx::kMaxEv] = {};
+        const int prof_every = h->arena_on ? 0 : h->prof_every;
         auto enqueue = [&](long long count) -> int {
             for (long long k = 0; k < count; ++k, ++launched) {
                 int slot = -1;
-                if (h->prof_every > 0 && launched % h->prof_every == 0)
+                if (prof_every > 0 && launched % prof_every == 0)
                     for (int v = 0; v < rl_ctx::kMaxEv && slot < 0; ++v)
                         if (!used[v]) slot = v;
                 if (slot >= 0) {
                     RL_HIP(record_sample(h, slot, launched, a, uni));
                     used[slot] = true;
-                    pend.push_back(slot);
+                    pend[npend++] = slot;
                 } else {
                     RL_HIP(launch_rod<kModeLoop>(st, a, uni, launched));
                     RL_HIP(launch_con<kModeLoop>(st, a, launched));
@@ -679,7 +687,6 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
             return RL_OK;
         };
         {
-            if (!h->chk_ev) RL_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
             int rc = enqueue(every);
             if (rc) return rc;
             for (;;) {
@@ -692,10 +699,11 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
                 // samples before the check have run; those at or after the stop
                 // iteration ran kernels that exited at once
                 const long long valid = done ? h->state_host->iter : checked;
-                std::vector<int> keep;
-                for (int v : pend) {
+                int nkeep = 0;
+                for (int u = 0; u < npend; ++u) {
+                    const int v = pend[u];
                     if (h->ev_iter[v] >= checked) {
-                        keep.push_back(v);
+                        pend[nkeep++] = v;
                         continue;
                     }
                     if (h->ev_iter[v] < valid) {
@@ -709,7 +717,7 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
                     }
                     used[v] = false;
                 }
-                pend.swap(keep);
+                npend = nkeep;
                 if (done) break;
                 if (checked > p.max_iter + every) {
                     set_error("rl_solve_lcp: stop flag never raised");

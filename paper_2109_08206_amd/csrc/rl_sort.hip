@@ -36,14 +36,23 @@ __global__ void k_scan_ends(int64_t m, int *__restrict__ out, int64_t *__restric
     if (total) *total = out[m];
 }
 
-int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total)
+int scan_tmp_bytes(int64_t m, size_t *bytes)
+{
+    *bytes = 0;
+    if (m <= 0) return RL_OK;
+    RL_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, *bytes, (const int *)nullptr, (int *)nullptr, (int)m,
+                                            (hipStream_t)0));
+    return RL_OK;
+}
+
+int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total, void *tmp)
 {
     hipStream_t st = h->stream;
     if (m > 0) {
         int werr = 0;
         size_t tmp_bytes = 0;
         RL_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, in, out + 1, (int)m, st));
-        void *tmp = ws_get(h, kWsScanTmp, tmp_bytes, &werr);
+        if (!tmp) tmp = ws_get(h, kWsScanTmp, tmp_bytes, &werr);
         if (werr) return werr;
         RL_HIP(hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, in, out + 1, (int)m, st));
     }
