@@ -168,6 +168,61 @@ int rl_solve_lcp(rl_handle h, int64_t n, const double *dir, const double *len, d
                  const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
                  const double *F, double *gamma, double *U, rl_solve_info *info);
 
+/* ---------------------------------------------------------------------------
+ * Bilateral constraints and general constraint sets
+ * ---------------------------------------------------------------------------
+ * Hookean links (crosslinkers, joints) are bilateral constraints: the
+ * spring law K (Phi_b - Phi_b^0) = -gamma_b (eq. bilateralconstraint),
+ * linearised over the step, adds the rows of eq. linearconstraints (b) to the
+ * problem: the quadratic program of eq. suppcqpdef with gamma_u >= 0 and
+ * gamma_b free, its matrix D^T M D plus K^-1/h on the bilateral diagonal
+ * (eq. blockdef, blocks C-F).  The same BBPGD solves it; bilateral entries
+ * are not projected and their residual is |w_b|.
+ *
+ * A link joins the point at arclength arm[k][0] on rod p[k]'s axis to the
+ * point at arm[k][1] on rod q[k]'s axis (points fixed on the bodies), or,
+ * with q[k] < 0, to the fixed point anchor[k] (a tether to the lab frame:
+ * only rod p's side enters D, Appendix "Equation of motion with geometric
+ * constraints", last paragraph).  Its vector r = (x_p + s_p d_p) - (x_q +
+ * s_q d_q) takes each component of the difference to its nearest periodic
+ * image; length |r|, e = r / |r| (from q to p; gamma > 0 pushes apart,
+ * gamma < 0 pulls).  kappa > 0 (pN/um; INFINITY: a rigid joint), rest >= 0
+ * (um). */
+typedef struct {
+    int64_t n_links;
+    const int32_t *p, *q;   /* [n_links] rod indices (device); q < 0: fixed point */
+    const double *arm;      /* [n_links][2] arclengths on the two axes (device) */
+    const double *kappa;    /* [n_links] stiffness (device) */
+    const double *rest;     /* [n_links] rest length (device) */
+    const double *anchor;   /* [n_links][3] fixed points (device; may be NULL if no q < 0) */
+} rl_links;
+
+/* Link geometry and rows: writes length[n_links], e[n_links][3], q[n_links]
+ * = (length - rest)/h + D^T M F (F may be NULL), cmp[n_links] = 1/(kappa h)
+ * and flags[n_links] (may be NULL; bit 2: zero length, e normal to both
+ * axes).  RL_ERR_ARG on an index outside the rods, p == q, kappa <= 0, a
+ * bad rest length or a missing anchor.  Synchronises. */
+int rl_assemble_links(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                      const rl_links *links, const double *F, double *length, double *e, double *q, double *cmp,
+                      uint8_t *flags);
+
+/* The mixed problem over a general constraint list of nc entries in any
+ * order: kind[c] = 0 for a unilateral constraint (contact, wall), 1 for a
+ * bilateral one with compliance cmp[c] >= 0 (cmp may be NULL when no entry
+ * is bilateral); pi[c] in [0, n) is the rod on the P side, pj[c] the rod on
+ * the Q side or -1 for a fixed body (a wall or an anchor; pj may equal pi
+ * for a periodic self-contact); e, arm and q as for rl_solve_lcp.  gamma
+ * (start on entry: unilateral entries clipped to >= 0; solution on exit) and
+ * U = M (D gamma + F) as in rl_solve_lcp; info->residual is the largest of
+ * |min(gamma_u, w_u)| and |w_b|.  RL_FP64 only.  The constraints are reordered
+ * internally (by P rod, unilateral first); every result is returned in the
+ * caller's order.  RL_ERR_ARG on a bad index, kind or compliance.
+ * Synchronises. */
+int rl_solve_general(rl_handle h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                     const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                     const uint8_t *kind, const double *cmp, const double *F, double *gamma, double *U,
+                     rl_solve_info *info);
+
 /* rl_solve_lcp without allocation, for callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, harnesses that
  * forbid allocation): the same problem, kernels and result as rl_solve_lcp

@@ -69,6 +69,10 @@ def _load():
             lib.ora_bbpgd.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, D, I64, P, P, P]
             lib.ora_bbpgd.restype = C.c_int
             lib.ora_integrate.argtypes = [I64, P, D, P, P, P, P]
+            lib.ora_bbpgd_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, D, I64, P, P, P]
+            lib.ora_bbpgd_gen.restype = C.c_int
+            lib.ora_apply_Mc_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, P, P]
+            lib.ora_links.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P, P, P, P, P]
             _lib = lib
     return _lib
 
@@ -308,3 +312,111 @@ def step_solve(sys, tol=None, max_iter=100_000, pair_method="auto") -> StepResul
     sr = bbpgd(d, L, sys.diam, sys.eta, pr, cs, tol=tol, max_iter=max_iter)
     U = velocity(d, L, sys.diam, sys.eta, pr, cs, sr.gamma, sys.force)
     return StepResult(d, pr, cs, sr, U)
+
+
+# --- bilateral links and general constraint sets ------------------------------
+
+@dataclass
+class Links:
+    """Hookean links between points on two rod axes (q < 0: to a fixed point)."""
+    p: np.ndarray        # [nl] int32
+    q: np.ndarray        # [nl] int32, -1 for a link to anchor[k]
+    arm: np.ndarray      # [nl, 2] arclengths (sP, sQ)
+    kappa: np.ndarray    # [nl] stiffness, +inf for a rigid joint
+    rest: np.ndarray     # [nl] rest length
+    anchor: Optional[np.ndarray] = None  # [nl, 3]
+
+    @property
+    def n(self) -> int:
+        return int(self.p.shape[0])
+
+
+@dataclass
+class LinkGeometry:
+    length: np.ndarray   # [nl]
+    e: np.ndarray        # [nl, 3]
+    q: np.ndarray        # [nl]
+    cmp: np.ndarray      # [nl] compliance 1/(kappa h)
+    flags: np.ndarray    # [nl] uint8
+
+
+def links_geometry(x, dir_, length, box, diam, eta, dt, lk: Links, F=None) -> LinkGeometry:
+    xa, d = _f64(x), _f64(dir_)
+    n = xa.shape[0]
+    la, l0 = _len_args(length, n)
+    nl = lk.n
+    out = LinkGeometry(np.empty(nl), np.empty((nl, 3)), np.empty(nl), np.empty(nl), np.empty(nl, np.uint8))
+    anchor = _f64(lk.anchor) if lk.anchor is not None else None
+    _load().ora_links(n, _p(xa), _p(d), _p(la), l0, _p(_box3(box)), diam, eta, dt, nl, _p(_i32(lk.p)),
+                      _p(_i32(lk.q)), _p(_f64(lk.arm)), _p(_f64(lk.kappa)), _p(_f64(lk.rest)), _p(anchor),
+                      _p(None if F is None else _f64(F)), _p(out.length), _p(out.e), _p(out.q), _p(out.cmp),
+                      _p(out.flags))
+    return out
+
+
+@dataclass
+class General:
+    """A general constraint list: contacts (kind 0) and links (kind 1); pj < 0
+    for a constraint against a fixed body."""
+    pi: np.ndarray
+    pj: np.ndarray
+    e: np.ndarray
+    arm: np.ndarray
+    q: np.ndarray
+    kind: np.ndarray     # uint8
+    cmp: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.pi.shape[0])
+
+
+def general(pr: Optional[Pairs] = None, cs: Optional[Constraints] = None, lk: Optional[Links] = None,
+            lg: Optional[LinkGeometry] = None) -> General:
+    """Contacts first, then links, each in its own order."""
+    parts = []
+    if pr is not None and pr.n:
+        parts.append((pr.pi, pr.pj, cs.e, cs.arm, cs.q, np.zeros(pr.n, np.uint8), np.zeros(pr.n)))
+    if lk is not None and lk.n:
+        parts.append((lk.p, lk.q, lg.e, lk.arm, lg.q, np.ones(lk.n, np.uint8), lg.cmp))
+    if not parts:
+        z = np.zeros(0)
+        return General(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros((0, 2)), z,
+                       np.zeros(0, np.uint8), z)
+    cols = list(zip(*parts))
+    return General(_i32(np.concatenate(cols[0])), _i32(np.concatenate(cols[1])), _f64(np.concatenate(cols[2])),
+                   _f64(np.concatenate(cols[3])), _f64(np.concatenate(cols[4])),
+                   np.ascontiguousarray(np.concatenate(cols[5]), dtype=np.uint8), _f64(np.concatenate(cols[6])))
+
+
+def apply_Mc_gen(dir_, length, diam, eta, gc: General, gamma, add_q: bool = True) -> np.ndarray:
+    d = _f64(dir_)
+    n = d.shape[0]
+    la, l0 = _len_args(length, n)
+    w = np.empty(gc.n)
+    _load().ora_apply_Mc_gen(n, _p(d), _p(la), l0, diam, eta, gc.n, _p(gc.pi), _p(gc.pj), _p(gc.e), _p(gc.arm),
+                             _p(gc.q if add_q else None), _p(gc.kind), _p(gc.cmp), _p(_f64(gamma)), _p(w))
+    return w
+
+
+def bbpgd_gen(dir_, length, diam, eta, gc: General, tol=1e-8, max_iter=100_000, gamma0=None) -> SolveResult:
+    d = _f64(dir_)
+    n = d.shape[0]
+    la, l0 = _len_args(length, n)
+    gamma = np.zeros(gc.n) if gamma0 is None else _f64(gamma0).copy()
+    g = np.empty(gc.n)
+    info = np.zeros(3)
+    st = _load().ora_bbpgd_gen(n, _p(d), _p(la), l0, diam, eta, gc.n, _p(gc.pi), _p(gc.pj), _p(gc.e), _p(gc.arm),
+                               _p(gc.q), _p(gc.kind), _p(gc.cmp), tol, int(max_iter), _p(gamma), _p(g), _p(info))
+    return SolveResult(gamma, g, int(info[0]), float(info[1]), float(info[2]), int(st))
+
+
+def velocity_gen(dir_, length, diam, eta, gc: General, gamma, F) -> np.ndarray:
+    """U = M (D gamma + F) over a general constraint list."""
+    d = _f64(dir_)
+    n = d.shape[0]
+    la, l0 = _len_args(length, n)
+    U = np.empty((n, 6))
+    _load().ora_velocity(n, _p(d), _p(la), l0, diam, eta, gc.n, _p(gc.pi), _p(gc.pj), _p(gc.e), _p(gc.arm),
+                         _p(_f64(gamma)), _p(_f64(F)), _p(U))
+    return U

@@ -497,16 +497,23 @@ static void pair_geometry(const double *x, const double *dir, const double *len,
 }
 
 /* Full 12-entry column of D for constraint c: [F_P(3), T_P(3), F_Q(3), T_Q(3)] per unit gamma. */
+/* A constraint against a fixed body (j < 0: a wall, or a tether to a fixed */
+/* point) has no Q side: only e_P and y_P enter D (Appendix "Equation of    */
+/* motion with geometric constraints", last paragraph).                     */
 static void d_column(const double *dir, int32_t i, int32_t j, const double *e, double si, double sj, double *col)
 {
     double yP[3], yQ[3], t[3];
     for (int a = 0; a < 3; ++a) {
         yP[a] = si * dir[3 * i + a];
-        yQ[a] = sj * dir[3 * j + a];
+        yQ[a] = j >= 0 ? sj * dir[3 * j + a] : 0.0;
     }
     for (int a = 0; a < 3; ++a) col[a] = e[a];
     cross3(yP, e, t);
     for (int a = 0; a < 3; ++a) col[3 + a] = t[a];
+    if (j < 0) {
+        for (int a = 6; a < 12; ++a) col[a] = 0.0;
+        return;
+    }
     double me[3] = {-e[0], -e[1], -e[2]};
     for (int a = 0; a < 3; ++a) col[6 + a] = me[a];
     cross3(yQ, me, t);
@@ -545,7 +552,7 @@ void ora_dense_D(int64_t n, const double *dir, int64_t nc, const int32_t *pi, co
         d_column(dir, pi[k], pj[k], e + 3 * k, arm[2 * k], arm[2 * k + 1], col);
         for (int a = 0; a < 6; ++a) {
             D[(6 * (int64_t)pi[k] + a) * nc + k] += col[a];
-            D[(6 * (int64_t)pj[k] + a) * nc + k] += col[6 + a];
+            if (pj[k] >= 0) D[(6 * (int64_t)pj[k] + a) * nc + k] += col[6 + a];
         }
     }
 }
@@ -556,13 +563,23 @@ void ora_dense_D(int64_t n, const double *dir, int64_t nc, const int32_t *pi, co
 /* scatter over constraints, M is applied per rod, D^T U is a gather.       */
 /* Fc[n][6] receives D gamma and Uc[n][6] receives M D gamma.               */
 /* ------------------------------------------------------------------------ */
+/* General constraint set (used by the bilateral and wall extensions):      */
+/* kind[c] = 0 for a unilateral constraint (gamma_c >= 0, complementarity), */
+/* 1 for a bilateral one (gamma_c free; eq. linearconstraints b), whose row */
+/* of Mc carries the compliance cmp[c] = 1/(kappa_c h) on the diagonal       */
+/* (eq. blockdef, block F: D_b^T M D_b + K^-1 / h).  kind == NULL: all      */
+/* unilateral.  pj[c] < 0: a constraint against a fixed body.               */
 typedef struct {
     int64_t n, nc;
     const double *dir, *len;
     double len0, diam, eta;
     const int32_t *pi, *pj;
     const double *e, *arm, *q;
+    const uint8_t *kind;
+    const double *cmp;
 } ora_sys;
+
+static int is_bilateral(const ora_sys *S, int64_t k) { return S->kind && S->kind[k]; }
 
 static void sys_D_gamma(const ora_sys *S, const double *gamma, double *Fc)
 {
@@ -572,7 +589,7 @@ static void sys_D_gamma(const ora_sys *S, const double *gamma, double *Fc)
         d_column(S->dir, S->pi[k], S->pj[k], S->e + 3 * k, S->arm[2 * k], S->arm[2 * k + 1], col);
         for (int a = 0; a < 6; ++a) {
             Fc[6 * S->pi[k] + a] += col[a] * gamma[k];
-            Fc[6 * S->pj[k] + a] += col[6 + a] * gamma[k];
+            if (S->pj[k] >= 0) Fc[6 * S->pj[k] + a] += col[6 + a] * gamma[k];
         }
     }
 }
@@ -583,17 +600,22 @@ static void sys_DT_U(const ora_sys *S, const double *U, double *w)
     for (int64_t k = 0; k < S->nc; ++k) {
         d_column(S->dir, S->pi[k], S->pj[k], S->e + 3 * k, S->arm[2 * k], S->arm[2 * k + 1], col);
         double v = 0.0;
-        for (int a = 0; a < 6; ++a) v += col[a] * U[6 * S->pi[k] + a] + col[6 + a] * U[6 * S->pj[k] + a];
+        for (int a = 0; a < 6; ++a) {
+            v += col[a] * U[6 * S->pi[k] + a];
+            if (S->pj[k] >= 0) v += col[6 + a] * U[6 * S->pj[k] + a];
+        }
         w[k] = v;
     }
 }
 
-/* w = Mc gamma (+ q if add_q) */
+/* w = Mc gamma (+ q if add_q); Mc includes the bilateral compliances */
 static void sys_apply(const ora_sys *S, const double *gamma, int add_q, double *Fc, double *Uc, double *w)
 {
     sys_D_gamma(S, gamma, Fc);
     ora_apply_mobility(S->n, S->dir, S->len, S->len0, S->diam, S->eta, Fc, Uc);
     sys_DT_U(S, Uc, w);
+    for (int64_t k = 0; k < S->nc; ++k)
+        if (is_bilateral(S, k)) w[k] += S->cmp[k] * gamma[k];
     if (add_q)
         for (int64_t k = 0; k < S->nc; ++k) w[k] += S->q[k];
 }
@@ -602,7 +624,7 @@ void ora_apply_Mc(int64_t n, const double *dir, const double *len, double len0, 
                   const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
                   const double *gamma, double *w)
 {
-    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, q};
+    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, q, NULL, NULL};
     double *Fc = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
     double *Uc = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
     sys_apply(&S, gamma, q != NULL, Fc, Uc, w);
@@ -616,7 +638,7 @@ void ora_velocity(int64_t n, const double *dir, const double *len, double len0, 
                   const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *gamma,
                   const double *F, double *U)
 {
-    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, NULL};
+    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, NULL, NULL, NULL};
     double *Ft = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
     sys_D_gamma(&S, gamma, Ft);
     for (int64_t k = 0; k < 6 * n; ++k) Ft[k] += F[k];
@@ -647,22 +669,20 @@ void ora_velocity(int64_t n, const double *dir, const double *len, double len0, 
 /*   [1e-12 alpha0, 1e12 alpha0]; otherwise alpha is kept.                  */
 /* info = {iterations, residual, status}.                                   */
 /* ------------------------------------------------------------------------ */
-static double natural_residual(int64_t nc, const double *gamma, const double *g)
+static double natural_residual(const ora_sys *S, const double *gamma, const double *g)
 {
     double r = 0.0;
-    for (int64_t k = 0; k < nc; ++k) {
-        const double m = fabs(gamma[k] < g[k] ? gamma[k] : g[k]);
+    for (int64_t k = 0; k < S->nc; ++k) {
+        /* bilateral rows: the residual of the equation itself, |w| */
+        const double m = is_bilateral(S, k) ? fabs(g[k]) : fabs(gamma[k] < g[k] ? gamma[k] : g[k]);
         r = m > r ? m : r;
     }
     return r;
 }
 
-int ora_bbpgd(int64_t n, const double *dir, const double *len, double len0, double diam, double eta, int64_t nc,
-              const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q, double tol,
-              int64_t max_iter, double *gamma /* in: start, out: solution */, double *g_out /* may be NULL */,
-              double *info /* [3]: iterations, residual, alpha0 */)
+static int bbpgd_core(const ora_sys *S, double tol, int64_t max_iter, double *gamma, double *g_out, double *info)
 {
-    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, q};
+    const int64_t n = S->n, nc = S->nc;
     const int64_t nb = nc > 0 ? nc : 1, rb = n > 0 ? n : 1;
     double *g = (double *)malloc(sizeof(double) * nb), *gn = (double *)malloc(sizeof(double) * nb);
     double *gam_n = (double *)malloc(sizeof(double) * nb), *gh = (double *)malloc(sizeof(double) * nb);
@@ -671,17 +691,19 @@ int ora_bbpgd(int64_t n, const double *dir, const double *len, double len0, doub
     int64_t it = 0;
     double res, alpha = 1.0, alpha0 = 1.0;
 
-    for (int64_t k = 0; k < nc; ++k) gamma[k] = gamma[k] > 0.0 ? gamma[k] : 0.0;
-    sys_apply(&S, gamma, 1, Fc, Uc, g);
-    res = natural_residual(nc, gamma, g);
+    /* projection onto the feasible set: gamma_u >= 0, gamma_b free */
+    for (int64_t k = 0; k < nc; ++k)
+        if (!is_bilateral(S, k)) gamma[k] = gamma[k] > 0.0 ? gamma[k] : 0.0;
+    sys_apply(S, gamma, 1, Fc, Uc, g);
+    res = natural_residual(S, gamma, g);
     if (res > tol) {
         double ghgh = 0.0, ghMgh = 0.0;
         for (int64_t k = 0; k < nc; ++k) {
-            gh[k] = (gamma[k] <= 0.0 && g[k] > 0.0) ? 0.0 : g[k];
+            gh[k] = (!is_bilateral(S, k) && gamma[k] <= 0.0 && g[k] > 0.0) ? 0.0 : g[k];
             ghgh += gh[k] * gh[k];
         }
         if (ghgh == 0.0) goto done;
-        sys_apply(&S, gh, 0, Fc, Uc, gn);
+        sys_apply(S, gh, 0, Fc, Uc, gn);
         for (int64_t k = 0; k < nc; ++k) ghMgh += gh[k] * gn[k];
         alpha0 = ghMgh > 0.0 ? ghgh / ghMgh : 1.0;
         alpha = alpha0;
@@ -689,11 +711,11 @@ int ora_bbpgd(int64_t n, const double *dir, const double *len, double len0, doub
         for (int64_t k = 0; k < max_iter; ++k) {
             for (int64_t c = 0; c < nc; ++c) {
                 const double v = gamma[c] - alpha * g[c];
-                gam_n[c] = v > 0.0 ? v : 0.0;
+                gam_n[c] = (is_bilateral(S, c) || v > 0.0) ? v : 0.0;
             }
-            sys_apply(&S, gam_n, 1, Fc, Uc, gn);
+            sys_apply(S, gam_n, 1, Fc, Uc, gn);
             it = k + 1;
-            res = natural_residual(nc, gam_n, gn);
+            res = natural_residual(S, gam_n, gn);
             double ss = 0.0, sy = 0.0, yy = 0.0;
             for (int64_t c = 0; c < nc; ++c) {
                 const double sc = gam_n[c] - gamma[c], yc = gn[c] - g[c];
@@ -731,6 +753,126 @@ done:
     free(Fc);
     free(Uc);
     return status;
+}
+
+int ora_bbpgd(int64_t n, const double *dir, const double *len, double len0, double diam, double eta, int64_t nc,
+              const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q, double tol,
+              int64_t max_iter, double *gamma /* in: start, out: solution */, double *g_out /* may be NULL */,
+              double *info /* [3]: iterations, residual, alpha0 */)
+{
+    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, q, NULL, NULL};
+    return bbpgd_core(&S, tol, max_iter, gamma, g_out, info);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mixed problem of eq. linearconstraints: unilateral constraints           */
+/* (kind 0) and bilateral ones (kind 1, compliance cmp), in any order, some */
+/* possibly against fixed bodies (pj < 0).  The quadratic program of eq.    */
+/* suppcqpdef with gamma_u >= 0 and gamma_b free, by the same BBPGD: the    */
+/* projection and the projected gradient leave bilateral entries alone,     */
+/* and the stop test uses |w_b| for them.                                    */
+/* ------------------------------------------------------------------------ */
+int ora_bbpgd_gen(int64_t n, const double *dir, const double *len, double len0, double diam, double eta, int64_t nc,
+                  const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                  const uint8_t *kind, const double *cmp, double tol, int64_t max_iter, double *gamma,
+                  double *g_out, double *info)
+{
+    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, q, kind, cmp};
+    return bbpgd_core(&S, tol, max_iter, gamma, g_out, info);
+}
+
+void ora_apply_Mc_gen(int64_t n, const double *dir, const double *len, double len0, double diam, double eta,
+                      int64_t nc, const int32_t *pi, const int32_t *pj, const double *e, const double *arm,
+                      const double *q, const uint8_t *kind, const double *cmp, const double *gamma, double *w)
+{
+    ora_sys S = {n, nc, dir, len, len0, diam, eta, pi, pj, e, arm, q, kind, cmp};
+    double *Fc = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
+    double *Uc = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
+    sys_apply(&S, gamma, q != NULL, Fc, Uc, w);
+    free(Fc);
+    free(Uc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Bilateral (spring) constraints: a Hookean link between the point at      */
+/* arclength sP on rod P's axis and the point at sQ on rod Q's axis         */
+/* (points fixed on the bodies; Appendix "Equation of motion with geometric */
+/* constraints": Phi_b is the distance between two fixed points, the link's */
+/* length).  r = x_P + sP d_P - (x_Q + sQ d_Q), each component of the       */
+/* centre difference taken to its nearest periodic image; length = |r|,     */
+/* e = r / |r| (from Q to P, gamma > 0 pushes the ends apart), the column   */
+/* of D is [e; y_P x e; -e; -(y_Q x e)] as for a contact (Appendix          */
+/* "Symmetry ...": the points are arbitrary for bilateral constraints).     */
+/* The Hookean law K (Phi_b - Phi_b^0) = -gamma_b (eq. bilateralconstraint) */
+/* linearised over the step gives the row (eq. linearconstraints b; eq.     */
+/* blockdef D and F): q_b = (length - rest)/h + D_b^T M F, and the diagonal */
+/* compliance cmp = 1/(kappa h) (kappa = +inf: a rigid joint, cmp = 0).     */
+/* A link of zero length has no direction: e is then taken normal to both   */
+/* axes, d_P x d_Q normalised, or d_P x (the coordinate axis least aligned  */
+/* with d_P) when the axes are parallel; its flag is set.  Q < 0 anchors    */
+/* the link at the fixed point (sQ unused) given in anchor[3*k].            */
+/* ------------------------------------------------------------------------ */
+static void unit_normal_of(const double *dP, const double *dQ, double *e)
+{
+    double c[3];
+    cross3(dP, dQ, c);
+    double nn = sqrt(dot3(c, c));
+    if (nn < 1e-12) {
+        const double ax = fabs(dP[0]), ay = fabs(dP[1]), az = fabs(dP[2]);
+        double ek[3] = {0.0, 0.0, 0.0};
+        int k = 0;
+        double best = ax;
+        if (ay < best) {
+            k = 1;
+            best = ay;
+        }
+        if (az < best) k = 2;
+        ek[k] = 1.0;
+        cross3(dP, ek, c);
+        nn = sqrt(dot3(c, c));
+    }
+    for (int a = 0; a < 3; ++a) e[a] = c[a] / nn;
+}
+
+void ora_links(int64_t n, const double *x, const double *dir, const double *len, double len0, const double *box,
+               double diam, double eta, double dt, int64_t nl, const int32_t *lp, const int32_t *lq,
+               const double *sarm, const double *kappa, const double *rest, const double *anchor, const double *F,
+               double *length, double *e, double *q, double *cmp, uint8_t *flags)
+{
+    double *Unc = (double *)calloc((size_t)(6 * (n > 0 ? n : 1)), sizeof(double));
+    if (F) ora_apply_mobility(n, dir, len, len0, diam, eta, F, Unc);
+    for (int64_t k = 0; k < nl; ++k) {
+        const int32_t P = lp[k], Q = lq[k];
+        const double sP = sarm[2 * k], sQ = sarm[2 * k + 1];
+        double r[3];
+        for (int a = 0; a < 3; ++a) {
+            const double aP = x[3 * P + a] + sP * dir[3 * P + a];
+            const double aQ = Q >= 0 ? x[3 * Q + a] + sQ * dir[3 * Q + a] : anchor[3 * k + a];
+            double d = aP - aQ;
+            d -= box[a] * floor(d / box[a] + 0.5);
+            r[a] = d;
+        }
+        const double L = sqrt(dot3(r, r));
+        flags[k] = 0;
+        if (L < ORA_DEGEN_DIST) {
+            const double ez[3] = {0.0, 0.0, 1.0};
+            unit_normal_of(dir + 3 * P, Q >= 0 ? dir + 3 * Q : ez, e + 3 * k);
+            flags[k] = ORA_FLAG_DEGENERATE;
+        } else {
+            for (int a = 0; a < 3; ++a) e[3 * k + a] = r[a] / L;
+        }
+        length[k] = L;
+        double col[12];
+        d_column(dir, P, Q, e + 3 * k, sP, sQ, col);
+        double dtu = 0.0;
+        for (int a = 0; a < 6; ++a) {
+            dtu += col[a] * Unc[6 * P + a];
+            if (Q >= 0) dtu += col[6 + a] * Unc[6 * Q + a];
+        }
+        q[k] = (L - rest[k]) / dt + dtu;
+        cmp[k] = isinf(kappa[k]) ? 0.0 : 1.0 / (kappa[k] * dt);
+    }
+    free(Unc);
 }
 
 /* ------------------------------------------------------------------------ */

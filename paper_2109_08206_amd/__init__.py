@@ -45,6 +45,11 @@ class SolveInfo(C.Structure):
                 ("status", C.c_int32), ("fp64_refreshes", C.c_int32)]
 
 
+class RLLinks(C.Structure):
+    _fields_ = [("n_links", C.c_int64), ("p", C.c_void_p), ("q", C.c_void_p), ("arm", C.c_void_p),
+                ("kappa", C.c_void_p), ("rest", C.c_void_p), ("anchor", C.c_void_p)]
+
+
 class StepExtra(C.Structure):
     _fields_ = [("x_unwrapped", C.c_void_p)]
 
@@ -58,7 +63,8 @@ class AdjointInfo(C.Structure):
 SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_stream", "rl_reserve",
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
-           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_solve_lcp_noalloc")
+           "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_solve_lcp_noalloc",
+           "rl_assemble_links", "rl_solve_general")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -89,6 +95,9 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_solve_lcp": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)], C.c_int),
             "rl_solve_lcp_noalloc": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)],
                                      C.c_int),
+            "rl_assemble_links": ([H, I64, P, P, P, D, C.POINTER(RLLinks), P, P, P, P, P, P], C.c_int),
+            "rl_solve_general": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)],
+                                 C.c_int),
             "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64), P, I64, I32,
                          C.POINTER(StepExtra)], C.c_int),
             "rl_profile_enable": ([H, C.c_int], C.c_int),
@@ -327,6 +336,56 @@ class Solver:
             _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
             _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
         self._check(rc, "rl_solve_lcp_noalloc")
+        return gamma, U, _result(info)
+
+    @staticmethod
+    def links_struct(p, q, arm, kappa, rest, anchor=None):
+        """An rl_links over device tensors (kept alive by the caller)."""
+        torch = _torch()
+        nl = p.shape[0]
+        return RLLinks(nl, _ptr(p, torch.int32, (nl,), "p"), _ptr(q, torch.int32, (nl,), "q"),
+                       _ptr(arm, torch.float64, (nl, 2), "arm"), _ptr(kappa, torch.float64, (nl,), "kappa"),
+                       _ptr(rest, torch.float64, (nl,), "rest"),
+                       _ptr(anchor, torch.float64, (nl, 3), "anchor"))
+
+    def assemble_links(self, x, dir_, length, p, q, arm, kappa, rest, anchor=None, F=None):
+        """Link geometry: returns (length, e, q, cmp, flags)."""
+        torch = _torch()
+        n, nl = x.shape[0], p.shape[0]
+        la, l0 = _len_args(length, n)
+        dev = x.device
+        L = torch.empty(nl, dtype=torch.float64, device=dev)
+        e = torch.empty((nl, 3), dtype=torch.float64, device=dev)
+        qq = torch.empty(nl, dtype=torch.float64, device=dev)
+        cmp = torch.empty(nl, dtype=torch.float64, device=dev)
+        fl = torch.empty(max(nl, 1), dtype=torch.uint8, device=dev)
+        lk = self.links_struct(p, q, arm, kappa, rest, anchor)
+        self._stream()
+        self._check(self.lib.rl_assemble_links(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
+                                               _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, C.byref(lk),
+                                               _ptr(F, torch.float64, (n, 6), "F"), _ptr(L), _ptr(e), _ptr(qq),
+                                               _ptr(cmp), _ptr(fl)), "rl_assemble_links")
+        return L, e, qq, cmp, fl[:nl]
+
+    def solve_general(self, dir_, length, pi, pj, e, arm, q, kind, cmp, F=None, gamma=None, U=None):
+        """Mixed unilateral/bilateral problem over a general list (any order;
+        pj = -1 for a fixed body).  Returns (gamma, U, SolveResult)."""
+        torch = _torch()
+        n, nc = dir_.shape[0], pi.shape[0]
+        la, l0 = _len_args(length, n)
+        dev = dir_.device
+        gamma = torch.zeros(nc, dtype=torch.float64, device=dev) if gamma is None else gamma
+        U = torch.empty((n, 6), dtype=torch.float64, device=dev) if U is None else U
+        info = SolveInfo()
+        self._stream()
+        rc = self.lib.rl_solve_general(
+            self._h, n, _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0, nc, _ptr(pi, torch.int32, (nc,), "pi"),
+            _ptr(pj, torch.int32, (nc,), "pj"), _ptr(e, torch.float64, (nc, 3), "e"),
+            _ptr(arm, torch.float64, (nc, 2), "arm"), _ptr(q, torch.float64, (nc,), "q"),
+            _ptr(kind, torch.uint8, (nc,), "kind"), _ptr(cmp, torch.float64, (nc,), "cmp"),
+            _ptr(F, torch.float64, (n, 6), "F"), _ptr(gamma, torch.float64, (nc,), "gamma"),
+            _ptr(U, torch.float64, (n, 6), "U"), C.byref(info))
+        self._check(rc, "rl_solve_general")
         return gamma, U, _result(info)
 
     def solve_lcp_batched(self, rod_off, pair_off, dir_, length, pi, pj, e, arm, q, F=None, gamma=None, U=None):

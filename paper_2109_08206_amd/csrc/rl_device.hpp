@@ -200,6 +200,16 @@ __device__ __forceinline__ double gamma_prime(double gam, double g, double alpha
     return gam;
 }
 
+// The same step for a bilateral (free) constraint: no projection
+// (eq. linearconstraints b: gamma_b may take any sign).
+template <int MODE>
+__device__ __forceinline__ double gamma_free(double gam, double g, double alpha)
+{
+    if (MODE == kModeAlpha0) return g;
+    if (MODE == kModeLoop) return fma(-alpha, g, gam);
+    return gam;
+}
+
 // Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
 // rod r, split over the kRodLanes lanes of the rod and combined by a fixed
 // tree.  The torque on the rod is dir x m.  A lane takes the records sub,
@@ -218,6 +228,7 @@ struct RodRec {
 
 struct RodLoads {
     int pb, pe, qb, qe;
+    int ps, qs;  // general constraint sets: first bilateral record of each side
     RodRec p[kRodRounds], q[kRodRounds];  // the first rounds of the P and Q sides
 };
 
@@ -241,6 +252,7 @@ __device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qpt
                                          bool active, int sub, RodLoads &L)
 {
     L.pb = L.pe = L.qb = L.qe = 0;
+    L.ps = L.qs = 0x7fffffff;
     if (active) {
         L.pb = pptr[r] + sub;
         L.pe = pptr[r + 1];
@@ -259,6 +271,16 @@ __device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool act
     rod_load(a.pptr, a.qptr, a.st, a.stq, a.geo, a.qgeo, r, active, sub, L);
 }
 
+// general constraint sets: a rod's records are unilateral before ps (P side,
+// constraint index) and qs (Q side, list position), bilateral from there on
+__device__ __forceinline__ void rod_load_split(const SolveArgs &a, int64_t r, bool active, RodLoads &L)
+{
+    if (active) {
+        L.ps = a.psplit[r];
+        L.qs = a.qsplit[r];
+    }
+}
+
 // f += +-gamma' e, m += +-gamma' s e for one incidence record
 __device__ __forceinline__ void rod_add(double sign, double gm, double2 g0, double2 g1, double f[3], double m[3])
 {
@@ -271,29 +293,37 @@ __device__ __forceinline__ void rod_add(double sign, double gm, double2 g0, doub
     m[2] += gs * g1.x;
 }
 
-template <int MODE>
-__device__ __forceinline__ void rod_side(double sign, const double2 *st, const double *geo, int b, int e,
+template <int MODE, bool BIL>
+__device__ __forceinline__ double gamma_of(double gam, double g, double alpha, int c, int split)
+{
+    if (BIL && c >= split) return gamma_free<MODE>(gam, g, alpha);
+    return gamma_prime<MODE>(gam, g, alpha);
+}
+
+template <int MODE, bool BIL = false>
+__device__ __forceinline__ void rod_side(double sign, const double2 *st, const double *geo, int b, int e, int split,
                                          const RodRec *rr, double alpha, double f[3], double m[3])
 {
 #pragma unroll
     for (int i = 0; i < kRodRounds; ++i) {
-        if (b + i * kRodLanes >= e) return;
-        rod_add(sign, gamma_prime<MODE>(rr[i].s.x, rr[i].s.y, alpha), rr[i].g0, rr[i].g1, f, m);
+        const int c = b + i * kRodLanes;
+        if (c >= e) return;
+        rod_add(sign, gamma_of<MODE, BIL>(rr[i].s.x, rr[i].s.y, alpha, c, split), rr[i].g0, rr[i].g1, f, m);
     }
     for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
         const double2 sg = st[c];
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
-        rod_add(sign, gamma_prime<MODE>(sg.x, sg.y, alpha), gd[0], gd[1], f, m);
+        rod_add(sign, gamma_of<MODE, BIL>(sg.x, sg.y, alpha, c, split), gd[0], gd[1], f, m);
     }
 }
 
-template <int MODE>
+template <int MODE, bool BIL = false>
 __device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads &L, double alpha, double f[3],
                                                double m[3])
 {
     f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    rod_side<MODE>(1.0, a.st, a.geo, L.pb, L.pe, L.p, alpha, f, m);
-    rod_side<MODE>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.q, alpha, f, m);
+    rod_side<MODE, BIL>(1.0, a.st, a.geo, L.pb, L.pe, L.ps, L.p, alpha, f, m);
+    rod_side<MODE, BIL>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.qs, L.q, alpha, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -363,6 +393,43 @@ __device__ __forceinline__ void con_apply(const SolveArgs &a, int64_t c, double 
     }
 }
 
+// The same for a general constraint set (FP64): cm >= 0 marks a bilateral
+// constraint with compliance cm (its row of Mc has cm added on the diagonal,
+// eq. blockdef block F; gamma is not projected and the residual is |w|);
+// cm < 0 a unilateral one.  qp < 0: no Q side (a fixed body).
+template <int MODE>
+__device__ __forceinline__ void con_apply_gen(const SolveArgs &a, int64_t c, double w, double q, double2 sg, int qp,
+                                              double cm, double alpha, double p[4])
+{
+    const bool bil = cm >= 0.0;
+    if (MODE == kModeApply) {
+        a.out[c] = w + q + (bil ? cm * sg.x : 0.0);
+        return;
+    }
+    if (MODE == kModeAlpha0) {
+        const double gh = bil ? sg.y : gamma_prime<kModeAlpha0>(sg.x, sg.y, 0.0);
+        p[0] += gh * gh;
+        p[1] += gh * (w + (bil ? cm * gh : 0.0));
+        return;
+    }
+    const double gp = MODE == kModeInit ? (bil ? sg.x : gamma_prime<kModeInit>(sg.x, 0.0, 0.0))
+                                        : (bil ? gamma_free<kModeLoop>(sg.x, sg.y, alpha)
+                                               : gamma_prime<kModeLoop>(sg.x, sg.y, alpha));
+    w += q + (bil ? cm * gp : 0.0);
+    a.st[c] = make_double2(gp, w);
+    if (qp >= 0) a.stq[qp] = make_double2(gp, w);
+    const double r = bil ? fabs(w) : fabs(gp < w ? gp : w);
+    if (MODE == kModeInit) {
+        p[2] += w * w;
+    } else {
+        const double sc = gp - sg.x, yc = w - sg.y;
+        p[0] += sc * sc;
+        p[1] += sc * yc;
+        p[2] += yc * yc;
+    }
+    p[3] = fmax(p[3], r);
+}
+
 // ---------------------------------------------------------------------------
 // contact-velocity form: the rod kernel projects its rod's
 // (V, W) onto e at every contact point it takes part in, u = e.(V + s W), so
@@ -401,6 +468,7 @@ __device__ __forceinline__ void rod_emit_u(const SolveArgs &a, const RodLoads &L
 struct ConLoadsU {
     double2 sg;
     double q, up, uq;
+    double cm;  // general sets: compliance (bilateral) or -1 (unilateral)
     int qp;
 };
 
@@ -429,11 +497,30 @@ __device__ __forceinline__ void con_load_u(const SolveArgs &a, int64_t c, ConLoa
     con_load_u<MODE>(ConIn{a.qpos, a.uP, a.qv, a.st, a.uQ}, c, L);
 }
 
+// general sets: every mode reads the state (the compliance term needs
+// gamma), a constraint without a Q side reads no u_Q
+__device__ __forceinline__ void con_load_gen(const ConIn &in, const double *cmpv, int64_t c, ConLoadsU &L)
+{
+    L.qp = in.qpos[c];
+    L.up = in.uP[c];
+    L.q = in.qv[c];
+    L.sg = in.st[c];
+    L.cm = cmpv[c];
+    L.uq = L.qp >= 0 ? in.uQ[L.qp] : 0.0;
+}
+
 template <int MODE>
 __device__ __forceinline__ void con_update_u(const SolveArgs &a, int64_t c, const ConLoadsU &L, double alpha,
                                              double p[4])
 {
     con_apply<MODE>(a, c, L.up - L.uq, L.q, L.sg, L.qp, alpha, p);
+}
+
+template <int MODE>
+__device__ __forceinline__ void con_update_gen(const SolveArgs &a, int64_t c, const ConLoadsU &L, double alpha,
+                                               double p[4])
+{
+    con_apply_gen<MODE>(a, c, L.up - L.uq, L.q, L.sg, L.qp, L.cm, alpha, p);
 }
 
 }  // namespace rl

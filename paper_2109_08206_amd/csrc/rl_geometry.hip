@@ -811,6 +811,120 @@ __global__ void k_assemble(int64_t nc, const double *__restrict__ x, const doubl
     q[c] = ph / dt + rate;
 }
 
+hipError_t launch_unc(hipStream_t st, int64_t n, const double *dir, const double *len, double len0, double diam,
+                      double eta, const double *F, double *Unc)
+{
+    if (n <= 0) return hipSuccess;
+    const Mob mob = mobility_of(len ? 1.0 : len0, diam, eta);
+    if (len)
+        hipLaunchKernelGGL(k_unc<false>, dim3(grid_of(n)), dim3(kBlock), 0, st, n, dir, len, mob, diam, eta, F, Unc);
+    else
+        hipLaunchKernelGGL(k_unc<true>, dim3(grid_of(n)), dim3(kBlock), 0, st, n, dir, len, mob, diam, eta, F, Unc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Bilateral links (eq. linearconstraints b): a Hookean link between the point
+// at arclength sP on rod P's axis and the point at sQ on rod Q's axis, or a
+// fixed point (Q < 0).  r = (x_P + sP d_P) - (x_Q + sQ d_Q) with each
+// component of the difference taken to its nearest periodic image; the
+// link's length is |r|, its direction e = r/|r| (from Q to P), its column of
+// D is that of a contact with lever arms sP d_P and sQ d_Q (Appendix
+// "Symmetry ...": the two points are arbitrary for bilateral constraints).
+// Row (eq. blockdef D and F): q = (|r| - rest)/h + D^T M F, compliance
+// 1/(kappa h), 0 for kappa = +inf.  A link of zero length takes e normal to
+// both axes (d_P x d_Q, or d_P x the coordinate axis least aligned with d_P
+// for parallel axes, d_Q = e_z for a fixed point) and flag bit 2.
+// inv (may be null) maps the caller's rod index to the rods' order in x.
+// ---------------------------------------------------------------------------
+__device__ V3 normal_to(V3 dp, V3 dq)
+{
+    V3 c = cross(dp, dq);
+    double nn = sqrt(dot(c, c));
+    if (nn < 1e-12) {
+        const double ax = fabs(dp.x), ay = fabs(dp.y), az = fabs(dp.z);
+        int k = 0;
+        double best = ax;
+        if (ay < best) {
+            k = 1;
+            best = ay;
+        }
+        if (az < best) k = 2;
+        c = cross(dp, v3(k == 0 ? 1.0 : 0.0, k == 1 ? 1.0 : 0.0, k == 2 ? 1.0 : 0.0));
+        nn = sqrt(dot(c, c));
+    }
+    return v3(c.x / nn, c.y / nn, c.z / nn);
+}
+
+__global__ void k_links(int64_t nl, int64_t n, const double *__restrict__ x, const double *__restrict__ dir,
+                        const int *__restrict__ inv, const int32_t *__restrict__ lp, const int32_t *__restrict__ lq,
+                        const double *__restrict__ larm, const double *__restrict__ kappa,
+                        const double *__restrict__ rest, const double *__restrict__ anchor, GridDev g, double dt,
+                        const double *__restrict__ Unc, int32_t *__restrict__ pi_out, int32_t *__restrict__ pj_out,
+                        double *__restrict__ len_out, double *__restrict__ e_out, double *__restrict__ arm_out,
+                        double *__restrict__ q_out, double *__restrict__ cmp_out, uint8_t *__restrict__ fl_out,
+                        int *__restrict__ err)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= nl) return;
+    const int32_t P0 = lp[k], Q0 = lq[k];
+    const double kap = kappa[k], r0 = rest[k];
+    if (P0 < 0 || P0 >= n || Q0 >= n || Q0 < -1 || P0 == Q0 || (Q0 < 0 && !anchor) || !(kap > 0.0) ||
+        !(r0 >= 0.0) || !isfinite(r0)) {
+        atomicOr(err, 16);
+        return;
+    }
+    const int P = inv ? inv[P0] : P0, Q = Q0 < 0 ? -1 : (inv ? inv[Q0] : Q0);
+    const double sP = larm[2 * k], sQ = larm[2 * k + 1];
+    const V3 xP = load3(x + 3 * (int64_t)P), dP = load3(dir + 3 * (int64_t)P);
+    const V3 aP = xP + sP * dP;
+    V3 dQ = v3(0.0, 0.0, 1.0), aQ;
+    if (Q >= 0) {
+        dQ = load3(dir + 3 * (int64_t)Q);
+        aQ = load3(x + 3 * (int64_t)Q) + sQ * dQ;
+    } else {
+        aQ = load3(anchor + 3 * k);
+    }
+    double r[3] = {aP.x - aQ.x, aP.y - aQ.y, aP.z - aQ.z};
+    for (int a = 0; a < 3; ++a) r[a] -= g.box[a] * floor(r[a] / g.box[a] + 0.5);
+    const V3 rv = v3(r[0], r[1], r[2]);
+    const double L = sqrt(dot(rv, rv));
+    V3 e;
+    uint8_t fl = 0;
+    if (L < kDegenDist) {
+        e = normal_to(dP, dQ);
+        fl = 4;
+    } else {
+        e = v3(rv.x / L, rv.y / L, rv.z / L);
+    }
+    // D^T U_nc: e.U_P + (sP d_P x e).W_P - e.U_Q - (sQ d_Q x e).W_Q
+    double rate = dot(e, load3(Unc + 6 * (int64_t)P)) + dot(cross(sP * dP, e), load3(Unc + 6 * (int64_t)P + 3));
+    if (Q >= 0)
+        rate -= dot(e, load3(Unc + 6 * (int64_t)Q)) + dot(cross(sQ * dQ, e), load3(Unc + 6 * (int64_t)Q + 3));
+    pi_out[k] = P;
+    pj_out[k] = Q;
+    len_out[k] = L;
+    store3(e_out + 3 * k, e);
+    arm_out[2 * k] = sP;
+    arm_out[2 * k + 1] = Q >= 0 ? sQ : 0.0;
+    q_out[k] = (L - r0) / dt + rate;
+    cmp_out[k] = isinf(kap) ? 0.0 : 1.0 / (kap * dt);
+    if (fl_out) fl_out[k] = fl;
+}
+
+hipError_t launch_links(hipStream_t st, int64_t nl, int64_t n, const double *x, const double *dir, const int *inv,
+                        const rl_links *lk, const double box[3], double dt, const double *Unc, int32_t *pi,
+                        int32_t *pj, double *len, double *e, double *arm, double *q, double *cmp, uint8_t *flags,
+                        int *err)
+{
+    if (nl <= 0) return hipSuccess;
+    GridDev g{};
+    for (int a = 0; a < 3; ++a) g.box[a] = box[a];
+    hipLaunchKernelGGL(k_links, dim3(grid_of(nl)), dim3(kBlock), 0, st, nl, n, x, dir, inv, lk->p, lk->q, lk->arm,
+                       lk->kappa, lk->rest, lk->anchor, g, dt, Unc, pi, pj, len, e, arm, q, cmp, flags, err);
+    return hipGetLastError();
+}
+
 int assemble_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                   int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
                   double *phi, double *e, double *arm, double *q)

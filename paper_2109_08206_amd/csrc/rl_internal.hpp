@@ -120,6 +120,12 @@ struct SolveArgs {
     const float4 *qgeo32;   // [nc] Q-side list order: (ex, ey, ez, s_j)
     float *uP32;            // [nc] contact velocities of the correction, P side
     float *uQ32;            // [nc] the same, Q side in list order
+    // general constraint sets (bilateral links, fixed bodies): constraints
+    // sorted by (pi, kind), Q lists by (kind, index)
+    bool gen;               // the set holds bilateral or one-sided constraints
+    const int32_t *psplit;  // [n] first bilateral constraint of rod r's P range
+    const int32_t *qsplit;  // [n] first bilateral position in rod r's Q list
+    const double *cmpv;     // [nc] compliance 1/(kappa h) (bilateral) or -1 (unilateral)
 };
 
 // --- kernels launchers (implemented in the .hip files) ----------------------
@@ -143,7 +149,7 @@ struct rl_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     // grow-only workspace slots
-    static constexpr int kSlots = 96;
+    static constexpr int kSlots = 128;
     void *buf[kSlots] = {};
     size_t cap[kSlots] = {};
     rl::SolverState *state = nullptr;       // device
@@ -185,6 +191,8 @@ enum Slot : int {
     kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs, kWsQv, kWsUP, kWsUQ,
+    kWsGenKey, kWsGenKeyOut, kWsGenOrd, kWsGenPi, kWsGenPj, kWsGenE, kWsGenArm, kWsGenQ, kWsGenCmp, kWsGenGamma,
+    kWsGenPsplit, kWsGenQsplit, kWsLinkLen, kWsLinkFlags, kWsInvPerm,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -276,6 +284,20 @@ hipError_t launch_geo_adjoint(hipStream_t st, int64_t nc, const double *x, const
                               double len0, const double box[3], const int32_t *pi, const int32_t *pj,
                               const int32_t *img, double dt, const double *q_bar, const double *e_bar,
                               const double *arm_bar, const double *d_bar, double *gbar);
+// general constraint sets (rl_general.hip): validation (unless trusted),
+// the merged order by (pi, kind) (*order: merged position -> input index),
+// and the solver's records
+int prepare_general(rl_ctx *h, int64_t n, const double *dir, const double *len, double len0, int64_t nc,
+                    const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
+                    const uint8_t *kind, const double *cmp, const double *gamma, bool trusted, SolveArgs *out,
+                    const int **order);
+hipError_t launch_scatter_gamma(hipStream_t st, const SolveArgs &a, const int *order, double *gamma);
+hipError_t launch_unc(hipStream_t st, int64_t n, const double *dir, const double *len, double len0, double diam,
+                      double eta, const double *F, double *Unc);
+hipError_t launch_links(hipStream_t st, int64_t nl, int64_t n, const double *x, const double *dir, const int *inv,
+                        const rl_links *lk, const double box[3], double dt, const double *Unc, int32_t *pi,
+                        int32_t *pj, double *len, double *e, double *arm, double *q, double *cmp, uint8_t *flags,
+                        int *err);
 int solve_batched_impl(rl_ctx *h, int S, const int64_t *rod_off, const int64_t *pair_off, SolveArgs &a,
                        const int32_t *pi, const int32_t *pj, const double *e, const double *arm, const double *q,
                        const double *gamma_in, const double *F, double *gamma_out, double *U, rl_solve_info *infos);

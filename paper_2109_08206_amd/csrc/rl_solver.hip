@@ -163,7 +163,7 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
 // (pptr, qptr, st, stq, geo, qgeo, grid size, n: 14 dwords, what the
 // hardware can preload into registers besides the argument block's address),
 // so that the first loads do not wait for the argument block.
-template <int MODE, bool UNI>
+template <int MODE, bool UNI, bool BIL>
 __global__ void __launch_bounds__(kRodLoopBlock)
     k_rod(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const double2 *st, const double2 *stq,
           const double *__restrict__ geo, const double *__restrict__ qgeo, unsigned nblk, int n, SolveArgs a,
@@ -179,6 +179,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     // flag: load them first (after the stop they are read for nothing)
     RodLoads L;
     rod_load(pptr, qptr, st, stq, geo, qgeo, r, active, sub, L);
+    if (BIL) rod_load_split(a, r, active, L);
     // so are the previous iteration's partials (read for nothing at k = 0)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
@@ -219,7 +220,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
         }
     }
     double f[3], m[3];
-    rod_accumulate<MODE>(a, L, alpha, f, m);
+    rod_accumulate<MODE, BIL>(a, L, alpha, f, m);
     if (!active) return;
     // translation a_perp f + (a_par - a_perp)(d.f) d; rotation Omega =
     // r_perp dir x m (normal to the axis) and Omega x dir = r_perp (m - (d.m) d)
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
 // As in k_rod, what the first loads need leads the argument list (qpos, u_P,
 // q, st, u_Q, constraint count, grid size, step lengths: 14 dwords).  CB
 // threads per workgroup take CPL constraints each per round.
-template <int MODE, int CB, int CPL>
+template <int MODE, int CB, int CPL, bool BIL>
 __global__ void __launch_bounds__(CB)
     k_con(const int32_t *__restrict__ qpos, const double *__restrict__ uP, const double *__restrict__ qv,
           const double2 *st, const double *__restrict__ uQ, int nc, unsigned nblk, const double *alpha_buf,
@@ -257,19 +258,28 @@ __global__ void __launch_bounds__(CB)
     ConLoadsU L[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u)
-        if (c0 + u * CB < hi) con_load_u<MODE>(in, c0 + u * CB, L[u]);
+        if (c0 + u * CB < hi) {
+            if (BIL) con_load_gen(in, a.cmpv, c0 + u * CB, L[u]);
+            else con_load_u<MODE>(in, c0 + u * CB, L[u]);
+        }
     // the step length too (read for nothing after the stop)
     const double alpha = MODE == kModeLoop ? alpha_buf[k & 1] : 0.0;
     if (MODE != kModeApply && a.state->done) return;
     for (;;) {
 #pragma unroll
         for (int u = 0; u < CPL; ++u)
-            if (c0 + u * CB < hi) con_update_u<MODE>(a, c0 + u * CB, L[u], alpha, p);
+            if (c0 + u * CB < hi) {
+                if (BIL) con_update_gen<MODE>(a, c0 + u * CB, L[u], alpha, p);
+                else con_update_u<MODE>(a, c0 + u * CB, L[u], alpha, p);
+            }
         c0 += step;
         if (c0 >= hi) break;
 #pragma unroll
         for (int u = 0; u < CPL; ++u)
-            if (c0 + u * CB < hi) con_load_u<MODE>(in, c0 + u * CB, L[u]);
+            if (c0 + u * CB < hi) {
+                if (BIL) con_load_gen(in, a.cmpv, c0 + u * CB, L[u]);
+                else con_load_u<MODE>(in, c0 + u * CB, L[u]);
+            }
     }
     if (MODE == kModeApply) return;
     block_reduce4_all<CB / 64>(p, lds);
@@ -553,17 +563,24 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
 // rod kernel grid: a multiple of 8 so that each XCD gets a contiguous range of rods
 static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
 
+template <int MODE, bool BIL>
+static void launch_rod_t(hipStream_t st, const SolveArgs &a, bool uni, long long k)
+{
+    const dim3 grid(rod_grid(a.n));
+    if (uni)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL>), grid, dim3(kRodLoopBlock), 0, st,
+                           RL_ROD_HOT(a, grid), a, k);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL>), grid, dim3(kRodLoopBlock), 0, st,
+                           RL_ROD_HOT(a, grid), a, k);
+}
+
 template <int MODE>
 static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long long k)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid(rod_grid(a.n));
-    if (uni)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true>), grid, dim3(kRodLoopBlock), 0, st, RL_ROD_HOT(a, grid),
-                           a, k);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false>), grid, dim3(kRodLoopBlock), 0, st, RL_ROD_HOT(a, grid),
-                           a, k);
+    if (a.gen) launch_rod_t<MODE, true>(st, a, uni, k);
+    else launch_rod_t<MODE, false>(st, a, uni, k);
     return hipGetLastError();
 }
 
@@ -577,15 +594,22 @@ static inline bool con_wide(const SolveArgs &a)
     return per > 4 * 512;
 }
 
+template <int MODE, bool BIL>
+static void launch_con_t(hipStream_t st, const SolveArgs &a, long long k)
+{
+    if (con_wide(a))
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 256, 8, BIL>), dim3(a.gcon), dim3(256), 0, st, RL_CON_HOT(a),
+                           a, k);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 512, 4, BIL>), dim3(a.gcon), dim3(512), 0, st, RL_CON_HOT(a),
+                           a, k);
+}
+
 template <int MODE>
 static hipError_t launch_con(hipStream_t st, const SolveArgs &a, long long k)
 {
-    if (con_wide(a))
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 256, 8>), dim3(a.gcon), dim3(256), 0, st, RL_CON_HOT(a), a,
-                           k);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 512, 4>), dim3(a.gcon), dim3(512), 0, st, RL_CON_HOT(a), a,
-                           k);
+    if (a.gen) launch_con_t<MODE, true>(st, a, k);
+    else launch_con_t<MODE, false>(st, a, k);
     return hipGetLastError();
 }
 
@@ -598,34 +622,39 @@ int apply_impl(rl_ctx *h, SolveArgs &a, double *w)
     return RL_OK;
 }
 
+template <bool BIL>
+static void record_sample_t(rl_ctx *h, int v, long long it, const SolveArgs &a, bool uni)
+{
+    hipStream_t st = h->stream;
+    if (a.n > 0) {
+        const dim3 grid(rod_grid(a.n));
+        if (uni)
+            hipExtLaunchKernelGGL(k_rod<kModeLoop, true, BIL>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
+                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
+        else
+            hipExtLaunchKernelGGL(k_rod<kModeLoop, false, BIL>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
+                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
+    }
+    if (con_wide(a))
+        hipExtLaunchKernelGGL(k_con<kModeLoop, 256, 8, BIL>, dim3(a.gcon), dim3(256), 0, st, h->ev[v][2],
+                              h->ev[v][3], 0, RL_CON_HOT(a), a, (long long)it);
+    else
+        hipExtLaunchKernelGGL(k_con<kModeLoop, 512, 4, BIL>, dim3(a.gcon), dim3(512), 0, st, h->ev[v][2],
+                              h->ev[v][3], 0, RL_CON_HOT(a), a, (long long)it);
+}
+
 // One loop iteration whose two kernels are launched with start/stop events
 // taken by the dispatch itself (the same span a kernel trace reports).
 static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs &a, bool uni)
 {
-    hipStream_t st = h->stream;
     for (int k = 0; k < 4; ++k)
         if (!h->ev[v][k]) {
             hipError_t e = hipEventCreateWithFlags(&h->ev[v][k], hipEventDisableSystemFence);
             if (e != hipSuccess) return e;
         }
     h->ev_iter[v] = it;
-    if (a.n > 0) {
-        const dim3 grid(rod_grid(a.n));
-        if (uni)
-            hipExtLaunchKernelGGL(k_rod<kModeLoop, true>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
-                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
-        else
-            hipExtLaunchKernelGGL(k_rod<kModeLoop, false>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
-                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (con_wide(a))
-        hipExtLaunchKernelGGL(k_con<kModeLoop, 256, 8>, dim3(a.gcon), dim3(256), 0, st, h->ev[v][2], h->ev[v][3], 0,
-                              RL_CON_HOT(a), a, (long long)it);
-    else
-        hipExtLaunchKernelGGL(k_con<kModeLoop, 512, 4>, dim3(a.gcon), dim3(512), 0, st, h->ev[v][2], h->ev[v][3], 0,
-                              RL_CON_HOT(a), a, (long long)it);
+    if (a.gen) record_sample_t<true>(h, v, it, a, uni);
+    else record_sample_t<false>(h, v, it, a, uni);
     return hipGetLastError();
 }
 
