@@ -223,6 +223,42 @@ int rl_solve_general(rl_handle h, int64_t n, const double *dir, const double *le
                      const uint8_t *kind, const double *cmp, const double *F, double *gamma, double *U,
                      rl_solve_info *info);
 
+/* Walls: confinement by fixed bodies (Appendix "Equation of motion with
+ * geometric constraints", last paragraph: a flat substrate or a spherical
+ * shell; only the rod's side enters D).
+ *   RL_WALL_PLANE        the allowed side is a.(x - p) >= 0 (a: unit normal)
+ *   RL_WALL_SPHERE_IN    inside the sphere |x - p| <= r
+ *   RL_WALL_CYLINDER_IN  inside the cylinder of axis p + t a (a unit), radius r
+ * Each region is convex, so a rod's axis stays inside exactly when both of
+ * its ends do.  For each rod, end s = -L/2 then +L/2, and each wall in order,
+ * the end's gap phi = (its distance to the wall) - diam/2; an end with
+ * phi < cutoff gives a unilateral constraint against the wall: e is the
+ * wall's unit normal at its nearest point, pointing into the allowed region,
+ * the lever arm is s, q = phi/h + D^T M F.  Walls are host structs, at most
+ * RL_MAX_WALLS per call; the caller keeps the confinement inside the
+ * periodic box (the centres are used as given). */
+#define RL_WALL_PLANE 0
+#define RL_WALL_SPHERE_IN 1
+#define RL_WALL_CYLINDER_IN 2
+#define RL_MAX_WALLS 8
+typedef struct {
+    int32_t kind;
+    double p[3];   /* a point of the plane / the centre / a point of the axis */
+    double a[3];   /* unit normal (plane) or unit axis (cylinder) */
+    double r;      /* radius (sphere, cylinder) */
+} rl_wall;
+
+/* Wall contacts in that order: rod[m] (int32), e[m][3], arm[m][2] = (s, 0),
+ * phi[m], q[m] (F may be NULL), flags[m] (may be NULL; bit 0: |phi - cutoff|
+ * <= 1e-9), each of length capacity; *n_contacts (host) gets the count.  If
+ * it exceeds capacity nothing is written and RL_ERR_CAPACITY is returned.
+ * For rl_solve_general they are kind 0 with pj = -1.  RL_ERR_ARG on a bad
+ * wall (unknown kind, zero normal or axis, radius <= 0, more than
+ * RL_MAX_WALLS).  Synchronises. */
+int rl_assemble_walls(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                      const double *F, int32_t n_walls, const rl_wall *walls, int64_t capacity, int32_t *rod,
+                      double *e, double *arm, double *phi, double *q, uint8_t *flags, int64_t *n_contacts);
+
 /* rl_solve_lcp without allocation, for callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, harnesses that
  * forbid allocation): the same problem, kernels and result as rl_solve_lcp
@@ -270,12 +306,27 @@ int rl_solve_lcp_noalloc(rl_handle h, int64_t n, const double *dir, const double
 #define RL_TAPE_NONE 0
 #define RL_TAPE_RECORD 1
 #define RL_TAPE_REPLAY 2
-/* Optional parts of a step (extra may be NULL: none of them).
+/* Optional parts of a step (extra may be NULL: none of them; NULL or 0
+ * fields are absent).
  *   x_unwrapped[n][3]  device, in/out: the centres without periodic
  *                      wrapping; the step adds h U_t to them (the same
- *                      increment as x, eq. constrainedeom_euler, first line). */
+ *                      increment as x, eq. constrainedeom_euler, first line).
+ *   links              bilateral links (rl_links, rod indices in the caller's
+ *                      numbering) solved together with the contacts
+ *                      (eq. linearconstraints a and b).
+ *   gamma_links        [n_links] device out: the links' forces (pN; > 0 pushes
+ *                      the ends apart).
+ *   n_walls, walls     host walls (rl_wall) confining the rods.
+ *   n_wall_contacts    host out: the step's wall constraints.
+ * With links or walls the step solves the general problem (RL_FP64 only, no
+ * gamma tape). */
 typedef struct {
     double *x_unwrapped;
+    const rl_links *links;
+    double *gamma_links;
+    int32_t n_walls;
+    const rl_wall *walls;
+    int64_t *n_wall_contacts;
 } rl_step_extra;
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
             double *U, rl_solve_info *info, int64_t *n_pairs, double *gamma_tape, int64_t tape_len,

@@ -73,6 +73,8 @@ def _load():
             lib.ora_bbpgd_gen.restype = C.c_int
             lib.ora_apply_Mc_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, P, P]
             lib.ora_links.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P, P, P, P, P]
+            lib.ora_walls.argtypes = [I64, P, P, P, D, D, D, D, D, I64, P, P, I64, P, P, P, P, P]
+            lib.ora_walls.restype = I64
             _lib = lib
     return _lib
 
@@ -420,3 +422,54 @@ def velocity_gen(dir_, length, diam, eta, gc: General, gamma, F) -> np.ndarray:
     _load().ora_velocity(n, _p(d), _p(la), l0, diam, eta, gc.n, _p(gc.pi), _p(gc.pj), _p(gc.e), _p(gc.arm),
                          _p(_f64(gamma)), _p(_f64(F)), _p(U))
     return U
+
+
+# --- walls ---------------------------------------------------------------------
+
+WALL_PLANE, WALL_SPHERE_IN, WALL_CYLINDER_IN = 0, 1, 2
+
+
+def wall(kind: int, p, a=(0.0, 0.0, 1.0), r: float = 0.0) -> np.ndarray:
+    """One wall as 8 doubles {kind, p[3], a[3], r}."""
+    return np.array([float(kind), *map(float, p), *map(float, a), float(r)])
+
+
+@dataclass
+class WallContacts:
+    rod: np.ndarray    # [m] int32
+    e: np.ndarray      # [m, 3] unit normal into the allowed region
+    arm: np.ndarray    # [m, 2] (s, 0)
+    phi: np.ndarray    # [m]
+    q: np.ndarray      # [m]
+
+    @property
+    def n(self) -> int:
+        return int(self.rod.shape[0])
+
+
+def walls(x, dir_, length, diam, eta, dt, cutoff, wall_list, F=None) -> WallContacts:
+    xa, d = _f64(x), _f64(dir_)
+    n = xa.shape[0]
+    la, l0 = _len_args(length, n)
+    W = _f64(np.asarray(wall_list, dtype=np.float64).reshape(-1, 8))
+    nw = W.shape[0]
+    Fa = None if F is None else _f64(F)
+    cap = 2 * n * max(nw, 1) + 1
+    rod = np.empty(cap, np.int32)
+    e, arm, phi, q = np.empty((cap, 3)), np.empty((cap, 2)), np.empty(cap), np.empty(cap)
+    m = _load().ora_walls(n, _p(xa), _p(d), _p(la), l0, diam, eta, dt, cutoff, nw, _p(W), _p(Fa), cap, _p(rod),
+                          _p(e), _p(arm), _p(phi), _p(q))
+    return WallContacts(rod[:m].copy(), e[:m].copy(), arm[:m].copy(), phi[:m].copy(), q[:m].copy())
+
+
+def general_all(pr=None, cs=None, lk=None, lg=None, wc: Optional[WallContacts] = None) -> General:
+    """Contacts, then links, then wall contacts (kind 0, no Q side)."""
+    g = general(pr, cs, lk, lg)
+    if wc is None or wc.n == 0:
+        return g
+    m = wc.n
+    return General(_i32(np.concatenate([g.pi, wc.rod])), _i32(np.concatenate([g.pj, -np.ones(m, np.int32)])),
+                   _f64(np.concatenate([g.e, wc.e])), _f64(np.concatenate([g.arm, wc.arm])),
+                   _f64(np.concatenate([g.q, wc.q])),
+                   np.ascontiguousarray(np.concatenate([g.kind, np.zeros(m, np.uint8)]), dtype=np.uint8),
+                   _f64(np.concatenate([g.cmp, np.zeros(m)])))

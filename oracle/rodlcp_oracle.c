@@ -876,6 +876,86 @@ void ora_links(int64_t n, const double *x, const double *dir, const double *len,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Walls (confinement): constraints between a rod and a fixed body, with    */
+/* only the rod's side in D (Appendix "Equation of motion with geometric    */
+/* constraints", last paragraph: a flat substrate or a spherical shell).    */
+/* Wall kinds, as 8 doubles {kind, p[3], a[3], r}:                          */
+/*   0 plane: the allowed side is a.x >= a.p (a unit normal, pointing in);  */
+/*   1 sphere, rods inside: |x - p| <= r;                                   */
+/*   2 cylinder, rods inside: |(x - p) - ((x - p).a) a| <= r (a unit axis). */
+/* Each region is convex, so a rod's axis stays inside exactly when both of */
+/* its end points do: each end is a candidate contact point.  For end       */
+/* s = -L/2 and +L/2 (in that order) of each rod, and each wall in order,   */
+/* the gap phi = (distance from the end point to the wall) - diam/2; ends   */
+/* with phi < cutoff become unilateral constraints with e the unit normal   */
+/* of the wall at its nearest point, pointing into the allowed region, the  */
+/* lever arm s, and q = phi/h + D^T M F as for a contact (eq. blockdef,     */
+/* block A).  Returns the count (lists written only up to cap).             */
+/* ------------------------------------------------------------------------ */
+static int wall_gap(const double *w, const double *pt, double diam, double *phi, double *e)
+{
+    const int kind = (int)w[0];
+    const double *p0 = w + 1, *a = w + 4, r = w[7];
+    if (kind == 0) {
+        double d = 0.0;
+        for (int k = 0; k < 3; ++k) d += a[k] * (pt[k] - p0[k]);
+        *phi = d - 0.5 * diam;
+        for (int k = 0; k < 3; ++k) e[k] = a[k];
+        return 0;
+    }
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = pt[k] - p0[k];
+    if (kind == 2) {
+        const double va = dot3(v, a);
+        for (int k = 0; k < 3; ++k) v[k] -= va * a[k];
+    }
+    const double dist = sqrt(dot3(v, v));
+    *phi = r - dist - 0.5 * diam;
+    if (dist > 0.0)
+        for (int k = 0; k < 3; ++k) e[k] = -v[k] / dist;
+    else
+        for (int k = 0; k < 3; ++k) e[k] = 0.0; /* at the centre: far from the wall */
+    return 0;
+}
+
+int64_t ora_walls(int64_t n, const double *x, const double *dir, const double *len, double len0, double diam,
+                  double eta, double dt, double cutoff, int64_t nw, const double *walls, const double *F, int64_t cap,
+                  int32_t *rod, double *e, double *arm, double *phi, double *q)
+{
+    double *Unc = (double *)calloc((size_t)(6 * (n > 0 ? n : 1)), sizeof(double));
+    if (F) ora_apply_mobility(n, dir, len, len0, diam, eta, F, Unc);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double L = rod_len(len, len0, i);
+        for (int end = 0; end < 2; ++end) {
+            const double s = end == 0 ? -0.5 * L : 0.5 * L;
+            double pt[3];
+            for (int k = 0; k < 3; ++k) pt[k] = x[3 * i + k] + s * dir[3 * i + k];
+            for (int64_t w = 0; w < nw; ++w) {
+                double ph, ee[3];
+                wall_gap(walls + 8 * w, pt, diam, &ph, ee);
+                if (!(ph < cutoff)) continue;
+                if (m < cap) {
+                    double col[12];
+                    d_column(dir, (int32_t)i, -1, ee, s, 0.0, col);
+                    double dtu = 0.0;
+                    for (int k = 0; k < 6; ++k) dtu += col[k] * Unc[6 * i + k];
+                    rod[m] = (int32_t)i;
+                    for (int k = 0; k < 3; ++k) e[3 * m + k] = ee[k];
+                    arm[2 * m] = s;
+                    arm[2 * m + 1] = 0.0;
+                    phi[m] = ph;
+                    q[m] = ph / dt + dtu;
+                }
+                ++m;
+            }
+        }
+    }
+    free(Unc);
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time integration.  Linearised implicit Euler on the configuration:       */
 /* C^{k+1} = C^k + h G U (eq. constrainedeom_euler, first line), i.e.       */
 /* x += h U_t and theta += h Psi(theta) Omega, then theta is renormalised   */

@@ -50,8 +50,27 @@ class RLLinks(C.Structure):
                 ("kappa", C.c_void_p), ("rest", C.c_void_p), ("anchor", C.c_void_p)]
 
 
+class RLWall(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("p", C.c_double * 3), ("a", C.c_double * 3), ("r", C.c_double)]
+
+
+WALL_PLANE, WALL_SPHERE_IN, WALL_CYLINDER_IN = 0, 1, 2
+
+
+def walls_array(walls):
+    """[(kind, p, a, r), ...] as an rl_wall array (host)."""
+    arr = (RLWall * max(len(walls), 1))()
+    for k, (kind, pt, ax, r) in enumerate(walls):
+        arr[k].kind = int(kind)
+        arr[k].p[:] = [float(v) for v in pt]
+        arr[k].a[:] = [float(v) for v in ax]
+        arr[k].r = float(r)
+    return arr
+
+
 class StepExtra(C.Structure):
-    _fields_ = [("x_unwrapped", C.c_void_p)]
+    _fields_ = [("x_unwrapped", C.c_void_p), ("links", C.c_void_p), ("gamma_links", C.c_void_p),
+                ("n_walls", C.c_int32), ("walls", C.c_void_p), ("n_wall_contacts", C.c_void_p)]
 
 
 class AdjointInfo(C.Structure):
@@ -64,7 +83,7 @@ SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
            "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_solve_lcp_noalloc",
-           "rl_assemble_links", "rl_solve_general")
+           "rl_assemble_links", "rl_solve_general", "rl_assemble_walls")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -98,6 +117,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_assemble_links": ([H, I64, P, P, P, D, C.POINTER(RLLinks), P, P, P, P, P, P], C.c_int),
             "rl_solve_general": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, P, P, C.POINTER(SolveInfo)],
                                  C.c_int),
+            "rl_assemble_walls": ([H, I64, P, P, P, D, P, I32, P, I64, P, P, P, P, P, P, C.POINTER(C.c_int64)],
+                                  C.c_int),
             "rl_step": ([H, I64, P, P, P, D, P, P, C.POINTER(SolveInfo), C.POINTER(C.c_int64), P, I64, I32,
                          C.POINTER(StepExtra)], C.c_int),
             "rl_profile_enable": ([H, C.c_int], C.c_int),
@@ -367,6 +388,29 @@ class Solver:
                                                _ptr(cmp), _ptr(fl)), "rl_assemble_links")
         return L, e, qq, cmp, fl[:nl]
 
+    def assemble_walls(self, x, dir_, length, walls, F=None, capacity=None):
+        """Wall constraints of the rods: returns (rod, e, arm, phi, q, flags)."""
+        torch = _torch()
+        n = x.shape[0]
+        la, l0 = _len_args(length, n)
+        cap = int(capacity) if capacity is not None else 2 * n * max(len(walls), 1)
+        dev = x.device
+        rod = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        e = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=dev)
+        arm = torch.empty((max(cap, 1), 2), dtype=torch.float64, device=dev)
+        phi = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        q = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        fl = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        wl = walls_array(walls)
+        cnt = C.c_int64(0)
+        self._stream()
+        self._check(self.lib.rl_assemble_walls(
+            self._h, n, _ptr(x, torch.float64, (n, 3), "x"), _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0,
+            _ptr(F, torch.float64, (n, 6), "F"), len(walls), C.cast(wl, C.c_void_p), cap, _ptr(rod), _ptr(e),
+            _ptr(arm), _ptr(phi), _ptr(q), _ptr(fl), C.byref(cnt)), "rl_assemble_walls")
+        m = int(cnt.value)
+        return rod[:m], e[:m], arm[:m], phi[:m], q[:m], fl[:m]
+
     def solve_general(self, dir_, length, pi, pj, e, arm, q, kind, cmp, F=None, gamma=None, U=None):
         """Mixed unilateral/bilateral problem over a general list (any order;
         pj = -1 for a fixed body).  Returns (gamma, U, SolveResult)."""
@@ -420,11 +464,16 @@ class Solver:
         self._check(self.lib.rl_batch_tuning(self._h, int(rod_block), int(con_block), out), "rl_batch_tuning")
         return int(out[0]), int(out[1])
 
-    def step(self, x, quat, length, F=None, U=None, tape=None, tape_mode=TAPE_NONE, x_unwrapped=None):
+    def step(self, x, quat, length, F=None, U=None, tape=None, tape_mode=TAPE_NONE, x_unwrapped=None,
+             links=None, gamma_links=None, walls=None):
         """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs).
         tape: float64 device tensor for the step's constraint forces
         (TAPE_RECORD writes them, TAPE_REPLAY starts from them).
-        x_unwrapped: [n, 3] centres without wrapping, advanced in place."""
+        x_unwrapped: [n, 3] centres without wrapping, advanced in place.
+        links: (p, q, arm, kappa, rest, anchor) device tensors (anchor may be
+        None), solved with the contacts; gamma_links receives their forces.
+        walls: [(kind, p, a, r), ...].  The step's wall constraint count is
+        left in self.last_wall_contacts."""
         torch = _torch()
         n = x.shape[0]
         la, l0 = _len_args(length, n)
@@ -432,13 +481,22 @@ class Solver:
         info = SolveInfo()
         npairs = C.c_int64(0)
         tlen = 0 if tape is None else int(tape.shape[0])
-        extra = StepExtra(_ptr(x_unwrapped, torch.float64, (n, 3), "x_unwrapped"))
+        lk = self.links_struct(*links) if links is not None else None
+        wl = walls_array(walls) if walls else None
+        nwc = C.c_int64(0)
+        nl = 0 if links is None else int(links[0].shape[0])
+        extra = StepExtra(_ptr(x_unwrapped, torch.float64, (n, 3), "x_unwrapped"),
+                          C.cast(C.pointer(lk), C.c_void_p) if lk is not None else None,
+                          _ptr(gamma_links, torch.float64, (nl,), "gamma_links"), len(walls) if walls else 0,
+                          C.cast(wl, C.c_void_p) if wl is not None else None,
+                          C.cast(C.pointer(nwc), C.c_void_p))
         self._stream()
         rc = self.lib.rl_step(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
                               _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
                               _ptr(F, torch.float64, (n, 6), "F"), _ptr(U, torch.float64, (n, 6), "U"),
                               C.byref(info), C.byref(npairs), _ptr(tape, torch.float64, None, "tape"), tlen,
                               int(tape_mode), C.byref(extra))
+        self.last_wall_contacts = int(nwc.value)
         if rc == ERR_CAPACITY and tape_mode == TAPE_RECORD:
             err = RodLCPError(rc, "rl_step", f"tape too short for {int(npairs.value)} constraints")
             err.count = int(npairs.value)

@@ -143,6 +143,139 @@ static int check_params(const rl_params *p)
     return RL_OK;
 }
 
+__global__ void k_invert_perm(int64_t n, const int *__restrict__ perm, int *__restrict__ inv)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < n) inv[perm[t]] = (int)t;
+}
+
+// the links' forces in the caller's link order: merged constraint m is input
+// constraint ord[m]; links are inputs [np, np + nl)
+__global__ void k_link_gamma(int64_t nc, const double2 *__restrict__ st, const int *__restrict__ ord, int64_t np,
+                             int64_t nl, double *__restrict__ out)
+{
+    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m >= nc) return;
+    const int64_t c = ord[m];
+    if (c >= np && c < np + nl) out[c - np] = st[m].x;
+}
+
+// One step with links and/or walls: the contacts, the links and the wall
+// constraints of the rods in cell order, concatenated in that order, solved
+// as one general problem.
+static int step_general(rl_ctx *h, int64_t n, double *x, double *quat, const double *len, double len0,
+                        const double *F, double *U, rl_solve_info *info, int64_t *n_pairs, const rl_step_extra *ex)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    if (p.precision != RL_FP64) {
+        set_error("rl_step: links and walls need RL_FP64");
+        return RL_ERR_ARG;
+    }
+    WallSet W;
+    int rc = wall_set(ex->n_walls, ex->walls, &W);
+    if (rc) return rc;
+    const rl_links *lk = ex->links;
+    const int64_t nl = lk ? lk->n_links : 0;
+    if (nl < 0 || nl >= 0x7fffffff || (nl > 0 && (!lk->p || !lk->q || !lk->arm || !lk->kappa || !lk->rest))) {
+        set_error("rl_step: bad links");
+        return RL_ERR_ARG;
+    }
+    int err = 0;
+    double *dir = (double *)ws_get(h, kWsDir, sizeof(double) * 3 * n, &err);
+    if (err) return err;
+    RL_HIP(launch_directors(st, n, quat, dir));
+    int64_t np = 0;
+    const int *perm = nullptr;
+    const double *xs = nullptr, *ds = nullptr, *ls = nullptr;
+    rc = build_pairs_sorted(h, n, x, dir, len, len0, &np, &perm, &xs, &ds, &ls);
+    if (rc) return rc;
+    if (n_pairs) *n_pairs = np;
+    const double *lsv = len ? ls : nullptr;
+    double *Fs = F ? (double *)ws_get(h, kWsFs, sizeof(double) * 6 * n, &err) : nullptr;
+    double *Unc = (double *)ws_get(h, kWsStepUnc, sizeof(double) * 6 * n, &err);
+    int *inv = (int *)ws_get(h, kWsInvPerm, sizeof(int) * n, &err);
+    double *Uw = U ? U : (double *)ws_get(h, kWsStepU, sizeof(double) * 6 * n, &err);
+    if (err) return err;
+    if (F) {
+        RL_HIP(launch_gather6(st, n, perm, F, Fs));
+        RL_HIP(launch_unc(st, n, ds, lsv, len0, p.diam, p.eta, Fs, Unc));
+    } else {
+        RL_HIP(hipMemsetAsync(Unc, 0, sizeof(double) * 6 * n, st));
+    }
+    // wall contacts: count first (sizes the concatenated list)
+    int64_t nw = 0;
+    rc = walls_impl(h, n, xs, ds, lsv, len0, Unc, W, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &nw);
+    if (rc && rc != RL_ERR_CAPACITY) return rc;
+    if (ex->n_wall_contacts) *ex->n_wall_contacts = nw;
+    const int64_t nc = np + nl + nw;
+    if (nc >= 0x7fffffff) {
+        set_error("rl_step: too many constraints");
+        return RL_ERR_CAPACITY;
+    }
+    const int64_t nb = nc > 0 ? nc : 1;
+    int32_t *cpi = (int32_t *)ws_get(h, kWsCatPi, sizeof(int32_t) * nb, &err);
+    int32_t *cpj = (int32_t *)ws_get(h, kWsCatPj, sizeof(int32_t) * nb, &err);
+    double *ce = (double *)ws_get(h, kWsCatE, sizeof(double) * 3 * nb, &err);
+    double *carm = (double *)ws_get(h, kWsCatArm, sizeof(double) * 2 * nb, &err);
+    double *cq = (double *)ws_get(h, kWsCatQ, sizeof(double) * nb, &err);
+    uint8_t *ckind = (uint8_t *)ws_get(h, kWsCatKind, (size_t)nb, &err);
+    double *ccmp = (double *)ws_get(h, kWsCatCmp, sizeof(double) * nb, &err);
+    double *cgam = (double *)ws_get(h, kWsStepGamma, sizeof(double) * nb, &err);
+    double *phi = (double *)ws_get(h, kWsStepPhi, sizeof(double) * (np > 0 ? np : 1), &err);
+    double *llen = (double *)ws_get(h, kWsLinkLen, sizeof(double) * (nl > 0 ? nl : 1), &err);
+    if (err) return err;
+    if (np > 0) {
+        RL_HIP(hipMemcpyAsync(cpi, h->buf[kWsStepPi], sizeof(int32_t) * np, hipMemcpyDeviceToDevice, st));
+        RL_HIP(hipMemcpyAsync(cpj, h->buf[kWsStepPj], sizeof(int32_t) * np, hipMemcpyDeviceToDevice, st));
+        rc = assemble_impl(h, n, xs, ds, lsv, len0, np, (const int32_t *)h->buf[kWsStepPi],
+                           (const int32_t *)h->buf[kWsStepPj], (const int32_t *)h->buf[kWsStepImg], Fs, phi, ce, carm,
+                           cq);
+        if (rc) return rc;
+        RL_HIP(hipMemsetAsync(ckind, 0, (size_t)np, st));
+    }
+    if (nl > 0) {
+        hipLaunchKernelGGL(k_invert_perm, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n, perm,
+                           inv);
+        RL_HIP(hipGetLastError());
+        RL_HIP(hipMemsetAsync(h->flag_dev, 0, sizeof(int), st));
+        RL_HIP(launch_links(st, nl, n, xs, ds, inv, lk, p.box, p.dt, Unc, cpi + np, cpj + np, llen, ce + 3 * np,
+                            carm + 2 * np, cq + np, ccmp + np, nullptr, h->flag_dev));
+        RL_HIP(hipMemcpyAsync(h->host_scratch, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipStreamSynchronize(st));
+        if (((int *)h->host_scratch)[0]) {
+            set_error("rl_step: a link has a rod index outside [0, n), p == q, kappa <= 0, a bad rest length or no "
+                      "anchor");
+            return RL_ERR_ARG;
+        }
+        RL_HIP(hipMemsetAsync(ckind + np, 1, (size_t)nl, st));
+    }
+    if (nw > 0) {
+        int64_t nw2 = 0;
+        rc = walls_impl(h, n, xs, ds, lsv, len0, Unc, W, nw, cpi + np + nl, ce + 3 * (np + nl), carm + 2 * (np + nl),
+                        nullptr, cq + np + nl, nullptr, &nw2);
+        if (rc) return rc;
+        RL_HIP(hipMemsetAsync(cpj + np + nl, 0xff, sizeof(int32_t) * nw, st));  // -1: no Q side
+        RL_HIP(hipMemsetAsync(ckind + np + nl, 0, (size_t)nw, st));
+    }
+    RL_HIP(hipMemsetAsync(cgam, 0, sizeof(double) * nb, st));
+    SolveArgs a;
+    const int *ord = nullptr;
+    rc = prepare_general(h, n, ds, lsv, len0, nc, cpi, cpj, ce, carm, cq, ckind, ccmp, cgam, true, &a, &ord);
+    if (rc) return rc;
+    rc = solve_impl(h, a, F, Uw, nullptr, info, perm);
+    if (rc < 0) return rc;
+    if (ex->gamma_links && nl > 0 && nc > 0) {
+        hipLaunchKernelGGL(k_link_gamma, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nc,
+                           (const double2 *)a.st, ord, np, nl, ex->gamma_links);
+        RL_HIP(hipGetLastError());
+    }
+    const int rc2 = integrate_impl(h, n, Uw, x, quat, ex->x_unwrapped);
+    if (rc2) return rc2;
+    RL_HIP(hipStreamSynchronize(st));
+    return rc;
+}
+
 }  // namespace rl
 
 using namespace rl;
@@ -399,8 +532,14 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     if (n == 0) {
         if (n_pairs) *n_pairs = 0;
         if (info) *info = rl_solve_info{0, 0.0, 0.0, RL_OK, 0};
+        if (extra && extra->n_wall_contacts) *extra->n_wall_contacts = 0;
         return RL_OK;
     }
+    if (extra && ((extra->links && extra->links->n_links > 0) || extra->n_walls > 0)) {
+        RL_REQUIRE(tape_mode == RL_TAPE_NONE, "rl_step: no gamma tape with links or walls");
+        return step_general(h, n, x, quat, len, len0, F, U, info, n_pairs, extra);
+    }
+    if (extra && extra->n_wall_contacts) *extra->n_wall_contacts = 0;
     int err = 0;
     double *dir = (double *)ws_get(h, kWsDir, sizeof(double) * 3 * n, &err);
     if (err) return err;

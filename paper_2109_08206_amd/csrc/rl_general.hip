@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "rl_device.hpp"
 
@@ -317,11 +318,70 @@ int prepare_general(rl_ctx *h, int64_t n, const double *dir, const double *len, 
     return RL_OK;
 }
 
+int wall_set(int n_walls, const rl_wall *walls, WallSet *W)
+{
+    *W = WallSet{};
+    if (n_walls < 0 || n_walls > RL_MAX_WALLS || (n_walls > 0 && !walls)) {
+        set_error("walls: need 0 <= n_walls <= %d and a wall array", RL_MAX_WALLS);
+        return RL_ERR_ARG;
+    }
+    W->n = n_walls;
+    for (int w = 0; w < n_walls; ++w) {
+        const rl_wall &src = walls[w];
+        const double an = sqrt(src.a[0] * src.a[0] + src.a[1] * src.a[1] + src.a[2] * src.a[2]);
+        const bool needs_a = src.kind == RL_WALL_PLANE || src.kind == RL_WALL_CYLINDER_IN;
+        const bool needs_r = src.kind == RL_WALL_SPHERE_IN || src.kind == RL_WALL_CYLINDER_IN;
+        if (src.kind < RL_WALL_PLANE || src.kind > RL_WALL_CYLINDER_IN || (needs_a && !(fabs(an - 1.0) < 1e-12)) ||
+            (needs_r && !(src.r > 0.0)) || !std::isfinite(src.p[0] + src.p[1] + src.p[2])) {
+            set_error("walls: wall %d has an unknown kind, a normal or axis that is not a unit vector, or a "
+                      "radius <= 0", w);
+            return RL_ERR_ARG;
+        }
+        W->kind[w] = src.kind;
+        W->r[w] = src.r;
+        for (int k = 0; k < 3; ++k) {
+            W->p[w][k] = src.p[k];
+            W->a[w][k] = src.a[k];
+        }
+    }
+    return RL_OK;
+}
+
 }  // namespace rl
 
 using namespace rl;
 
 extern "C" {
+
+int rl_assemble_walls(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                      const double *F, int32_t n_walls, const rl_wall *walls, int64_t capacity, int32_t *rod,
+                      double *e, double *arm, double *phi, double *q, uint8_t *flags, int64_t *n_contacts)
+{
+    if (!h) {
+        set_error("handle is NULL");
+        return RL_ERR_ARG;
+    }
+    RL_HIP(hipSetDevice(h->device));
+    if (n < 0 || n >= 0x7fffffff || capacity < 0 || (n > 0 && (!x || !dir)) || (!len && !(len0 > 0.0)) ||
+        (capacity > 0 && (!rod || !e || !arm || !phi || !q))) {
+        set_error("rl_assemble_walls: bad sizes or NULL array");
+        return RL_ERR_ARG;
+    }
+    WallSet W;
+    int rc = wall_set(n_walls, walls, &W);
+    if (rc) return rc;
+    int werr = 0;
+    double *Unc = (double *)ws_get(h, kWsUnc, sizeof(double) * 6 * (n > 0 ? n : 1), &werr);
+    if (werr) return werr;
+    if (F) RL_HIP(launch_unc(h->stream, n, dir, len, len0, h->prm.diam, h->prm.eta, F, Unc));
+    else RL_HIP(hipMemsetAsync(Unc, 0, sizeof(double) * 6 * (n > 0 ? n : 1), h->stream));
+    int64_t m = 0;
+    rc = walls_impl(h, n, x, dir, len, len0, Unc, W, capacity, rod, e, arm, phi, q, flags, &m);
+    if (n_contacts) *n_contacts = m;
+    if (rc) return rc;
+    RL_HIP(hipStreamSynchronize(h->stream));
+    return RL_OK;
+}
 
 int rl_assemble_links(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                       const rl_links *links, const double *F, double *length, double *e, double *q, double *cmp,

@@ -925,6 +925,101 @@ hipError_t launch_links(hipStream_t st, int64_t nl, int64_t n, const double *x, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Walls (confinement): constraints between a rod and a fixed body, only the
+// rod's side in D (Appendix "Equation of motion with geometric constraints",
+// last paragraph).  The allowed regions are convex (a half-space, the inside
+// of a sphere or of a cylinder), so each end of a rod is a candidate contact
+// point: for ends s = -L/2, +L/2 and each wall in order, phi = (distance of
+// the end to the wall) - diam/2, and an end with phi < cutoff gives a
+// unilateral constraint with e the wall's inward unit normal at its nearest
+// point, lever arm s and q = phi/h + D^T M F.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wall_gap(const WallSet &W, int w, V3 pt, double diam, V3 &e)
+{
+    const int kind = W.kind[w];
+    const V3 p0 = v3(W.p[w][0], W.p[w][1], W.p[w][2]), a = v3(W.a[w][0], W.a[w][1], W.a[w][2]);
+    V3 v = pt - p0;
+    if (kind == RL_WALL_PLANE) {
+        e = a;
+        return dot(a, v) - 0.5 * diam;
+    }
+    if (kind == RL_WALL_CYLINDER_IN) v = v - dot(v, a) * a;
+    const double dist = sqrt(dot(v, v));
+    e = dist > 0.0 ? v3(-v.x / dist, -v.y / dist, -v.z / dist) : v3(0.0, 0.0, 0.0);
+    return W.r[w] - dist - 0.5 * diam;
+}
+
+// FILL = false: per-rod counts; FILL = true: the list at the rod's offset
+template <bool FILL>
+__global__ void k_walls(int64_t n, const double *__restrict__ x, const double *__restrict__ dir,
+                        const double *__restrict__ len, double len0, double diam, double cutoff, double dt, WallSet W,
+                        const double *__restrict__ Unc, int *__restrict__ cnt, const int *__restrict__ off,
+                        int32_t *__restrict__ rod, double *__restrict__ e_out, double *__restrict__ arm,
+                        double *__restrict__ phi, double *__restrict__ q, uint8_t *__restrict__ flags)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const V3 xi = load3(x + 3 * i), di = load3(dir + 3 * i);
+    const double L = len ? len[i] : len0;
+    int m = FILL ? off[i] : 0;
+    for (int end = 0; end < 2; ++end) {
+        const double s = end == 0 ? -0.5 * L : 0.5 * L;
+        const V3 pt = xi + s * di;
+        for (int w = 0; w < W.n; ++w) {
+            V3 e;
+            const double ph = wall_gap(W, w, pt, diam, e);
+            if (!(ph < cutoff)) continue;
+            if (FILL) {
+                const double rate = dot(e, load3(Unc + 6 * i)) + dot(cross(s * di, e), load3(Unc + 6 * i + 3));
+                rod[m] = (int32_t)i;
+                store3(e_out + 3 * (int64_t)m, e);
+                arm[2 * (int64_t)m] = s;
+                arm[2 * (int64_t)m + 1] = 0.0;
+                if (phi) phi[m] = ph;
+                q[m] = ph / dt + rate;
+                if (flags) flags[m] = fabs(ph - cutoff) <= kCutoffBand ? 1u : 0u;
+            }
+            ++m;
+        }
+    }
+    if (!FILL) cnt[i] = m;
+}
+
+int walls_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+               const double *Unc, const WallSet &W, int64_t capacity, int32_t *rod, double *e, double *arm,
+               double *phi, double *q, uint8_t *flags, int64_t *count)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    int werr = 0;
+    *count = 0;
+    if (n <= 0 || W.n <= 0) return RL_OK;
+    int *cnt = (int *)ws_get(h, kWsWallCnt, sizeof(int) * n, &werr);
+    int *off = (int *)ws_get(h, kWsWallOff, sizeof(int) * (n + 1), &werr);
+    int64_t *tot = (int64_t *)ws_get(h, kWsScan, sizeof(int64_t) * 2, &werr);
+    if (werr) return werr;
+    hipLaunchKernelGGL(k_walls<false>, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, len, len0, p.diam, p.cutoff,
+                       p.dt, W, Unc, cnt, (const int *)nullptr, (int32_t *)nullptr, (double *)nullptr,
+                       (double *)nullptr, (double *)nullptr, (double *)nullptr, (uint8_t *)nullptr);
+    RL_HIP(hipGetLastError());
+    int rc = device_scan(h, cnt, n, off, tot);
+    if (rc) return rc;
+    RL_HIP(hipMemcpyAsync(h->host_scratch, tot, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipStreamSynchronize(st));
+    const int64_t total = h->host_scratch[0];
+    *count = total;
+    if (total > capacity) {
+        set_error("walls: %lld contacts exceed capacity %lld", (long long)total, (long long)capacity);
+        return RL_ERR_CAPACITY;
+    }
+    if (total == 0) return RL_OK;
+    hipLaunchKernelGGL(k_walls<true>, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, len, len0, p.diam, p.cutoff,
+                       p.dt, W, Unc, cnt, (const int *)off, rod, e, arm, phi, q, flags);
+    RL_HIP(hipGetLastError());
+    return RL_OK;
+}
+
 int assemble_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                   int64_t nc, const int32_t *pi, const int32_t *pj, const int32_t *img, const double *F,
                   double *phi, double *e, double *arm, double *q)

@@ -133,6 +133,13 @@ hipError_t launch_directors(hipStream_t st, int64_t n, const double *quat, doubl
 hipError_t launch_mobility_coeffs(hipStream_t st, int64_t n, const double *len, double diam, double eta,
                                   double *coef);
 
+// the walls of one call, by value in kernel arguments
+struct WallSet {
+    int n;
+    int kind[RL_MAX_WALLS];
+    double p[RL_MAX_WALLS][3], a[RL_MAX_WALLS][3], r[RL_MAX_WALLS];
+};
+
 struct PairGrid {
     int nc[3];
     double cell[3];
@@ -192,7 +199,8 @@ enum Slot : int {
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs, kWsQv, kWsUP, kWsUQ,
     kWsGenKey, kWsGenKeyOut, kWsGenOrd, kWsGenPi, kWsGenPj, kWsGenE, kWsGenArm, kWsGenQ, kWsGenCmp, kWsGenGamma,
-    kWsGenPsplit, kWsGenQsplit, kWsLinkLen, kWsLinkFlags, kWsInvPerm,
+    kWsGenPsplit, kWsGenQsplit, kWsLinkLen, kWsLinkFlags, kWsInvPerm, kWsWallCnt, kWsWallOff,
+    kWsCatPi, kWsCatPj, kWsCatE, kWsCatArm, kWsCatQ, kWsCatKind, kWsCatCmp, kWsCatLen, kWsStepUnc,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -292,6 +300,12 @@ int prepare_general(rl_ctx *h, int64_t n, const double *dir, const double *len, 
                     const uint8_t *kind, const double *cmp, const double *gamma, bool trusted, SolveArgs *out,
                     const int **order);
 hipError_t launch_scatter_gamma(hipStream_t st, const SolveArgs &a, const int *order, double *gamma);
+// wall contacts of rods (x, dir, len in one order; Unc = M F in the same)
+int walls_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+               const double *Unc, const WallSet &W, int64_t capacity, int32_t *rod, double *e, double *arm,
+               double *phi, double *q, uint8_t *flags, int64_t *count);
+// checks and copies the caller's walls
+int wall_set(int n_walls, const rl_wall *walls, WallSet *W);
 hipError_t launch_unc(hipStream_t st, int64_t n, const double *dir, const double *len, double len0, double diam,
                       double eta, const double *F, double *Unc);
 hipError_t launch_links(hipStream_t st, int64_t nl, int64_t n, const double *x, const double *dir, const int *inv,

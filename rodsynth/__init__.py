@@ -305,6 +305,48 @@ def cfg_rollout(seed: int = 0, n: int = 50_000) -> RodSystem:
                        name=f"rods{n // 1000}k_phi0.05_iso")
 
 
+def confined_system(n: int = 3200, *, seed: int = 0, radius: float = 3.0, length: float = 1.0,
+                    margin: float = 0.02, diam: float = DIAM, force_scale: float = 1.0,
+                    name: str = "") -> RodSystem:
+    """Rods of one length inside a spherical shell (the paper's confined
+    suspension: 3,200 microtubules 1 um long in a sphere of radius 3 um,
+    Fig. 1).  Centres uniform in the ball and axes isotropic, redrawn until
+    both ends lie at least `margin` + diam/2 inside the shell; the periodic
+    box is wide enough that no rod meets another's image.  Draw order from
+    PCG64(seed): rounds of (centres, axes, twists) for the rods still
+    outside, then forces."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    box = 2.0 * radius + 2.0 * length + 1.0
+    c = np.full(3, 0.5 * box)
+    x = np.empty((n, 3))
+    ax = np.empty((n, 3))
+    tw = np.empty(n)
+    todo = np.arange(n)
+    lim = radius - margin - 0.5 * diam
+    while todo.size:
+        m = todo.size
+        xc = c + radius * (rng.random((m, 3)) * 2.0 - 1.0)
+        a = rng.standard_normal((m, 3))
+        a /= np.linalg.norm(a, axis=1, keepdims=True)
+        t = rng.random(m) * 2.0 * math.pi
+        ok = (np.linalg.norm(xc + 0.5 * length * a - c, axis=1) <= lim) & \
+             (np.linalg.norm(xc - 0.5 * length * a - c, axis=1) <= lim)
+        x[todo[ok]], ax[todo[ok]], tw[todo[ok]] = xc[ok], a[ok], t[ok]
+        todo = todo[~ok]
+    quat = _tilt_twist_quaternions(ax[:, 2], np.arctan2(ax[:, 1], ax[:, 0]), tw)
+    force = rng.standard_normal((n, 6)) * force_scale
+    return RodSystem(x=np.ascontiguousarray(x), quat=np.ascontiguousarray(quat), length=np.full(n, float(length)),
+                     force=np.ascontiguousarray(force), box=float(box), diam=diam,
+                     name=name or f"rods{n}_sphere_r{radius}")
+
+
+def shell_wall(s: RodSystem, radius: float = 3.0):
+    """The spherical shell of ``confined_system`` as (kind, p, a, r) with
+    kind 1 (rods inside)."""
+    c = 0.5 * s.box
+    return (1, (c, c, c), (0.0, 0.0, 1.0), float(radius))
+
+
 def cfg_hub(seed: int = 0, crossers: int = 36) -> RodSystem:
     """One long rod (length 4, along x) crossed by ``crossers`` short rods
     (length 1, along y with small tilts) whose axes pass 0.005-0.06 um above
