@@ -75,6 +75,8 @@ def _load():
             lib.ora_links.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P, P, P, P, P]
             lib.ora_walls.argtypes = [I64, P, P, P, D, D, D, D, D, I64, P, P, I64, P, P, P, P, P]
             lib.ora_walls.restype = I64
+            lib.ora_mobility_pow_block.argtypes = [P, D, D, D, D, P]
+            lib.ora_brownian_force.argtypes = [I64, P, P, D, D, D, D, D, P, P]
             _lib = lib
     return _lib
 
@@ -473,3 +475,50 @@ def general_all(pr=None, cs=None, lk=None, lg=None, wc: Optional[WallContacts] =
                    _f64(np.concatenate([g.q, wc.q])),
                    np.ascontiguousarray(np.concatenate([g.kind, np.zeros(m, np.uint8)]), dtype=np.uint8),
                    _f64(np.concatenate([g.cmp, np.zeros(m)])))
+
+
+# --- Brownian force and stress ----------------------------------------------------
+
+KT_300K = 1.380649e-23 * 300.0 * 1e18   # pN um (Boltzmann constant x 300 K)
+
+
+def mobility_pow_block(d, L: float, diam: float, eta: float, power: float) -> np.ndarray:
+    M = np.empty(36)
+    _load().ora_mobility_pow_block(_p(_f64(d)), L, diam, eta, power, _p(M))
+    return M.reshape(6, 6)
+
+
+def brownian_force(dir_, length, diam, eta, dt, kT, xi) -> np.ndarray:
+    """F_B = sqrt(2 kT / h) M^(-1/2) xi per rod (xi: [n, 6] standard normal draws)."""
+    d = _f64(dir_)
+    n = d.shape[0]
+    la, l0 = _len_args(length, n)
+    FB = np.empty((n, 6))
+    _load().ora_brownian_force(n, _p(d), _p(la), l0, diam, eta, dt, kT, _p(_f64(xi)), _p(FB))
+    return FB
+
+
+def stress(x, dir_, length, box, pr: Pairs, cs: Constraints, gamma_pairs, lk: Optional[Links] = None,
+           lg: Optional[LinkGeometry] = None, gamma_links=None):
+    """Virial stress of the constraint forces between rods, (collision, link),
+    each 3x3: sigma = (1/V) sum_c gamma_c (x_P - x_Q') (outer) e_c over the
+    pairs (x_Q' the imaged centre) and over the links between two rods
+    (x_P - x_Q' = r - s_P d_P + s_Q d_Q with r = length e the link vector;
+    links to fixed points and walls are external), V the box volume.
+    Positive trace for repulsion; the paper's pressure is Tr(sigma) / 3."""
+    b = _box3(box)
+    V = float(np.prod(b))
+    x = _f64(x)
+    d = _f64(dir_)
+    sc = np.zeros((3, 3))
+    if pr.n:
+        shift = img_unpack(pr.img) * b
+        rc = x[pr.pi] - (x[pr.pj] + shift)
+        sc = np.einsum("c,ca,cb->ab", _f64(gamma_pairs), rc, cs.e) / V
+    sl = np.zeros((3, 3))
+    if lk is not None and lk.n:
+        two = lk.q >= 0          # links to fixed points are external, like walls
+        r = lg.length[two, None] * lg.e[two]
+        rc = r - lk.arm[two, :1] * d[lk.p[two]] + lk.arm[two, 1:2] * d[lk.q[two]]
+        sl = np.einsum("c,ca,cb->ab", _f64(gamma_links)[two], rc, lg.e[two]) / V
+    return sc, sl

@@ -876,6 +876,47 @@ void ora_links(int64_t n, const double *x, const double *dir, const double *len,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Brownian force (F_nc = Brownian + external, Appendix "Filament dynamics" */
+/* and eq. mobilitydef).  The paper does not print the noise amplitude; the */
+/* overdamped Langevin equation with the fluctuation-dissipation relation    */
+/* gives a velocity noise of covariance 2 kT M / h over one Euler step,      */
+/* i.e. U_B = sqrt(2 kT / h) M^(1/2) xi with xi ~ N(0, I_6) per rod, or as a  */
+/* force F_B = sqrt(2 kT / h) M^(-1/2) xi (so that M F_B = U_B).  M^(1/2) of */
+/* the block a_perp I + (a_par - a_perp) d d^T is sqrt(a_perp) I +           */
+/* (sqrt(a_par) - sqrt(a_perp)) d d^T (same eigenvectors); the rotational    */
+/* block is r I (axial = normal).  xi is passed in: the oracle draws        */
+/* nothing.                                                                 */
+/* ------------------------------------------------------------------------ */
+void ora_mobility_pow_block(const double *d, double L, double diam, double eta, double power, double *M6)
+{
+    double c[4];
+    ora_mobility_coeffs(L, diam, eta, c);
+    const double ap = pow(c[0], power), an = pow(c[1], power), rn = pow(c[2], power), rp = pow(c[3], power);
+    memset(M6, 0, 36 * sizeof(double));
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double ddt = d[a] * d[b];
+            M6[6 * a + b] = (a == b ? an : 0.0) + (ap - an) * ddt;
+            M6[6 * (a + 3) + (b + 3)] = (a == b ? rn : 0.0) + (rp - rn) * ddt;
+        }
+}
+
+void ora_brownian_force(int64_t n, const double *dir, const double *len, double len0, double diam, double eta,
+                        double dt, double kT, const double *xi, double *FB)
+{
+    const double amp = sqrt(2.0 * kT / dt);
+    double M6[36];
+    for (int64_t i = 0; i < n; ++i) {
+        ora_mobility_pow_block(dir + 3 * i, rod_len(len, len0, i), diam, eta, -0.5, M6);
+        for (int a = 0; a < 6; ++a) {
+            double v = 0.0;
+            for (int b = 0; b < 6; ++b) v += M6[6 * a + b] * xi[6 * i + b];
+            FB[6 * i + a] = amp * v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Walls (confinement): constraints between a rod and a fixed body, with    */
 /* only the rod's side in D (Appendix "Equation of motion with geometric    */
 /* constraints", last paragraph: a flat substrate or a spherical shell).    */
