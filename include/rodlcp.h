@@ -318,6 +318,24 @@ int rl_solve_lcp_noalloc(rl_handle h, int64_t n, const double *dir, const double
  *                      the ends apart).
  *   n_walls, walls     host walls (rl_wall) confining the rods.
  *   n_wall_contacts    host out: the step's wall constraints.
+ *   noise[n][6], kT    device N(0,1) draws (caller's rod order) and the
+ *                      thermal energy (pN um): the Brownian force
+ *                      F_B = sqrt(2 kT/h) M^(-1/2) noise joins F in F_nc
+ *                      (velocity noise of covariance 2 kT M / h over the
+ *                      step; the caller draws the numbers).
+ *   warm_start         1: start the solve from the forces of the previous
+ *                      step on this handle that also had warm_start set,
+ *                      matched by constraint (a contact by its two rods and
+ *                      periodic shift in the caller's numbering, a link by
+ *                      its index; wall contacts start at 0), and keep this
+ *                      step's forces for the next one.  The result is the
+ *                      same problem's solution; only the start differs.
+ *   stress[18]         host out: the virial of the constraint forces between
+ *                      rods, (1/V) sum_c gamma_c (x_P - x_Q') e_c^T over the
+ *                      contacts (stress[0..8], row-major) and over the links
+ *                      between two rods (stress[9..17]); V = box volume,
+ *                      pN/um^2; positive trace for repulsion (pressure =
+ *                      trace / 3).
  * With links or walls the step solves the general problem (RL_FP64 only, no
  * gamma tape). */
 typedef struct {
@@ -327,6 +345,10 @@ typedef struct {
     int32_t n_walls;
     const rl_wall *walls;
     int64_t *n_wall_contacts;
+    const double *noise;
+    double kT;
+    int32_t warm_start;
+    double *stress;
 } rl_step_extra;
 int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, double len0, const double *F,
             double *U, rl_solve_info *info, int64_t *n_pairs, double *gamma_tape, int64_t tape_len,

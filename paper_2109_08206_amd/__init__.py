@@ -70,7 +70,8 @@ def walls_array(walls):
 
 class StepExtra(C.Structure):
     _fields_ = [("x_unwrapped", C.c_void_p), ("links", C.c_void_p), ("gamma_links", C.c_void_p),
-                ("n_walls", C.c_int32), ("walls", C.c_void_p), ("n_wall_contacts", C.c_void_p)]
+                ("n_walls", C.c_int32), ("walls", C.c_void_p), ("n_wall_contacts", C.c_void_p),
+                ("noise", C.c_void_p), ("kT", C.c_double), ("warm_start", C.c_int32), ("stress", C.c_void_p)]
 
 
 class AdjointInfo(C.Structure):
@@ -465,7 +466,7 @@ class Solver:
         return int(out[0]), int(out[1])
 
     def step(self, x, quat, length, F=None, U=None, tape=None, tape_mode=TAPE_NONE, x_unwrapped=None,
-             links=None, gamma_links=None, walls=None):
+             links=None, gamma_links=None, walls=None, noise=None, kT=0.0, warm_start=False, stress=False):
         """One whole timestep in place on x and quat; returns (U, SolveResult, n_pairs).
         tape: float64 device tensor for the step's constraint forces
         (TAPE_RECORD writes them, TAPE_REPLAY starts from them).
@@ -473,7 +474,11 @@ class Solver:
         links: (p, q, arm, kappa, rest, anchor) device tensors (anchor may be
         None), solved with the contacts; gamma_links receives their forces.
         walls: [(kind, p, a, r), ...].  The step's wall constraint count is
-        left in self.last_wall_contacts."""
+        left in self.last_wall_contacts.
+        noise: [n, 6] N(0,1) draws with kT > 0: Brownian force.
+        warm_start: start from the last warm step's forces (and keep these).
+        stress: leave the contact and link virial stresses (2 x 3 x 3, numpy)
+        in self.last_stress."""
         torch = _torch()
         n = x.shape[0]
         la, l0 = _len_args(length, n)
@@ -485,11 +490,13 @@ class Solver:
         wl = walls_array(walls) if walls else None
         nwc = C.c_int64(0)
         nl = 0 if links is None else int(links[0].shape[0])
+        sbuf = (C.c_double * 18)() if stress else None
         extra = StepExtra(_ptr(x_unwrapped, torch.float64, (n, 3), "x_unwrapped"),
                           C.cast(C.pointer(lk), C.c_void_p) if lk is not None else None,
                           _ptr(gamma_links, torch.float64, (nl,), "gamma_links"), len(walls) if walls else 0,
                           C.cast(wl, C.c_void_p) if wl is not None else None,
-                          C.cast(C.pointer(nwc), C.c_void_p))
+                          C.cast(C.pointer(nwc), C.c_void_p), _ptr(noise, torch.float64, (n, 6), "noise"),
+                          float(kT), 1 if warm_start else 0, C.cast(sbuf, C.c_void_p) if stress else None)
         self._stream()
         rc = self.lib.rl_step(self._h, n, _ptr(x, torch.float64, (n, 3), "x"),
                               _ptr(quat, torch.float64, (n, 4), "quat"), la, l0,
@@ -497,6 +504,9 @@ class Solver:
                               C.byref(info), C.byref(npairs), _ptr(tape, torch.float64, None, "tape"), tlen,
                               int(tape_mode), C.byref(extra))
         self.last_wall_contacts = int(nwc.value)
+        if stress:
+            import numpy as np
+            self.last_stress = np.array(list(sbuf)).reshape(2, 3, 3)
         if rc == ERR_CAPACITY and tape_mode == TAPE_RECORD:
             err = RodLCPError(rc, "rl_step", f"tape too short for {int(npairs.value)} constraints")
             err.count = int(npairs.value)

@@ -149,17 +149,6 @@ __global__ void k_invert_perm(int64_t n, const int *__restrict__ perm, int *__re
     if (t < n) inv[perm[t]] = (int)t;
 }
 
-// the links' forces in the caller's link order: merged constraint m is input
-// constraint ord[m]; links are inputs [np, np + nl)
-__global__ void k_link_gamma(int64_t nc, const double2 *__restrict__ st, const int *__restrict__ ord, int64_t np,
-                             int64_t nl, double *__restrict__ out)
-{
-    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (m >= nc) return;
-    const int64_t c = ord[m];
-    if (c >= np && c < np + nl) out[c - np] = st[m].x;
-}
-
 // One step with links and/or walls: the contacts, the links and the wall
 // constraints of the rods in cell order, concatenated in that order, solved
 // as one general problem.
@@ -185,6 +174,13 @@ static int step_general(rl_ctx *h, int64_t n, double *x, double *quat, const dou
     double *dir = (double *)ws_get(h, kWsDir, sizeof(double) * 3 * n, &err);
     if (err) return err;
     RL_HIP(launch_directors(st, n, quat, dir));
+    if (ex->noise && ex->kT > 0.0) {
+        // F_nc = F + the Brownian force, caller order
+        double *Ftot = (double *)ws_get(h, kWsFtot, sizeof(double) * 6 * n, &err);
+        if (err) return err;
+        RL_HIP(launch_brownian(st, n, dir, len, len0, p.diam, p.eta, p.dt, ex->kT, ex->noise, F, Ftot));
+        F = Ftot;
+    }
     int64_t np = 0;
     const int *perm = nullptr;
     const double *xs = nullptr, *ds = nullptr, *ls = nullptr;
@@ -258,17 +254,30 @@ static int step_general(rl_ctx *h, int64_t n, double *x, double *quat, const dou
         RL_HIP(hipMemsetAsync(cpj + np + nl, 0xff, sizeof(int32_t) * nw, st));  // -1: no Q side
         RL_HIP(hipMemsetAsync(ckind + np + nl, 0, (size_t)nw, st));
     }
-    RL_HIP(hipMemsetAsync(cgam, 0, sizeof(double) * nb, st));
+    const StepList L{n, np, nl, nc, perm, cpi, cpj, (const int32_t *)h->buf[kWsStepImg], ds, ce, carm, phi, llen};
+    if (ex->warm_start) {
+        rc = warm_lookup(h, L, cgam);
+        if (rc) return rc;
+    } else {
+        RL_HIP(hipMemsetAsync(cgam, 0, sizeof(double) * nb, st));
+    }
     SolveArgs a;
     const int *ord = nullptr;
     rc = prepare_general(h, n, ds, lsv, len0, nc, cpi, cpj, ce, carm, cq, ckind, ccmp, cgam, true, &a, &ord);
     if (rc) return rc;
     rc = solve_impl(h, a, F, Uw, nullptr, info, perm);
     if (rc < 0) return rc;
-    if (ex->gamma_links && nl > 0 && nc > 0) {
-        hipLaunchKernelGGL(k_link_gamma, dim3((unsigned)((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nc,
-                           (const double2 *)a.st, ord, np, nl, ex->gamma_links);
-        RL_HIP(hipGetLastError());
+    // the forces back in input order: contacts, links, walls
+    RL_HIP(launch_scatter_gamma(st, a, ord, cgam));
+    if (ex->gamma_links && nl > 0)
+        RL_HIP(hipMemcpyAsync(ex->gamma_links, cgam + np, sizeof(double) * nl, hipMemcpyDeviceToDevice, st));
+    if (ex->warm_start) {
+        const int rcw = warm_store(h, L, cgam);
+        if (rcw) return rcw;
+    }
+    if (ex->stress) {
+        const int rcs = step_stress(h, L, cgam, ex->stress);
+        if (rcs) return rcs;
     }
     const int rc2 = integrate_impl(h, n, Uw, x, quat, ex->x_unwrapped);
     if (rc2) return rc2;
@@ -540,10 +549,20 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
         return step_general(h, n, x, quat, len, len0, F, U, info, n_pairs, extra);
     }
     if (extra && extra->n_wall_contacts) *extra->n_wall_contacts = 0;
+    const bool warm = extra && extra->warm_start;
+    RL_REQUIRE(!warm || tape_mode == RL_TAPE_NONE, "rl_step: warm start and gamma tape exclude each other");
     int err = 0;
     double *dir = (double *)ws_get(h, kWsDir, sizeof(double) * 3 * n, &err);
     if (err) return err;
     RL_HIP(launch_directors(h->stream, n, quat, dir));
+    if (extra && extra->noise && extra->kT > 0.0) {
+        // F_nc = F + the Brownian force, caller order
+        double *Ftot = (double *)ws_get(h, kWsFtot, sizeof(double) * 6 * n, &err);
+        if (err) return err;
+        RL_HIP(launch_brownian(h->stream, n, dir, len, len0, h->prm.diam, h->prm.eta, h->prm.dt, extra->kT,
+                               extra->noise, F, Ftot));
+        F = Ftot;
+    }
     // pairs with the rods renumbered in cell order: the solver then reads
     // neighbouring rods and constraints from neighbouring memory
     int64_t np = 0;
@@ -578,15 +597,30 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     const int32_t *img = (const int32_t *)h->buf[kWsStepImg];
     rc = assemble_impl(h, n, xs, ds, lsv, len0, np, pi, pj, img, Fs, phi, e, arm, q);
     if (rc) return rc;
-    if (tape_mode == RL_TAPE_REPLAY && np > 0)
+    const StepList L{n, np, 0, np, perm, pi, pj, img, ds, e, arm, phi, nullptr};
+    if (tape_mode == RL_TAPE_REPLAY && np > 0) {
         RL_HIP(hipMemcpyAsync(gamma, gamma_tape, sizeof(double) * np, hipMemcpyDeviceToDevice, h->stream));
-    else
+    } else if (warm) {
+        rc = warm_lookup(h, L, gamma);
+        if (rc) return rc;
+    } else {
         RL_HIP(hipMemsetAsync(gamma, 0, sizeof(double) * nb, h->stream));
+    }
     SolveArgs a;
     rc = prepare_solve(h, n, ds, lsv, len0, np, pi, pj, e, arm, q, gamma, &a, true);
     if (rc) return rc;
     rc = solve_impl(h, a, F, Uw, tape_mode != RL_TAPE_NONE && np > 0 ? gamma_tape : gamma, info, perm);
     if (rc < 0) return rc;
+    // gamma (or the tape) holds the forces in the step's constraint order
+    const double *gsol = tape_mode != RL_TAPE_NONE && np > 0 ? gamma_tape : gamma;
+    if (warm) {
+        const int rcw = warm_store(h, L, gsol);
+        if (rcw) return rcw;
+    }
+    if (extra && extra->stress) {
+        const int rcs = step_stress(h, L, gsol, extra->stress);
+        if (rcs) return rcs;
+    }
     const int rc2 = integrate_impl(h, n, Uw, x, quat, extra ? extra->x_unwrapped : nullptr);
     if (rc2) return rc2;
     RL_HIP(hipStreamSynchronize(h->stream));

@@ -318,6 +318,184 @@ int prepare_general(rl_ctx *h, int64_t n, const double *dir, const double *len, 
     return RL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Multi-step pieces of a step
+// ---------------------------------------------------------------------------
+// Brownian force per rod, caller order: F_B = sqrt(2 kT/h) M^(-1/2) xi with
+// M^(-1/2) = a_perp^(-1/2) I + (a_par^(-1/2) - a_perp^(-1/2)) d d^T on the
+// translation and r^(-1/2) I on the rotation (axial = normal mobility).
+__global__ void k_brownian(int64_t n, const double *__restrict__ dir, const double *__restrict__ len, double len0,
+                           double diam, double eta, double amp, const double *__restrict__ xi,
+                           const double *__restrict__ F, double *__restrict__ Ftot)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double L = len ? len[i] : len0;
+    const double lg = log(2.0 * L / diam);
+    const double aperp = lg / (4.0 * M_PI * eta * L), apar = 2.0 * aperp;
+    const double rperp = 3.0 * lg / (M_PI * eta * L * L * L);
+    const double sn = 1.0 / sqrt(aperp), sp = 1.0 / sqrt(apar), sr = 1.0 / sqrt(rperp);
+    const double dx = dir[3 * i], dy = dir[3 * i + 1], dz = dir[3 * i + 2];
+    const double *z = xi + 6 * i;
+    const double dz3 = (sp - sn) * (dx * z[0] + dy * z[1] + dz * z[2]);
+    const double fb[6] = {sn * z[0] + dz3 * dx, sn * z[1] + dz3 * dy, sn * z[2] + dz3 * dz,
+                          sr * z[3], sr * z[4], sr * z[5]};
+    for (int a = 0; a < 6; ++a) Ftot[6 * i + a] = (F ? F[6 * i + a] : 0.0) + amp * fb[a];
+}
+
+hipError_t launch_brownian(hipStream_t st, int64_t n, const double *dir, const double *len, double len0, double diam,
+                           double eta, double dt, double kT, const double *noise, const double *F, double *Ftot)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_brownian, dim3(grid_of(n)), dim3(kBlock), 0, st, n, dir, len, len0, diam, eta,
+                       sqrt(2.0 * kT / dt), noise, F, Ftot);
+    return hipGetLastError();
+}
+
+// Key of input constraint c in the caller's numbering: a contact by its two
+// rods (smaller caller index first, the shift negated when they swap) and
+// shift, a link by its index; wall contacts have no key (0).
+__device__ __forceinline__ unsigned long long step_key(const StepList &L, int64_t c)
+{
+    if (c < L.np) {
+        unsigned long long a = (unsigned)L.perm[L.pi[c]], b = (unsigned)L.perm[L.pj[c]];
+        int img = L.img[c];
+        if (a > b) {
+            const unsigned long long t = a;
+            a = b;
+            b = t;
+            const int sx = ((img >> 8) & 15) - 8, sy = ((img >> 4) & 15) - 8, sz = (img & 15) - 8;
+            img = ((-sx + 8) << 8) | ((-sy + 8) << 4) | (-sz + 8);
+        }
+        return (1ull << 62) | (a << 37) | (b << 12) | (unsigned long long)img;
+    }
+    if (c < L.np + L.nl) return (2ull << 62) | (unsigned long long)(c - L.np);
+    return 0ull;
+}
+
+__global__ void k_warm_lookup(StepList L, const unsigned long long *__restrict__ keys,
+                              const double *__restrict__ gam, int64_t m, double *__restrict__ gamma0)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= L.nc) return;
+    const unsigned long long k = step_key(L, c);
+    double g = 0.0;
+    if (k != 0ull && m > 0) {
+        int64_t lo = 0, hi = m;  // first stored key >= k
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < k) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < m && keys[lo] == k) g = gam[lo];
+    }
+    gamma0[c] = g;
+}
+
+__global__ void k_warm_keys(StepList L, const double *__restrict__ gamma, unsigned long long *__restrict__ keys,
+                            double *__restrict__ vals)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= L.nc) return;
+    keys[c] = step_key(L, c);
+    vals[c] = gamma[c];
+}
+
+int warm_lookup(rl_ctx *h, const StepList &L, double *gamma0)
+{
+    if (L.nc <= 0) return RL_OK;
+    const bool have = h->warm_count >= 0 && h->warm_n == L.n;
+    hipLaunchKernelGGL(k_warm_lookup, dim3(grid_of(L.nc)), dim3(kBlock), 0, h->stream, L,
+                       (const unsigned long long *)h->buf[kWsWarmKeys], (const double *)h->buf[kWsWarmGam],
+                       have ? h->warm_count : (int64_t)0, gamma0);
+    RL_HIP(hipGetLastError());
+    return RL_OK;
+}
+
+int warm_store(rl_ctx *h, const StepList &L, const double *gamma)
+{
+    int werr = 0;
+    const int64_t nb = L.nc > 0 ? L.nc : 1;
+    auto *kn = (unsigned long long *)ws_get(h, kWsWarmKeysNew, sizeof(unsigned long long) * nb, &werr);
+    auto *vn = (double *)ws_get(h, kWsWarmGamNew, sizeof(double) * nb, &werr);
+    auto *ks = (unsigned long long *)ws_get(h, kWsWarmKeys, sizeof(unsigned long long) * nb, &werr);
+    auto *vs = (double *)ws_get(h, kWsWarmGam, sizeof(double) * nb, &werr);
+    if (werr) return werr;
+    if (L.nc > 0) {
+        hipLaunchKernelGGL(k_warm_keys, dim3(grid_of(L.nc)), dim3(kBlock), 0, h->stream, L, gamma, kn, vn);
+        RL_HIP(hipGetLastError());
+        const int rc = sort_key_values(h, L.nc, kn, vn, ks, vs);
+        if (rc) return rc;
+    }
+    h->warm_count = L.nc;
+    h->warm_n = L.n;
+    return RL_OK;
+}
+
+// per-workgroup partial sums of gamma (x_P - x_Q') e^T over contacts [0..8]
+// and two-sided links [9..17] (walls and links to fixed points are external)
+constexpr int kStressBlock = 256;
+
+__global__ void __launch_bounds__(kStressBlock) k_stress(StepList L, double diam, const double *__restrict__ gamma,
+                                                        double *__restrict__ part)
+{
+    __shared__ double lds[kStressBlock / 64][18];
+    double acc[18];
+    for (int k = 0; k < 18; ++k) acc[k] = 0.0;
+    for (int64_t c = blockIdx.x * (int64_t)kStressBlock + threadIdx.x; c < L.np + L.nl;
+         c += (int64_t)gridDim.x * kStressBlock) {
+        const double g = gamma[c];
+        const double e[3] = {L.e[3 * c], L.e[3 * c + 1], L.e[3 * c + 2]};
+        const double si = L.arm[2 * c], sj = L.arm[2 * c + 1];
+        const int P = L.pi[c], Q = L.pj[c];
+        if (Q < 0) continue;
+        // x_P - x_Q' = r - s_P d_P + s_Q d_Q with r the vector between the two
+        // points: (phi + diam) e for a contact, length e for a link
+        const double rl = c < L.np ? L.phi[c] + diam : L.link_len[c - L.np];
+        const int off = c < L.np ? 0 : 9;
+        for (int a = 0; a < 3; ++a) {
+            const double ra = rl * e[a] - si * L.dir[3 * (int64_t)P + a] + sj * L.dir[3 * (int64_t)Q + a];
+            for (int b = 0; b < 3; ++b) acc[off + 3 * a + b] += g * ra * e[b];
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = 0; k < 18; ++k) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) lds[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 18) {
+        double v = 0.0;
+        for (int k = 0; k < kStressBlock / 64; ++k) v += lds[k][threadIdx.x];
+        part[18 * (int64_t)blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+int step_stress(rl_ctx *h, const StepList &L, const double *gamma, double *out)
+{
+    const rl_params &p = h->prm;
+    const int64_t m = L.np + L.nl;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + kStressBlock - 1) / kStressBlock, 512));
+    int werr = 0;
+    double *part = (double *)ws_get(h, kWsStress, sizeof(double) * 18 * grid, &werr);
+    if (werr) return werr;
+    int err = 0;
+    double *host = (double *)ws_get_host(h, sizeof(double) * 18 * grid, &err);
+    if (err) return err;
+    hipLaunchKernelGGL(k_stress, dim3(grid), dim3(kStressBlock), 0, h->stream, L, p.diam, gamma, part);
+    RL_HIP(hipGetLastError());
+    RL_HIP(hipMemcpyAsync(host, part, sizeof(double) * 18 * grid, hipMemcpyDeviceToHost, h->stream));
+    RL_HIP(hipStreamSynchronize(h->stream));
+    const double V = p.box[0] * p.box[1] * p.box[2];
+    for (int k = 0; k < 18; ++k) {
+        double v = 0.0;
+        for (unsigned b = 0; b < grid; ++b) v += host[18 * b + k];
+        out[k] = v / V;
+    }
+    return RL_OK;
+}
+
 int wall_set(int n_walls, const rl_wall *walls, WallSet *W)
 {
     *W = WallSet{};

@@ -184,6 +184,9 @@ struct rl_ctx {
     char *scratch = nullptr;                   // this device's scratch array
     size_t arena_used = 0;
     bool arena_on = false;
+    // warm start: sorted constraint keys and forces of the last warm step
+    int64_t warm_count = -1;                   // -1: none kept
+    int64_t warm_n = 0;                        // its rod count
 };
 
 namespace rl {
@@ -201,6 +204,7 @@ enum Slot : int {
     kWsGenKey, kWsGenKeyOut, kWsGenOrd, kWsGenPi, kWsGenPj, kWsGenE, kWsGenArm, kWsGenQ, kWsGenCmp, kWsGenGamma,
     kWsGenPsplit, kWsGenQsplit, kWsLinkLen, kWsLinkFlags, kWsInvPerm, kWsWallCnt, kWsWallOff,
     kWsCatPi, kWsCatPj, kWsCatE, kWsCatArm, kWsCatQ, kWsCatKind, kWsCatCmp, kWsCatLen, kWsStepUnc,
+    kWsFtot, kWsWarmKeys, kWsWarmGam, kWsWarmKeysNew, kWsWarmGamNew, kWsStress,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -226,6 +230,8 @@ int scan_tmp_bytes(int64_t m, size_t *bytes);
 constexpr size_t kScratchBytes = (size_t)RL_NOALLOC_SCRATCH_BYTES;
 // sorts m pair keys ((pi << (ibits + 12)) | (pj << 12) | shift, `bits` wide)
 // with their flags and writes the canonical pi, pj, img, flags lists
+int sort_key_values(rl_ctx *h, int64_t m, const unsigned long long *keys, const double *vals,
+                    unsigned long long *keys_out, double *vals_out);
 int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *keys, const uint8_t *kflags, int ibits,
                    int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags);
 // Pair list in the solver's own rod order (cell order).  On return *perm
@@ -300,6 +306,26 @@ int prepare_general(rl_ctx *h, int64_t n, const double *dir, const double *len, 
                     const uint8_t *kind, const double *cmp, const double *gamma, bool trusted, SolveArgs *out,
                     const int **order);
 hipError_t launch_scatter_gamma(hipStream_t st, const SolveArgs &a, const int *order, double *gamma);
+// Multi-step pieces of a step (rl_general.hip).  A step's constraint list in
+// input order: [0, np) contacts (pi, pj in the solver's rod order, img),
+// [np, np + nl) links, then wall contacts.  perm: solver -> caller rod.
+struct StepList {
+    int64_t n, np, nl, nc;
+    const int *perm;
+    const int32_t *pi, *pj, *img;
+    const double *dir;                 // solver order
+    const double *e, *arm, *phi;       // input order (phi: contacts)
+    const double *link_len;            // [nl]
+};
+// Brownian force: Ftot = F + sqrt(2 kT/h) M^(-1/2) noise (caller order)
+hipError_t launch_brownian(hipStream_t st, int64_t n, const double *dir, const double *len, double len0, double diam,
+                           double eta, double dt, double kT, const double *noise, const double *F, double *Ftot);
+// gamma0 (input order) from the last warm step's keys (0 where none matches)
+int warm_lookup(rl_ctx *h, const StepList &L, double *gamma0);
+// keeps this step's keys and forces (gamma in input order)
+int warm_store(rl_ctx *h, const StepList &L, const double *gamma);
+// the 18 stress components (host) from the forces in input order
+int step_stress(rl_ctx *h, const StepList &L, const double *gamma, double *out);
 // wall contacts of rods (x, dir, len in one order; Unc = M F in the same)
 int walls_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                const double *Unc, const WallSet &W, int64_t capacity, int32_t *rod, double *e, double *arm,

@@ -93,4 +93,19 @@ int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *key
     return RL_OK;
 }
 
+// sorts m (key, value) pairs by key into keys_out / vals_out
+int sort_key_values(rl_ctx *h, int64_t m, const unsigned long long *keys, const double *vals,
+                    unsigned long long *keys_out, double *vals_out)
+{
+    hipStream_t st = h->stream;
+    if (m <= 0) return RL_OK;
+    int werr = 0;
+    size_t tmp_bytes = 0;
+    RL_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, keys_out, vals, vals_out, (int)m, 0, 64, st));
+    void *tmp = ws_get(h, kWsSortTmp, tmp_bytes, &werr);
+    if (werr) return werr;
+    RL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, keys_out, vals, vals_out, (int)m, 0, 64, st));
+    return RL_OK;
+}
+
 }  // namespace rl
