@@ -29,56 +29,91 @@ FLAG_CUTOFF, FLAG_PARALLEL, FLAG_DEGENERATE = 1, 2, 4
 OK, NOT_CONVERGED, STAGNATED = 0, 1, 2
 
 
+_CHECK_FLAGS = ["-O2", "-ffp-contract=off"]
+# Timing build of the same source for the CPU baseline: optimised for the
+# host it runs on, so it is compiled there, into a private temporary folder,
+# and never loaded by the tests' checker calls.
+_TIMING_FLAGS = ["-O3", "-march=native"]
+_timing_lib = None
+_active = "check"
+
+
+def _compile(out: str, flags) -> None:
+    tmp = out + ".tmp"
+    cmd = ["gcc", *flags, "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no GPU code involved)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fPIC", "-shared",
-               "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        _compile(_LIB, _CHECK_FLAGS)
     return _LIB
 
 
+def use_build(name: str) -> str:
+    """Select the library the wrappers call: "check" (the default, -O2
+    -ffp-contract=off, what every test uses) or "timing" (-O3 -march=native,
+    built on first use for this host; the same source, so its results agree
+    with the checker's to rounding).  Returns the previous choice."""
+    global _active
+    if name not in ("check", "timing"):
+        raise ValueError(name)
+    prev, _active = _active, name
+    return prev
+
+
 def _load():
-    global _lib
+    global _lib, _timing_lib
     with _lock:
+        if _active == "timing":
+            if _timing_lib is None:
+                import tempfile
+                out = os.path.join(tempfile.mkdtemp(prefix="rodlcp_oracle_"), "liboracle_timing.so")
+                _compile(out, _TIMING_FLAGS)
+                _timing_lib = _declare(C.CDLL(out))
+            return _timing_lib
         if _lib is None:
             if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
                 build(force=True)
-            lib = C.CDLL(_LIB)
-            P = C.c_void_p
-            I64 = C.c_int64
-            D = C.c_double
-            lib.ora_img_pack.argtypes = [C.c_int, C.c_int, C.c_int]
-            lib.ora_img_pack.restype = C.c_int
-            lib.ora_rotation.argtypes = [P, P]
-            lib.ora_directors.argtypes = [I64, P, P]
-            lib.ora_psi_times.argtypes = [P, P, P]
-            lib.ora_mobility_coeffs.argtypes = [D, D, D, P]
-            lib.ora_mobility_block.argtypes = [P, D, D, D, P]
-            lib.ora_apply_mobility.argtypes = [I64, P, P, D, D, D, P, P]
-            lib.ora_closest_flat.argtypes = [P, P, D, P, P, D, P]
-            for fn in (lib.ora_pairs_brute, lib.ora_pairs_cells):
-                fn.argtypes = [I64, P, P, P, D, P, D, D, I64, P, P, P, P]
-                fn.restype = I64
-            lib.ora_assemble.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P]
-            lib.ora_dense_D.argtypes = [I64, P, I64, P, P, P, P, P]
-            lib.ora_apply_Mc.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P]
-            lib.ora_velocity.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P]
-            lib.ora_bbpgd.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, D, I64, P, P, P]
-            lib.ora_bbpgd.restype = C.c_int
-            lib.ora_integrate.argtypes = [I64, P, D, P, P, P, P]
-            lib.ora_bbpgd_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, D, I64, P, P, P]
-            lib.ora_bbpgd_gen.restype = C.c_int
-            lib.ora_apply_Mc_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, P, P]
-            lib.ora_links.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P, P, P, P, P]
-            lib.ora_walls.argtypes = [I64, P, P, P, D, D, D, D, D, I64, P, P, I64, P, P, P, P, P]
-            lib.ora_walls.restype = I64
-            lib.ora_mobility_pow_block.argtypes = [P, D, D, D, D, P]
-            lib.ora_brownian_force.argtypes = [I64, P, P, D, D, D, D, D, P, P]
-            _lib = lib
+            _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+def _declare(lib):
+    """Argument and result types of the exported functions."""
+    P = C.c_void_p
+    I64 = C.c_int64
+    D = C.c_double
+    lib.ora_img_pack.argtypes = [C.c_int, C.c_int, C.c_int]
+    lib.ora_img_pack.restype = C.c_int
+    lib.ora_rotation.argtypes = [P, P]
+    lib.ora_directors.argtypes = [I64, P, P]
+    lib.ora_psi_times.argtypes = [P, P, P]
+    lib.ora_mobility_coeffs.argtypes = [D, D, D, P]
+    lib.ora_mobility_block.argtypes = [P, D, D, D, P]
+    lib.ora_apply_mobility.argtypes = [I64, P, P, D, D, D, P, P]
+    lib.ora_closest_flat.argtypes = [P, P, D, P, P, D, P]
+    for fn in (lib.ora_pairs_brute, lib.ora_pairs_cells):
+        fn.argtypes = [I64, P, P, P, D, P, D, D, I64, P, P, P, P]
+        fn.restype = I64
+    lib.ora_assemble.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P]
+    lib.ora_dense_D.argtypes = [I64, P, I64, P, P, P, P, P]
+    lib.ora_apply_Mc.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P]
+    lib.ora_velocity.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P]
+    lib.ora_bbpgd.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, D, I64, P, P, P]
+    lib.ora_bbpgd.restype = C.c_int
+    lib.ora_integrate.argtypes = [I64, P, D, P, P, P, P]
+    lib.ora_bbpgd_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, D, I64, P, P, P]
+    lib.ora_bbpgd_gen.restype = C.c_int
+    lib.ora_apply_Mc_gen.argtypes = [I64, P, P, D, D, D, I64, P, P, P, P, P, P, P, P, P]
+    lib.ora_links.argtypes = [I64, P, P, P, D, P, D, D, D, I64, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.ora_walls.argtypes = [I64, P, P, P, D, D, D, D, D, I64, P, P, I64, P, P, P, P, P]
+    lib.ora_walls.restype = I64
+    lib.ora_mobility_pow_block.argtypes = [P, D, D, D, D, P]
+    lib.ora_brownian_force.argtypes = [I64, P, P, D, D, D, D, D, P, P]
+    return lib
 
 
 def _p(a: Optional[np.ndarray]):

@@ -17,9 +17,10 @@
  * and the distance is a point-to-segment distance.  The routine evaluates
  * those five candidates and keeps the smallest.
  *
- * Sweeps are Jacobi steps: every rod sums, in a fixed neighbour order, the
- * pushes of the pairs it overlaps, and all rods move at the end of the sweep,
- * so the result does not depend on the thread count.
+ * Sweeps are Gauss-Seidel steps over the candidate pairs (each push moves
+ * the pair's two rods at once, over-relaxed), swept brick by brick in a fixed
+ * colouring so that bricks of one colour touch disjoint rods and run in
+ * parallel: the result does not depend on the thread count.
  */
 #include <math.h>
 #include <stdio.h>

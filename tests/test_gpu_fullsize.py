@@ -1,12 +1,13 @@
 """Parity at the full benchmark size: the 100,000-rod nematic suspension
 that bench.py times, through the same entry points and launch shapes.
 
-The oracle cannot solve this system within a test, so the expected values
-were written once by tests/golden/make_rods100k_golden.py (oracle only):
-the canonical pair list (as a SHA-256), and U at 500 sampled rods.  Beside
-that, the GPU's gamma is certified with the oracle's own operator: it must
-satisfy the complementarity conditions to the tolerance, which pins U
-(unique for a convex QP) independently of the stored values."""
+The expected values were written once by tests/golden/make_rods100k_golden.py
+(oracle only): the canonical pair list (as a SHA-256) and U at 500 sampled
+rods.  The step's U is also compared over all 6N entries with the oracle's
+own solve, run in the test (about 15 s of CPU).  Beside that, the GPU's gamma
+is certified with the oracle's own operator: it must satisfy the
+complementarity conditions to the tolerance, which pins U (unique for a
+convex QP) independently of the stored values."""
 import hashlib
 import json
 import os
@@ -49,7 +50,20 @@ def test_fullsize_pair_list_bit_exact(gpu_lib, system):
     assert h.hexdigest() == GOLD["pair_sha256"]
 
 
-def test_fullsize_step_velocities(gpu_lib, system):
+@pytest.fixture(scope="module")
+def oracle_velocities(system):
+    """The oracle's own solve of the whole system (cell-list pairs, BBPGD to
+    1e-8; about 15 s of CPU): U over all 6N entries."""
+    s = system
+    d = oracle.directors(s.quat)
+    pr = oracle.pairs(s.x, d, 1.0, s.box, s.diam, s.cutoff, method="cells")
+    cs = oracle.assemble(s.x, d, 1.0, s.box, s.diam, s.eta, s.dt, pr, s.force)
+    r = oracle.bbpgd(d, 1.0, s.diam, s.eta, pr, cs, tol=1e-8, max_iter=200_000)
+    assert r.status == oracle.OK
+    return oracle.velocity(d, 1.0, s.diam, s.eta, pr, cs, r.gamma, s.force)
+
+
+def test_fullsize_step_velocities(gpu_lib, system, oracle_velocities):
     s = system
     with _solver(gpu_lib, s) as slv:
         x, q = _t(s.x), _t(s.quat)
@@ -57,6 +71,9 @@ def test_fullsize_step_velocities(gpu_lib, system):
     assert npairs == GOLD["n_pairs"]
     assert info.status == gpu_lib.OK and info.residual <= 1e-8
     U = U.cpu().numpy()
+    # the bar over all 6N entries, against the oracle's solve
+    Uo = oracle_velocities
+    assert np.linalg.norm(U - Uo) <= 1e-6 * np.linalg.norm(Uo)
     want = np.asarray(GOLD["U_sample"])
     got = U[np.asarray(GOLD["sample_rods"])]
     assert np.linalg.norm(got - want) <= 1e-6 * np.linalg.norm(want)

@@ -129,6 +129,76 @@ def test_pairs_hand_cases(gpu_lib):
     assert np.allclose(arm.cpu().numpy(), cs.arm, atol=1e-15)
 
 
+def _c6_cases():
+    """Pairs that take the closest-point fallbacks, one pair per case, each
+    case far from the others (box 24, cases 4 apart).  Directors are given
+    exactly (axis-aligned or simple), so both sides see the same inputs.
+      0 axes crossing at both centres (dist 0: e = +d_i x d_j)
+      1 axes crossing off-centre (s = 0.25 on rod 0)
+      2 axes 5e-13 apart (below the degenerate distance): e = -z, the sign
+        of r0 along d_i x d_j
+      3 collinear, overlapping end to end (e from the least-aligned axis)
+      4 collinear, antiparallel
+      5 parallel side by side, interior overlap (midpoint rule)
+      6 parallel, not overlapping along the axis (end points)
+      7 near-parallel (tilt 1e-9 rad: 1 - b^2 below the parallel band)
+    """
+    X, D = [], []
+    ex, ey, ez = np.eye(3)
+    c = lambda k: np.array([2.0 + 4.0 * (k % 5), 2.0 + 4.0 * (k // 5), 12.0])  # noqa: E731
+    cases = [
+        ((0, 0, 0), ex, (0, 0, 0), ey),
+        ((0, 0, 0), ex, (0.25, 0, 0), ey),
+        ((0, 0, 0), ex, (0.25, 0, 5e-13), ey),
+        ((0, 0, 0), ex, (0.5, 0, 0), ex),
+        ((0, 0, 0), ex, (0.75, 0, 0), -ex),
+        ((0, 0, 0), ex, (0.3, 0.02, 0), ex),
+        ((0, 0, 0), ex, (1.01, 0.01, 0), ex),
+        ((0, 0, 0), ex, (0.3, 0.02, 0), np.array([1.0, 1e-9, 0.0]) / math.hypot(1.0, 1e-9)),
+    ]
+    for k, (x0, d0, x1, d1) in enumerate(cases):
+        X += [c(k) + np.asarray(x0, float), c(k) + np.asarray(x1, float)]
+        D += [np.asarray(d0, float), np.asarray(d1, float)]
+    return np.array(X), np.array(D)
+
+
+def test_closest_point_fallbacks_match_the_oracle(gpu_lib):
+    """The parallel, intersecting and collinear fallbacks change D and U, so
+    the GPU must take the same choices as the oracle: pairs, flags, gaps,
+    normals, lever arms and q compared element by element with no mask, then
+    the solve's velocities."""
+    x, d = _c6_cases()
+    n = x.shape[0]
+    rng = np.random.default_rng(8)
+    F = rng.standard_normal((n, 6))
+    box = 24.0
+    s = rodsynth.make_system(n, seed=0, box=box)
+    s = rodsynth.RodSystem(x=x, quat=s.quat, length=np.ones(n), force=F, box=box)
+    pr = oracle.pairs(x, d, 1.0, box, s.diam, s.cutoff)
+    cs = oracle.assemble(x, d, 1.0, box, s.diam, s.eta, s.dt, pr, F)
+    assert pr.n == 8 and np.array_equal(pr.pi, np.arange(0, n, 2)) and np.array_equal(pr.pj, pr.pi + 1)
+    assert np.all(pr.flags[[0, 1, 2, 3, 4]] & oracle.FLAG_DEGENERATE)
+    assert np.all(pr.flags[[3, 4, 5, 6, 7]] & oracle.FLAG_PARALLEL)
+    assert np.array_equal(cs.e[0], [0.0, 0.0, 1.0]) and np.array_equal(cs.e[2], [0.0, 0.0, -1.0])
+    assert np.array_equal(cs.arm[1], [0.25, 0.0]) and np.allclose(cs.arm[5], [0.15, -0.15], atol=1e-15)
+    with _solver(gpu_lib, s) as slv:
+        got = _gpu_pairs(gpu_lib, slv, s, _t(d))
+        assert np.array_equal(got[0], pr.pi) and np.array_equal(got[1], pr.pj)
+        assert np.array_equal(got[2], pr.img) and np.array_equal(got[3], pr.flags)
+        phi, e, arm, q = slv.assemble_D(_t(x), _t(d), 1.0, *[_t(v, torch.int32) for v in got[:3]], _t(F))
+        phi, e, arm, q = (v.cpu().numpy() for v in (phi, e, arm, q))
+        assert np.abs(phi - cs.phi).max() <= 1e-15
+        assert np.abs(e - cs.e).max() <= 1e-15
+        assert np.abs(arm - cs.arm).max() <= 1e-15
+        assert np.abs(q - cs.q).max() <= 1e-12 * np.abs(cs.q).max()
+        g, U, info = slv.solve_lcp(_t(d), 1.0, _t(pr.pi, torch.int32), _t(pr.pj, torch.int32), _t(cs.e),
+                                   _t(cs.arm), _t(cs.q), F=_t(F))
+    assert info.status == gpu_lib.OK
+    ref = oracle.bbpgd(d, 1.0, s.diam, s.eta, pr, cs, tol=1e-8)
+    Uo = oracle.velocity(d, 1.0, s.diam, s.eta, pr, cs, ref.gamma, F)
+    assert np.linalg.norm(U.cpu().numpy() - Uo) <= 1e-6 * np.linalg.norm(Uo)
+
+
 def test_pairs_capacity_and_errors(gpu_lib):
     s = rodsynth.cfg_small(0)
     d = _t(oracle.directors(s.quat))

@@ -219,3 +219,23 @@ def test_single_contact_converges_in_one_iteration():
     D, Mb, Mc = _dense_Mc(r)
     assert r.solve.alpha0 == pytest.approx(1.0 / Mc[0, 0], rel=1e-14)
     assert r.solve.gamma[0] == pytest.approx(-r.cons.q[0] / Mc[0, 0], rel=1e-13)
+
+
+def test_timing_build_agrees_with_the_checker():
+    """The CPU baseline times the same oracle source built -O3 -march=native
+    (contractions allowed); its solution must agree with the checker build's
+    to rounding: both certified, the same unique U."""
+    s = rodsynth.cfg_small(2)
+    d = oracle.directors(s.quat)
+    pr = oracle.pairs(s.x, d, 1.0, s.box, s.diam, s.cutoff)
+    cs = oracle.assemble(s.x, d, 1.0, s.box, s.diam, s.eta, s.dt, pr, s.force)
+    ref = oracle.bbpgd(d, 1.0, s.diam, s.eta, pr, cs, tol=1e-10)
+    Uref = oracle.velocity(d, 1.0, s.diam, s.eta, pr, cs, ref.gamma, s.force)
+    prev = oracle.use_build("timing")
+    try:
+        r = oracle.bbpgd(d, 1.0, s.diam, s.eta, pr, cs, tol=1e-10)
+        U = oracle.velocity(d, 1.0, s.diam, s.eta, pr, cs, r.gamma, s.force)
+    finally:
+        oracle.use_build(prev)
+    assert ref.status == oracle.OK and r.status == oracle.OK
+    assert np.linalg.norm(U - Uref) <= 1e-9 * np.linalg.norm(Uref)

@@ -88,6 +88,23 @@ def test_mobility_coefficients_closed_form():
     assert c[2] == pytest.approx(418.4, abs=0.1)
 
 
+@pytest.mark.parametrize("L", [0.5, 1.0, 1.37, 4.0])
+def test_rotational_drag_is_the_second_moment_of_the_normal_drag(L):
+    """Resistive-force picture: a rod turning at rate w about a normal axis
+    through its centre moves its point at arclength s at w s, normal to the
+    axis, against the normal drag density zeta_perp / L; the torque of that
+    drag, integrated along the rod by quadrature, must be the torque that
+    gives w through the oracle's rotational mobility."""
+    from scipy.integrate import quad
+    d, eta = 0.025, 0.01
+    c = oracle.mobility_coeffs(L, d, eta)
+    zeta_perp = 1.0 / c[1]
+    torque = 2.7
+    w = c[2] * torque
+    drag_torque, _ = quad(lambda s: s * (zeta_perp / L) * (w * s), -0.5 * L, 0.5 * L, epsabs=0.0, epsrel=1e-13)
+    assert drag_torque == pytest.approx(torque, rel=1e-12)
+
+
 def test_mobility_block_eigenstructure():
     rng = np.random.default_rng(3)
     d = _unit(rng.standard_normal(3))
