@@ -97,9 +97,12 @@ typedef struct {
     double tol;         /* BBPGD stops when max_c |min(gamma_c, w_c)| <= tol */
     int64_t max_iter;   /* BBPGD iteration cap, >= 0 */
     int32_t precision;  /* RL_FP64 or RL_FP32_MIXED */
-    int32_t check_every;/* iterations between host checks of the stop flag; 0 = default (32).  Up to 8
-                           more iterations are queued behind each check; after the stop they
-                           return at once without touching the result */
+    int32_t check_every;/* 0 = default (32).  FP64 loop: the host follows a progress word that the
+                           loop stores into pinned host memory and keeps min(check_every, 7)
+                           iterations queued past the running one.  FP32-mixed, batched and
+                           adjoint loops: iterations between host checks of the stop flag, with
+                           up to 8 more queued behind each check.  Iterations queued past the
+                           stop return at once without touching the result */
 } rl_params;
 
 typedef struct {

@@ -346,6 +346,8 @@ int rl_create(rl_handle *out, const rl_params *prm)
         hipMalloc(&h->flag_dev, sizeof(int) * 4) != hipSuccess ||
         hipHostMalloc(&h->state_host, sizeof(SolverState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&h->host_scratch, sizeof(int64_t) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&h->progress_host, 64, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&h->progress_dev, h->progress_host, 0) != hipSuccess ||
         hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming) != hipSuccess) {
         set_error("rl_create: allocation failed");
         rl_destroy(h);
@@ -379,6 +381,7 @@ int rl_destroy(rl_handle h)
     if (h->flag_dev) (void)hipFree(h->flag_dev);
     if (h->state_host) (void)hipHostFree(h->state_host);
     if (h->host_scratch) (void)hipHostFree(h->host_scratch);
+    if (h->progress_host) (void)hipHostFree(h->progress_host);
     if (h->host_buf) (void)hipHostFree(h->host_buf);
     if (h->own_stream) {
         (void)hipStreamSynchronize(h->own_stream);

@@ -197,7 +197,16 @@ __device__ __forceinline__ int cell_coord(double x, double cell, int nc)
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
 
-__global__ void k_bin(int64_t n, const double *__restrict__ x, const double *__restrict__ dir, GridDev g,
+// Spread the low three bits of v to bits 0, 3 and 6.
+__device__ __forceinline__ unsigned spread3(unsigned v)
+{
+    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
+}
+
+// cell_of[i] = the rod's cell, followed by `fb` bits (0, 3, 6 or 9) of the
+// Morton code of its sub-cell (fb / 3 bits per direction) when the rods are
+// to be ordered by position inside their cells as well.
+__global__ void k_bin(int64_t n, const double *__restrict__ x, const double *__restrict__ dir, GridDev g, int fb,
                       int *__restrict__ cell_of, int *__restrict__ cell_cnt, int *__restrict__ err)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -214,14 +223,21 @@ __global__ void k_bin(int64_t n, const double *__restrict__ x, const double *__r
         return;
     }
     int kc[3];
+    unsigned sub = 0;
+    const int per = fb / 3, side = 1 << per;
     bool inside = true;
     for (int a = 0; a < 3; ++a) {
         inside = inside && xs[a] >= 0.0 && xs[a] < g.box[a];
         kc[a] = cell_coord(xs[a], g.cell[a], g.nc[a]);
+        if (per > 0) {
+            int f = (int)floor((xs[a] / g.cell[a] - kc[a]) * side);
+            f = f < 0 ? 0 : (f >= side ? side - 1 : f);
+            sub |= spread3((unsigned)f << (3 - per)) << a;
+        }
     }
     if (!inside) atomicOr(err, 2);
     const int id = (kc[0] * g.nc[1] + kc[1]) * g.nc[2] + kc[2];
-    cell_of[i] = id;
+    cell_of[i] = (int)(((unsigned)id << fb) | (sub >> (9 - fb)));
     atomicAdd(cell_cnt + id, 1);
 }
 
@@ -609,17 +625,23 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     int64_t *tot = (int64_t *)ws_get(h, kWsScan, sizeof(int64_t) * 2, &werr);
     if (werr) return werr;
 
+    // internal order: by cell, then along a Morton curve of 8^3 sub-cells
+    // inside the cell (fewer when the cell ids leave no room in 31 bits), so
+    // that rods with consecutive numbers are close in space and so are their
+    // partners' records in the solver's Q-side arrays
+    int cbits = 1;
+    while ((1LL << cbits) < ncell) ++cbits;
+    const int fb = internal ? std::min(9, (31 - cbits) / 3 * 3) : 0;
     RL_HIP(hipMemsetAsync(cell_cnt, 0, sizeof(int) * ncell, st));
-    hipLaunchKernelGGL(k_bin, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, g, cell_of, cell_cnt, h->flag_dev);
+    hipLaunchKernelGGL(k_bin, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, g, fb, cell_of, cell_cnt,
+                       h->flag_dev);
     RL_HIP(hipGetLastError());
     {
         const int rc = device_scan(h, cell_cnt, ncell, cell_start, nullptr);
         if (rc) return rc;
     }
     if (internal) {
-        int bits = 1;
-        while ((1LL << bits) < ncell) ++bits;
-        int rc = stable_sort_by_key(h, n, cell_of, bits, cell_key, sorted);
+        int rc = stable_sort_by_key(h, n, cell_of, cbits + fb, cell_key, sorted);
         if (rc) return rc;
         hipLaunchKernelGGL(k_gather_rods, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)sorted, x, dir, len,
                            len0, xs, ds, ls);

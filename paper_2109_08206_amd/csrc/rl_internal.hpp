@@ -126,6 +126,10 @@ struct SolveArgs {
     const int32_t *psplit;  // [n] first bilateral constraint of rod r's P range
     const int32_t *qsplit;  // [n] first bilateral position in rod r's Q list
     const double *cmpv;     // [nc] compliance 1/(kappa h) (bilateral) or -1 (unilateral)
+    // host-visible progress word of the FP64 loop: workgroup 0 of the rod
+    // kernel of iteration k stores 2 k + (1 once the stop is decided), so the
+    // host follows the loop without copies in the stream (may be null)
+    unsigned long long *progress;
 };
 
 // --- kernels launchers (implemented in the .hip files) ----------------------
@@ -163,6 +167,8 @@ struct rl_ctx {
     rl::SolverState *state_host = nullptr;  // pinned
     int *flag_dev = nullptr;                // device error flags
     int64_t *host_scratch = nullptr;        // pinned, for small readbacks
+    unsigned long long *progress_host = nullptr;  // pinned coherent word written by the loop (SolveArgs::progress)
+    unsigned long long *progress_dev = nullptr;   // its device address
     // event sampling of the loop kernels
     static constexpr int kMaxEv = 64;
     int prof_every = 0;

@@ -159,6 +159,14 @@ __global__ void k_unpack_gamma(int64_t nc, const double2 *__restrict__ st, doubl
 }
 
 
+// The loop's progress for the host: one relaxed store at system scope to a
+// word of coherent pinned host memory (a vector store; the host only polls it).
+__device__ __forceinline__ void report_progress(unsigned long long *w, long long k, bool stop)
+{
+    if (w) __hip_atomic_store(w, 2ull * (unsigned long long)k + (stop ? 1ull : 0ull), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // The arrays and sizes that the first loads need lead the argument list
 // (pptr, qptr, st, stq, geo, qgeo, grid size, n: 14 dwords, what the
 // hardware can preload into registers besides the argument block's address),
@@ -192,16 +200,24 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     rod_mob(a, rr, UNI, apar, aperp, rperp);
     DecideIn din{};
     if (MODE == kModeLoop) din = decide_in(a.state, a.alpha_buf, k);
-    if (MODE != kModeApply && a.state->done) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (MODE != kModeApply && a.state->done) {
+        if (MODE == kModeLoop && lead) report_progress(a.progress, k, true);
+        return;
+    }
     if (MODE == kModeLoop) {
         if (k == 0) {
             alpha = a.state->alpha;
-            if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[0] = alpha;
+            if (lead) {
+                a.alpha_buf[0] = alpha;
+                report_progress(a.progress, 0, false);
+            }
         } else {
             double t[4];
             sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
             const Decision d = decide_from(din, k, t);
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (lead) {
+                report_progress(a.progress, k, d.stop);
                 if (d.stop) {
                     SolverState *st = a.state;
                     st->iter = k;
@@ -687,11 +703,19 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         RL_HIP(launch_con<kModeAlpha0>(st, a, 0));
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fin<kModeAlpha0>), dim3(1), dim3(kRodBlock), 0, st, a);
         RL_HIP(hipGetLastError());
+        // The host follows the loop through the progress word that workgroup 0
+        // of each rod kernel stores (2 k + stop), keeping `ahead` iterations
+        // queued past the one running: the GPU never waits for the host, no
+        // copy enters the stream, and at most ahead + 1 iterations are
+        // launched after the stop (they exit at once).
         const int every = p.check_every > 0 ? p.check_every : 32;
-        // Host checks of the stop flag: after each batch of `every` iterations the
-        // state is copied back while `la` more are already queued, so the GPU does
-        // not wait for the host; iterations queued past the stop exit at once.
-        const int la = std::min(every, 8);
+        const long long ahead = std::min(every, 7);
+        volatile unsigned long long *prog = h->progress_host;
+        constexpr unsigned long long kNone = ~0ull;
+        *prog = kNone;
+        a.progress = h->progress_dev;
+        // the stop is decided at k = max_iter at the latest
+        const long long limit = p.max_iter + 1;
         long long launched = 0;
         // event slots of sampled iterations not yet read (no sampling in an
         // allocation-free call: its events would be created on first use)
@@ -699,7 +723,7 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
         bool used[rl_ctx::kMaxEv] = {};
         const int prof_every = h->arena_on ? 0 : h->prof_every;
         auto enqueue = [&](long long count) -> int {
-            for (long long k = 0; k < count; ++k, ++launched) {
+            for (long long k = 0; k < count && launched < limit; ++k, ++launched) {
                 int slot = -1;
                 if (prof_every > 0 && launched % prof_every == 0)
                     for (int v = 0; v < rl_ctx::kMaxEv && slot < 0; ++v)
@@ -715,45 +739,64 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
             }
             return RL_OK;
         };
-        {
-            int rc = enqueue(every);
-            if (rc) return rc;
-            for (;;) {
-                RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
-                RL_HIP(hipEventRecord(h->chk_ev, st));
-                const long long checked = launched;
-                if ((rc = enqueue(la))) return rc;
-                RL_HIP(hipEventSynchronize(h->chk_ev));
-                const bool done = h->state_host->done;
-                // samples before the check have run; those at or after the stop
-                // iteration ran kernels that exited at once
-                const long long valid = done ? h->state_host->iter : checked;
-                int nkeep = 0;
-                for (int u = 0; u < npend; ++u) {
-                    const int v = pend[u];
-                    if (h->ev_iter[v] >= checked) {
-                        pend[nkeep++] = v;
-                        continue;
-                    }
-                    if (h->ev_iter[v] < valid) {
-                        float t0 = 0.f, t1 = 0.f;
-                        if (a.n > 0) RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
-                        RL_HIP(hipEventElapsedTime(&t1, h->ev[v][2], h->ev[v][3]));
-                        h->prof_ms[0] += t0;
-                        h->prof_ms[1] += t1;
-                        h->prof_cnt[0] += 1.0;
-                        h->prof_cnt[1] += 1.0;
-                    }
-                    used[v] = false;
+        // a sampled iteration counts once its kernels have finished and the
+        // loop was still running in it (live < the first iteration known to
+        // be dead, or any earlier one once the stop is known)
+        auto drain = [&](bool all, long long live) -> int {
+            int nkeep = 0;
+            for (int u = 0; u < npend; ++u) {
+                const int v = pend[u];
+                if (!all && (h->ev_iter[v] >= live || hipEventQuery(h->ev[v][3]) != hipSuccess)) {
+                    pend[nkeep++] = v;
+                    continue;
                 }
-                npend = nkeep;
-                if (done) break;
-                if (checked > p.max_iter + every) {
-                    set_error("rl_solve_lcp: stop flag never raised");
-                    return RL_ERR_HIP;
+                if (h->ev_iter[v] < live) {
+                    float t0 = 0.f, t1 = 0.f;
+                    if (a.n > 0) RL_HIP(hipEventElapsedTime(&t0, h->ev[v][0], h->ev[v][1]));
+                    RL_HIP(hipEventElapsedTime(&t1, h->ev[v][2], h->ev[v][3]));
+                    h->prof_ms[0] += t0;
+                    h->prof_ms[1] += t1;
+                    h->prof_cnt[0] += 1.0;
+                    h->prof_cnt[1] += 1.0;
                 }
-                if ((rc = enqueue(every - la))) return rc;
+                used[v] = false;
             }
+            npend = nkeep;
+            return RL_OK;
+        };
+        {
+            int rc = enqueue(ahead + 1);
+            if (rc) return rc;
+            unsigned spins = 0;
+            for (;;) {
+                const unsigned long long w = *prog;
+                const long long cur = w == kNone ? -1 : (long long)(w >> 1);
+                if (w != kNone && (w & 1ull)) break;
+                if (npend && (rc = drain(false, cur))) return rc;
+                if (launched < limit && launched - cur <= ahead) {
+                    if ((rc = enqueue(1))) return rc;
+                    spins = 0;
+                    continue;
+                }
+                if (launched >= limit && ++spins > (1u << 20)) {
+                    // everything is queued: wait for the stream, then the stop
+                    // must have been stored
+                    RL_HIP(hipStreamSynchronize(st));
+                    const unsigned long long w2 = *prog;
+                    if (w2 == kNone || !(w2 & 1ull)) {
+                        set_error("rl_solve_lcp: stop flag never raised");
+                        return RL_ERR_HIP;
+                    }
+                    break;
+                }
+                __builtin_ia32_pause();
+            }
+        }
+        RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipStreamSynchronize(st));
+        {
+            const int rc = drain(true, h->state_host->iter);
+            if (rc) return rc;
         }
         iters = h->state_host->iter;
         if (gamma_out) {
