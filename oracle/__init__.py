@@ -20,6 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rodlcp_oracle.c")
+_SRC_KMC = os.path.join(_HERE, "kmc_oracle.c")
+_SOURCES = (_SRC, _SRC_KMC)
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -40,7 +42,7 @@ _active = "check"
 
 def _compile(out: str, flags) -> None:
     tmp = out + ".tmp"
-    cmd = ["gcc", *flags, "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+    cmd = ["gcc", *flags, "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", tmp, *_SOURCES, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
 
@@ -75,7 +77,7 @@ def _load():
                 _timing_lib = _declare(C.CDLL(out))
             return _timing_lib
         if _lib is None:
-            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SOURCES):
                 build(force=True)
             _lib = _declare(C.CDLL(_LIB))
     return _lib
@@ -113,6 +115,13 @@ def _declare(lib):
     lib.ora_walls.restype = I64
     lib.ora_mobility_pow_block.argtypes = [P, D, D, D, D, P]
     lib.ora_brownian_force.argtypes = [I64, P, P, D, D, D, D, D, P, P]
+    lib.ora_kmc_effective_volume.argtypes = [P]
+    lib.ora_kmc_effective_volume.restype = D
+    lib.ora_kmc_inside_length.argtypes = [I64, P, P, P, D, P, I64, P, D]
+    lib.ora_kmc_inside_length.restype = D
+    lib.ora_kmc_cross_sum.argtypes = [I64, P, P, P, D, P, P, P, I64]
+    lib.ora_kmc_cross_sum.restype = D
+    lib.ora_kmc_step.argtypes = [I64, P, P, P, D, P, P, D, I64, P, P, P, P, P, P, P]
     return lib
 
 
@@ -557,3 +566,74 @@ def stress(x, dir_, length, box, pr: Pairs, cs: Constraints, gamma_pairs, lk: Op
         rc = r - lk.arm[two, :1] * d[lk.p[two]] + lk.arm[two, 1:2] * d[lk.q[two]]
         sl = np.einsum("c,ca,cb->ab", _f64(gamma_links)[two], rc, lg.e[two]) / V
     return sc, sl
+
+
+# --- crosslinker kinetics (kinetic Monte Carlo) ----------------------------------
+
+AVOGADRO_UM3_PER_UM = 602.214076  # molecules per um^3 in a 1 uM solution
+KMC_U, KMC_SA, KMC_SB, KMC_D = 0, 1, 2, 3
+EV_NONE, EV_BIND, EV_UNBIND, EV_CROSS, EV_RELEASE = 0, 1, 2, 3, 4
+
+
+class KmcParams(C.Structure):
+    """Parameters of the crosslinker kinetics (units um, s, pN).  Association
+    constants are volumes (um^3): a constant K in (uM)^-1 is
+    K / AVOGADRO_UM3_PER_UM."""
+    _fields_ = [("eps", C.c_double), ("Ka", C.c_double * 2), ("koS", C.c_double * 2), ("Ke", C.c_double * 2),
+                ("koD", C.c_double * 2), ("kappa", C.c_double), ("rest", C.c_double), ("lam", C.c_double),
+                ("xc", C.c_double), ("kT", C.c_double), ("rcs", C.c_double), ("rcd", C.c_double),
+                ("dU", C.c_double), ("diam", C.c_double), ("dt", C.c_double)]
+
+
+def kmc_params(*, eps, Ka, koS, Ke, koD, kappa, rest, lam, kT, rcs, rcd, dU, diam, dt, xc=0.0) -> KmcParams:
+    pair = lambda v: (C.c_double * 2)(*((v, v) if np.isscalar(v) else v))  # noqa: E731
+    return KmcParams(float(eps), pair(Ka), pair(koS), pair(Ke), pair(koD), float(kappa), float(rest), float(lam),
+                     float(xc), float(kT), float(rcs), float(rcd), float(dU), float(diam), float(dt))
+
+
+def kmc_effective_volume(P: KmcParams) -> float:
+    return float(_load().ora_kmc_effective_volume(C.byref(P)))
+
+
+def kmc_inside_length(x, dir_, length, box, i, point, r) -> float:
+    x, d = _f64(x), _f64(dir_)
+    la, l0 = _len_args(length, x.shape[0])
+    return float(_load().ora_kmc_inside_length(x.shape[0], _p(x), _p(d), _p(la), l0, _p(_box3(box)), int(i),
+                                               _p(_f64(point)), float(r)))
+
+
+def kmc_cross_sum(x, dir_, length, box, P: KmcParams, point, skip=-1) -> float:
+    x, d = _f64(x), _f64(dir_)
+    la, l0 = _len_args(length, x.shape[0])
+    return float(_load().ora_kmc_cross_sum(x.shape[0], _p(x), _p(d), _p(la), l0, _p(_box3(box)), C.byref(P),
+                                           _p(_f64(point)), int(skip)))
+
+
+@dataclass
+class Crosslinkers:
+    """state[m] (KMC_*), rod[m][2] and arc[m][2] (filament and arclength of
+    heads A and B, -1 when unbound), x[m][3] (position: the crosslinker's when
+    unbound, else the bound head's, head A's when both are bound)."""
+    state: np.ndarray
+    rod: np.ndarray
+    arc: np.ndarray
+    x: np.ndarray
+
+    def copy(self) -> "Crosslinkers":
+        return Crosslinkers(self.state.copy(), self.rod.copy(), self.arc.copy(), self.x.copy())
+
+
+def kmc_step(x, dir_, length, box, P: KmcParams, Vbd: float, xl: Crosslinkers, u, xi) -> np.ndarray:
+    """One step of the crosslinker kinetics, in place on xl; returns the
+    event of each crosslinker (EV_*)."""
+    x, d = _f64(x), _f64(dir_)
+    la, l0 = _len_args(length, x.shape[0])
+    m = xl.state.shape[0]
+    for a, dt in ((xl.state, np.int32), (xl.rod, np.int32), (xl.arc, np.float64), (xl.x, np.float64)):
+        assert a.dtype == dt and a.flags.c_contiguous
+    u, xi = _f64(u), _f64(xi)
+    assert u.shape == (m, 4) and xi.shape == (m, 3)
+    ev = np.zeros(m, np.int32)
+    _load().ora_kmc_step(x.shape[0], _p(x), _p(d), _p(la), l0, _p(_box3(box)), C.byref(P), float(Vbd), m,
+                         _p(xl.state), _p(xl.rod), _p(xl.arc), _p(xl.x), _p(u), _p(xi), _p(ev))
+    return ev
