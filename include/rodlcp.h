@@ -447,6 +447,101 @@ int rl_step_adjoint(rl_handle h, int64_t n, const double *x, const double *quat,
                     const double *F, const double *gamma_tape, int64_t tape_len, double *x_bar, double *quat_bar,
                     double *F_bar, double cg_tol, rl_adjoint_info *info);
 
+/* ---------------------------------------------------------------------------
+ * Crosslinker kinetics (kinetic Monte Carlo of binding and unbinding)
+ * ---------------------------------------------------------------------------
+ * Section "2. Crosslinker binding and unbinding" (Table tab:rates) and the
+ * appendix "Kinetic Monte-Carlo" (Table tab:supprates).  A crosslinker is a
+ * Hookean tether between heads A and B, in one of four states: RL_XL_U (both
+ * unbound), RL_XL_SA / RL_XL_SB (one head bound), RL_XL_D (both bound).  In a
+ * step of length h (the handle's dt) every crosslinker makes at most one
+ * transition, with probability 1 - exp(-R h) for the total rate R of its
+ * possible transitions (eq. P_bind), chosen in proportion to the rates:
+ *   U -> S_h : R = k_oS[h] K_a[h] eps 3/(4 pi r_cs^3) sum_i L_in,i, L_in,i the
+ *              length of filament i's axis inside the sphere of radius r_cs
+ *              about the crosslinker (eq. KMC01exp); the head lands
+ *              uniformly on the captured length (filaments in index order).
+ *   S_h -> U : R = k_oS[h]; the crosslinker reappears uniformly in the
+ *              sphere of radius r_cs about the head.
+ *   S_h -> D : the free head g binds a site of another filament within r_cd
+ *              of the bound head: R = k_oD[g] K_e[g] / V_bd sum_sites
+ *              exp(-(kappa/kT)((1 - lambda)/2 Delta^2 - x_c Delta)), Delta =
+ *              l - l_o - D the tether's stretch (eq. Ucl); the site is chosen
+ *              over the filaments in index order, their sites in order.
+ *   D -> S   : head h releases at R = k_oD[h] exp((kappa/kT)(lambda/2
+ *              Delta^2 + x_c Delta)) (eq. KMC_DS_Edep, eq. KMC_SD_fdep).
+ * Sites: floor(eps L) per filament (at least one) at the centres of equal
+ * arclength intervals.  V_bd = 4 pi int_0^r_cd exp(-kappa (r - l_o - D)^2 /
+ * (2 kT)) r^2 dr (eq. double_bind_volume_gen).  Before the transitions the
+ * unbound crosslinkers diffuse, x += sqrt(2 d_U h) xi (Section "1.
+ * Crosslinking motor diffusion and stepping").  Filaments are taken at the
+ * periodic image of their centre nearest to the query point, so L_max/2 +
+ * max(r_cs, r_cd) must not exceed half the box (RL_ERR_ARG).  Association
+ * constants are volumes (um^3; K in 1/uM is K / 602.214 um^3).  Random
+ * numbers are inputs: per crosslinker and step u[m][4] uniform in [0, 1)
+ * (event, which transition, target, reappearance radius) and xi[m][3]
+ * N(0, 1) (diffusion, reappearance direction). */
+#define RL_XL_U 0
+#define RL_XL_SA 1
+#define RL_XL_SB 2
+#define RL_XL_D 3
+#define RL_EV_NONE 0
+#define RL_EV_BIND 1     /* U -> S */
+#define RL_EV_UNBIND 2   /* S -> U */
+#define RL_EV_CROSS 3    /* S -> D */
+#define RL_EV_RELEASE 4  /* D -> S */
+typedef struct {
+    double eps;     /* binding sites per um of filament */
+    double Ka[2];   /* U <-> S association constants of heads A, B (um^3) */
+    double koS[2];  /* S -> U rates (1/s) */
+    double Ke[2];   /* S <-> D association constants (um^3) */
+    double koD[2];  /* D -> S rates without load (1/s) */
+    double kappa;   /* tether stiffness (pN/um) */
+    double rest;    /* tether free length l_o (um) */
+    double lambda;  /* energy factor of the release rate, in [0, 1] */
+    double xc;      /* characteristic length of the force dependence (um) */
+    double kT;      /* thermal energy (pN um), > 0 */
+    double rcs;     /* capture radius of U -> S (um), > 0 */
+    double rcd;     /* cutoff of the S -> D site sum (um), > 0 */
+    double dU;      /* diffusion constant of unbound crosslinkers (um^2/s) */
+} rl_kmc_params;
+
+/* The crosslinkers, device arrays owned by the caller, updated in place:
+ * state[m]; rod[m][2] and arc[m][2] the filament (-1: unbound) and arclength
+ * of heads A and B; x[m][3] the position (the crosslinker's when unbound,
+ * the bound head's in S, head A's in D; in the box). */
+typedef struct {
+    int64_t m;
+    int32_t *state;
+    int32_t *rod;
+    double *arc;
+    double *x;
+} rl_crosslinkers;
+
+/* V_bd of kp with the handle's diameter (host out).  RL_ERR_ARG on bad
+ * parameters. */
+int rl_kmc_effective_volume(rl_handle h, const rl_kmc_params *kp, double *vbd);
+
+/* One step of the kinetics for all crosslinkers against the filaments (x,
+ * dir, len as for rl_build_pairs; not changed).  u, xi: the step's random
+ * numbers (device).  event[m] (device, may be NULL): RL_EV_* per crosslinker.
+ * counts[5] (host, may be NULL): crosslinkers per event.  RL_ERR_ARG on bad
+ * parameters, a bad state or head, or a box below the reach.
+ * Synchronises. */
+int rl_kmc_step(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+                const rl_kmc_params *kp, const rl_crosslinkers *xl, const double *u, const double *xi,
+                int32_t *event, int64_t *counts);
+
+/* The doubly bound crosslinkers as bilateral links (rl_links) for the
+ * filament step: p = head A's filament, q = head B's, arm = their
+ * arclengths, kappa = kp->kappa, rest = kp->rest + diam (the tether's rest
+ * length between the axes, eq. Ucl), in crosslinker order; each array has
+ * room for capacity links.  *n_links (host) gets the count; if it exceeds
+ * capacity nothing is written and RL_ERR_CAPACITY is returned.
+ * Synchronises. */
+int rl_kmc_links(rl_handle h, const rl_kmc_params *kp, const rl_crosslinkers *xl, int64_t capacity, int32_t *p,
+                 int32_t *q, double *arm, double *kappa, double *rest, int64_t *n_links);
+
 /* Kernel timing with HIP events on the handle's stream, for measurement.
  * With every > 0, every every-th BBPGD iteration of later solves records
  * events around its rod kernel and its constraint kernel (iterations after

@@ -162,6 +162,19 @@ static double site_sum(const ora_kmc_params *P, const double *x, const double *d
     const int64_t m = sites_of(P, L);
     double sum = 0.0;
     int64_t last = -1;
+    if (site) *site = -1;
+    /* every site lies on the axis segment: none is within r_cd when the
+     * segment's nearest point is farther (a margin covers rounding) */
+    {
+        double c[3];
+        centre_rel(x, box, j, p, c);
+        const double *d = dir + 3 * j;
+        double t = -(c[0] * d[0] + c[1] * d[1] + c[2] * d[2]);
+        if (t < -0.5 * L) t = -0.5 * L;
+        if (t > 0.5 * L) t = 0.5 * L;
+        const double v[3] = {c[0] + t * d[0], c[1] + t * d[1], c[2] + t * d[2]};
+        if (sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) > P->rcd * (1.0 + 1e-9)) return 0.0;
+    }
     for (int64_t k = 0; k < m; ++k) {
         const double l = site_dist(x, dir, box, j, p, site_arc(L, m, k));
         if (!(l <= P->rcd)) continue;
@@ -260,6 +273,7 @@ void ora_kmc_step(int64_t n, const double *x, const double *dir, const double *l
                     cum += hi - lo;
                     if (cum > t) break;
                 }
+                if (pick < 0) goto done; /* no captured length: cannot happen with R > 0 */
                 double sa = plo + (t - before);
                 if (sa > phi) sa = phi;
                 if (sa < plo) sa = plo;
@@ -313,6 +327,7 @@ void ora_kmc_step(int64_t n, const double *x, const double *dir, const double *l
                         cum += wj;
                         site_sum(P, x, dir, len, len0, box, j, p, -1.0, &site);
                     }
+                    if (pick < 0 || site < 0) goto done; /* no weight: cannot happen with R_on > 0 */
                     const double L = rlen(len, len0, pick);
                     state[c] = KMC_D;
                     rod[2 * c + g] = (int32_t)pick;
@@ -344,6 +359,7 @@ void ora_kmc_step(int64_t n, const double *x, const double *dir, const double *l
                 ev = EV_RELEASE;
             }
         }
+    done:
         if (event) event[c] = ev;
     }
 }

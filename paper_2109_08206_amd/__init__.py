@@ -74,6 +74,31 @@ class StepExtra(C.Structure):
                 ("noise", C.c_void_p), ("kT", C.c_double), ("warm_start", C.c_int32), ("stress", C.c_void_p)]
 
 
+class KmcParams(C.Structure):
+    _fields_ = [("eps", C.c_double), ("Ka", C.c_double * 2), ("koS", C.c_double * 2), ("Ke", C.c_double * 2),
+                ("koD", C.c_double * 2), ("kappa", C.c_double), ("rest", C.c_double), ("lam", C.c_double),
+                ("xc", C.c_double), ("kT", C.c_double), ("rcs", C.c_double), ("rcd", C.c_double),
+                ("dU", C.c_double)]
+
+
+def kmc_params(*, eps, Ka, koS, Ke, koD, kappa, rest, lam, kT, rcs, rcd, dU, xc=0.0) -> KmcParams:
+    """rl_kmc_params; Ka, koS, Ke, koD a number (both heads) or a pair (A, B).
+    Association constants in um^3."""
+    pair = lambda v: (C.c_double * 2)(*((float(v), float(v)) if isinstance(v, (int, float)) else  # noqa: E731
+                                       (float(v[0]), float(v[1]))))
+    return KmcParams(float(eps), pair(Ka), pair(koS), pair(Ke), pair(koD), float(kappa), float(rest), float(lam),
+                     float(xc), float(kT), float(rcs), float(rcd), float(dU))
+
+
+class RLCrosslinkers(C.Structure):
+    _fields_ = [("m", C.c_int64), ("state", C.c_void_p), ("rod", C.c_void_p), ("arc", C.c_void_p),
+                ("x", C.c_void_p)]
+
+
+XL_U, XL_SA, XL_SB, XL_D = 0, 1, 2, 3
+EV_NONE, EV_BIND, EV_UNBIND, EV_CROSS, EV_RELEASE = 0, 1, 2, 3, 4
+
+
 class AdjointInfo(C.Structure):
     _fields_ = [("cg_iterations", C.c_int64), ("cg_residual", C.c_double), ("n_active", C.c_int64),
                 ("status", C.c_int32), ("solve_status", C.c_int32), ("solve_iterations", C.c_int64),
@@ -84,7 +109,8 @@ SYMBOLS = ("rl_create", "rl_destroy", "rl_set_params", "rl_get_params", "rl_set_
            "rl_status_str", "rl_last_error", "rl_directors", "rl_build_pairs", "rl_assemble_D", "rl_apply_M",
            "rl_solve_lcp", "rl_step", "rl_profile_enable", "rl_profile_read", "rl_solve_lcp_batched",
            "rl_batch_tuning", "rl_solve_lcp_adjoint", "rl_step_adjoint", "rl_solve_lcp_noalloc",
-           "rl_assemble_links", "rl_solve_general", "rl_assemble_walls")
+           "rl_assemble_links", "rl_solve_general", "rl_assemble_walls", "rl_kmc_effective_volume", "rl_kmc_step",
+           "rl_kmc_links")
 
 
 def load(path: Optional[str] = None) -> C.CDLL:
@@ -129,6 +155,11 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_solve_lcp_adjoint": ([H, I64, P, P, D, I64, P, P, P, P, P, P, P, P, D, P, P, P, P, P,
                                       C.POINTER(AdjointInfo)], C.c_int),
             "rl_step_adjoint": ([H, I64, P, P, P, D, P, P, I64, P, P, P, D, C.POINTER(AdjointInfo)], C.c_int),
+            "rl_kmc_effective_volume": ([H, C.POINTER(KmcParams), C.POINTER(C.c_double)], C.c_int),
+            "rl_kmc_step": ([H, I64, P, P, P, D, C.POINTER(KmcParams), C.POINTER(RLCrosslinkers), P, P, P,
+                             C.POINTER(C.c_int64)], C.c_int),
+            "rl_kmc_links": ([H, C.POINTER(KmcParams), C.POINTER(RLCrosslinkers), I64, P, P, P, P, P,
+                              C.POINTER(C.c_int64)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -411,6 +442,53 @@ class Solver:
             _ptr(arm), _ptr(phi), _ptr(q), _ptr(fl), C.byref(cnt)), "rl_assemble_walls")
         m = int(cnt.value)
         return rod[:m], e[:m], arm[:m], phi[:m], q[:m], fl[:m]
+
+    def kmc_effective_volume(self, kp: KmcParams) -> float:
+        out = C.c_double(0.0)
+        self._check(self.lib.rl_kmc_effective_volume(self._h, C.byref(kp), C.byref(out)), "rl_kmc_effective_volume")
+        return float(out.value)
+
+    @staticmethod
+    def _xl_struct(state, rod, arc, x):
+        torch = _torch()
+        m = state.shape[0]
+        return RLCrosslinkers(m, _ptr(state, torch.int32, (m,), "state"), _ptr(rod, torch.int32, (m, 2), "rod"),
+                              _ptr(arc, torch.float64, (m, 2), "arc"), _ptr(x, torch.float64, (m, 3), "x"))
+
+    def kmc_step(self, x, dir_, length, kp: KmcParams, state, rod, arc, xl, u, xi, event=None):
+        """One step of the crosslinker kinetics; (state, rod, arc, xl) are
+        updated in place.  Returns the counts of each event (5 ints)."""
+        torch = _torch()
+        n, m = x.shape[0], state.shape[0]
+        la, l0 = _len_args(length, n)
+        X = self._xl_struct(state, rod, arc, xl)
+        counts = (C.c_int64 * 5)()
+        self._stream()
+        self._check(self.lib.rl_kmc_step(
+            self._h, n, _ptr(x, torch.float64, (n, 3), "x"), _ptr(dir_, torch.float64, (n, 3), "dir"), la, l0,
+            C.byref(kp), C.byref(X), _ptr(u, torch.float64, (m, 4), "u"), _ptr(xi, torch.float64, (m, 3), "xi"),
+            _ptr(event, torch.int32, (m,), "event"), counts), "rl_kmc_step")
+        return [int(v) for v in counts]
+
+    def kmc_links(self, kp: KmcParams, state, rod, arc, capacity=None):
+        """The doubly bound crosslinkers as links: (p, q, arm, kappa, rest)."""
+        torch = _torch()
+        m = state.shape[0]
+        cap = int(capacity) if capacity is not None else m
+        dev = state.device
+        p = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        q = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        arm = torch.empty((max(cap, 1), 2), dtype=torch.float64, device=dev)
+        kap = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        rest = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        X = RLCrosslinkers(m, _ptr(state, torch.int32, (m,), "state"), _ptr(rod, torch.int32, (m, 2), "rod"),
+                           _ptr(arc, torch.float64, (m, 2), "arc"), None)
+        cnt = C.c_int64(0)
+        self._stream()
+        self._check(self.lib.rl_kmc_links(self._h, C.byref(kp), C.byref(X), cap, _ptr(p), _ptr(q), _ptr(arm),
+                                          _ptr(kap), _ptr(rest), C.byref(cnt)), "rl_kmc_links")
+        k = int(cnt.value)
+        return p[:k], q[:k], arm[:k], kap[:k], rest[:k]
 
     def solve_general(self, dir_, length, pi, pj, e, arm, q, kind, cmp, F=None, gamma=None, U=None):
         """Mixed unilateral/bilateral problem over a general list (any order;

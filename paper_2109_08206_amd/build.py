@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librodlcp.so")
-SOURCES = ["rl_api.hip", "rl_geometry.hip", "rl_solver.hip", "rl_mixed.hip", "rl_batched.hip", "rl_sort.hip", "rl_adjoint.hip", "rl_general.hip"]
+SOURCES = ["rl_api.hip", "rl_geometry.hip", "rl_solver.hip", "rl_mixed.hip", "rl_batched.hip", "rl_sort.hip", "rl_adjoint.hip", "rl_general.hip", "rl_kmc.hip"]
 ARCH = os.environ.get("RODLCP_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

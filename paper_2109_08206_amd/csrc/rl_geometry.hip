@@ -737,6 +737,108 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     return RL_OK;
 }
 
+int rod_cells(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+              double radius, RodCells *out)
+{
+    hipStream_t st = h->stream;
+    const rl_params &p = h->prm;
+    int werr = 0;
+    double Lmax = len0;
+    RL_HIP(hipMemsetAsync(h->flag_dev, 0, sizeof(int) * 4, st));
+    if (len && n > 0) {
+        auto *lm = (unsigned long long *)ws_get(h, kWsLenMax, sizeof(unsigned long long), &werr);
+        if (werr) return werr;
+        RL_HIP(hipMemsetAsync(lm, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_len_max, dim3(grid_of(n)), dim3(kBlock), 0, st, n, len, lm, h->flag_dev);
+        RL_HIP(hipGetLastError());
+        RL_HIP(hipMemcpyAsync(h->host_scratch, lm, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipMemcpyAsync(h->host_scratch + 1, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+        RL_HIP(hipStreamSynchronize(st));
+        if (((int *)(h->host_scratch + 1))[0] & 4) {
+            set_error("rod cells: rod lengths must be finite and > 0");
+            return RL_ERR_ARG;
+        }
+        unsigned long long bits = (unsigned long long)h->host_scratch[0];
+        std::memcpy(&Lmax, &bits, sizeof(double));
+    } else if (!(len0 > 0.0)) {
+        set_error("rod cells: len0 must be > 0");
+        return RL_ERR_ARG;
+    }
+    const double reach = 0.5 * Lmax + radius;
+    GridDev g;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(2.0 * reach <= p.box[a])) {
+            set_error("rod cells: half the longest rod plus the radius %g exceeds half the box edge %g", reach,
+                      0.5 * p.box[a]);
+            return RL_ERR_ARG;
+        }
+        int nca = (int)floor(p.box[a] / reach);
+        if (nca < 1) nca = 1;
+        if (nca > 1024) nca = 1024;
+        g.nc[a] = nca;
+        g.cell[a] = p.box[a] / nca;
+        g.S[a] = 1;
+        g.box[a] = p.box[a];
+        ncell *= nca;
+    }
+    if (ncell > (1 << 26)) {
+        set_error("rod cells: too many cells (%lld)", (long long)ncell);
+        return RL_ERR_ARG;
+    }
+    const int64_t nb = n > 0 ? n : 1;
+    int *cell_of = (int *)ws_get(h, kWsCellOf, sizeof(int) * nb, &werr);
+    int *cell_cnt = (int *)ws_get(h, kWsCellCnt, sizeof(int) * ncell, &werr);
+    int *cell_start = (int *)ws_get(h, kWsCellStart, sizeof(int) * (ncell + 1), &werr);
+    int *sorted = (int *)ws_get(h, kWsSorted, sizeof(int) * nb, &werr);
+    int *cell_key = (int *)ws_get(h, kWsCellKey, sizeof(int) * nb, &werr);
+    double *xs = (double *)ws_get(h, kWsXs, sizeof(double) * 3 * nb, &werr);
+    double *ds = (double *)ws_get(h, kWsDs, sizeof(double) * 3 * nb, &werr);
+    double *ls = (double *)ws_get(h, kWsLs, sizeof(double) * nb, &werr);
+    if (werr) return werr;
+    RL_HIP(hipMemsetAsync(cell_cnt, 0, sizeof(int) * ncell, st));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin, dim3(grid_of(n)), dim3(kBlock), 0, st, n, x, dir, g, 0, cell_of, cell_cnt,
+                           h->flag_dev);
+        RL_HIP(hipGetLastError());
+    }
+    {
+        const int rc = device_scan(h, cell_cnt, ncell, cell_start, nullptr);
+        if (rc) return rc;
+    }
+    if (n > 0) {
+        int cbits = 1;
+        while ((1LL << cbits) < ncell) ++cbits;
+        const int rc = stable_sort_by_key(h, n, cell_of, cbits, cell_key, sorted);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_gather_rods, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)sorted, x, dir, len,
+                           len0, xs, ds, ls);
+        RL_HIP(hipGetLastError());
+    }
+    RL_HIP(hipMemcpyAsync(h->host_scratch + 1, h->flag_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipStreamSynchronize(st));
+    const int ferr = ((int *)(h->host_scratch + 1))[0];
+    if (ferr & 1) {
+        set_error("rod cells: non-finite centre or director");
+        return RL_ERR_NONFINITE;
+    }
+    if (ferr & 2) {
+        set_error("rod cells: a centre lies outside [0, box)");
+        return RL_ERR_ARG;
+    }
+    for (int a = 0; a < 3; ++a) {
+        out->nc[a] = g.nc[a];
+        out->cell[a] = g.cell[a];
+        out->box[a] = g.box[a];
+    }
+    out->start = cell_start;
+    out->order = sorted;
+    out->xs = xs;
+    out->ds = ds;
+    out->ls = ls;
+    return RL_OK;
+}
+
 int build_pairs_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                      int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs)
 {

@@ -211,6 +211,7 @@ enum Slot : int {
     kWsGenPsplit, kWsGenQsplit, kWsLinkLen, kWsLinkFlags, kWsInvPerm, kWsWallCnt, kWsWallOff,
     kWsCatPi, kWsCatPj, kWsCatE, kWsCatArm, kWsCatQ, kWsCatKind, kWsCatCmp, kWsCatLen, kWsStepUnc,
     kWsFtot, kWsWarmKeys, kWsWarmGam, kWsWarmKeysNew, kWsWarmGamNew, kWsStress,
+    kWsKmcCount, kWsKmcFlag, kWsKmcOff,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");
@@ -227,6 +228,20 @@ int build_pairs_impl(rl_ctx *h, int64_t n, const double *x, const double *dir, c
                      int64_t capacity, int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags, int64_t *n_pairs);
 hipError_t launch_gather6(hipStream_t st, int64_t n, const int *perm, const double *src, double *dst);
 int stable_sort_by_key(rl_ctx *h, int64_t n, const int *keys, int bits, int *keys_out, int *perm);
+
+// Filaments binned by centre into periodic cells of edge >= L_max/2 +
+// radius, for queries of the filaments whose axis passes within `radius` of
+// a point (the nearest image of each centre; RL_ERR_ARG when L_max/2 +
+// radius exceeds half the box).  Rods in cell order, stable by index.
+struct RodCells {
+    int nc[3];
+    double cell[3], box[3];
+    const int *start;             // [ncell + 1]
+    const int *order;             // cell position -> caller's index
+    const double *xs, *ds, *ls;   // centres, directors, lengths in cell order
+};
+int rod_cells(rl_ctx *h, int64_t n, const double *x, const double *dir, const double *len, double len0,
+              double radius, RodCells *out);
 // out[0..m] = exclusive prefix sums of in[0..m-1] (out[m] = the total, also
 // written to *total when given), on the handle's stream.  tmp (may be null:
 // taken from the workspace) holds scan_tmp_bytes(m) bytes.

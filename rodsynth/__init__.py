@@ -385,3 +385,22 @@ def cfg_hub(seed: int = 0, crossers: int = 36) -> RodSystem:
         force[i, 2] -= 2.0
         k += 1
     return RodSystem(x=x, quat=quat, length=lens, force=force, box=10.0, name="hub")
+
+
+# --- crosslinkers ---------------------------------------------------------------
+
+def crosslinker_positions(m: int, box: float, seed: int = 0) -> np.ndarray:
+    """m unbound crosslinkers uniform in the periodic box, from
+    PCG64([seed, 12])."""
+    rng = np.random.Generator(np.random.PCG64([seed, 12]))
+    x = rng.random((m, 3)) * box
+    return np.ascontiguousarray(np.where(x >= box, 0.0, x))
+
+
+def kmc_draws(m: int, seed: int, step: int):
+    """The random numbers of one kinetics step: u[m][4] uniform in [0, 1) and
+    xi[m][3] standard normal, from PCG64([seed, 13, step])."""
+    rng = np.random.Generator(np.random.PCG64([seed, 13, step]))
+    u = rng.random((m, 4))
+    xi = rng.standard_normal((m, 3))
+    return np.ascontiguousarray(u), np.ascontiguousarray(xi)
