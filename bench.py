@@ -369,6 +369,123 @@ def form_adjoint(args, torch, rl, rodsynth) -> dict:
     }
 
 
+def form_kmc(args, torch, rl, rodsynth) -> dict:
+    """Crosslinker kinetics on the paper-scale suspension: 400,000
+    crosslinkers with the kinesin-5 parameters of the crosslinker table on
+    the 100,000 nematic filaments, whole kinetics steps (filament binning and
+    every crosslinker's transition) with the step's random numbers resident;
+    then the coupled step of the method (kinetics, the doubly bound
+    crosslinkers as links, the filament step with contacts, links and
+    Brownian forces)."""
+    dev = torch.device("cuda:0")
+    s = rodsynth.cfg_paper_scale(args.seed)
+    m = args.crosslinkers
+    um3 = 602.214076
+    kw = dict(eps=1625.0, Ka=90.9 / um3, koS=0.11, Ke=90.9 / um3, koD=0.11, kappa=300.0, rest=0.053, lam=0.258,
+              kT=4.11e-3, rcs=0.039, rcd=0.11, dU=1.0)
+    kp = rl.kmc_params(**kw)
+    x = torch.as_tensor(s.x, device=dev)
+    quat = torch.as_tensor(s.quat, device=dev)
+    F = torch.as_tensor(s.force, device=dev)
+    slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8, max_iter=200_000)
+    d = slv.directors(quat)
+    state = torch.zeros(m, dtype=torch.int32, device=dev)
+    rod = torch.full((m, 2), -1, dtype=torch.int32, device=dev)
+    arc = torch.zeros((m, 2), dtype=torch.float64, device=dev)
+    xl = torch.as_tensor(rodsynth.crosslinker_positions(m, s.box, args.seed), device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+
+    def draws(k):
+        return ([torch.rand((m, 4), dtype=torch.float64, device=dev, generator=gen) for _ in range(k)],
+                [torch.randn((m, 3), dtype=torch.float64, device=dev, generator=gen) for _ in range(k)])
+
+    # populate: steps of the same kinetics until the states settle
+    us, xis = draws(args.kmc_populate)
+    for k in range(args.kmc_populate):
+        slv.kmc_step(x, d, 1.0, kp, state, rod, arc, xl, us[k], xis[k])
+    us, xis = draws(args.warmup + args.steps)
+    for k in range(args.warmup):
+        slv.kmc_step(x, d, 1.0, kp, state, rod, arc, xl, us[k], xis[k])
+    torch.cuda.synchronize()
+    ev = [0] * 5
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        c = slv.kmc_step(x, d, 1.0, kp, state, rod, arc, xl, us[k], xis[k])
+        ev = [a + b for a, b in zip(ev, c)]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    occupancy = [int((state == k).sum()) for k in range(4)]
+    # the coupled step: kinetics, links, filament step (contacts + links + Brownian)
+    noise_gen = torch.Generator(device=dev)
+    noise_gen.manual_seed(args.seed + 1)
+    xs, qs = x.clone(), quat.clone()
+    pipe = []
+    nlinks = 0
+    for k in range(3):
+        u1, xi1 = draws(1)
+        noise = torch.randn((s.n, 6), dtype=torch.float64, device=dev, generator=noise_gen)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dk = slv.directors(qs)
+        slv.kmc_step(xs, dk, 1.0, kp, state, rod, arc, xl, u1[0], xi1[0])
+        p, q, arm, kap, rest = slv.kmc_links(kp, state, rod, arc)
+        nlinks = int(p.shape[0])
+        _, info, _ = slv.step(xs, qs, 1.0, F=F, links=(p, q, arm, kap, rest, None), noise=noise, kT=kw["kT"])
+        torch.cuda.synchronize()
+        pipe.append(time.perf_counter() - t1)
+    slv.close()
+    out = {
+        "metric": "crosslinker kinetics: crosslinker updates per second (binding/unbinding kinetic Monte Carlo)",
+        "value": m / el, "unit": "crosslinker updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{m} crosslinkers (kinesin-5 parameters of the crosslinker table: eps 1625/um, "
+                               f"K_a = K_e = 90.9/uM, k_o = 0.11/s, kappa 300 pN/um, l_o 53 nm, lambda 0.258, "
+                               f"r_cs 39 nm, r_cd 110 nm) on {s.n} filaments L=1 phi=0.05 nematic vMF kappa=20",
+                   "crosslinkers": m, "rods": s.n, "box": round(s.box, 4), "seed": args.seed},
+        "states_U_SA_SB_D": occupancy, "events_per_step": [e / args.steps for e in ev],
+        "coupled_step": {"ms": [round(1e3 * v, 3) for v in pipe], "links": nlinks,
+                         "what": "kinetics + links of the doubly bound + filament step (contacts, links, "
+                                 "Brownian force) to residual 1e-8",
+                         "last_status": info.status, "last_iterations": info.iterations},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = kmc_cpu_baseline(s, kw, state, rod, arc, xl)
+    return out
+
+
+def kmc_cpu_baseline(s, kw, state, rod, arc, xl) -> dict:
+    """The oracle's kinetics step (every crosslinker against every
+    filament) on 2,000 crosslinkers sampled across the four states."""
+    import numpy as np
+
+    import oracle
+    prev = oracle.use_build("timing")
+    try:
+        st = state.cpu().numpy()
+        rng = np.random.default_rng(0)
+        pick = np.concatenate([rng.choice(np.flatnonzero(st == k), min(500, int((st == k).sum())), replace=False)
+                               for k in range(4) if (st == k).any()])
+        sub = oracle.Crosslinkers(st[pick].copy(), rod.cpu().numpy()[pick].copy(),
+                                  np.ascontiguousarray(arc.cpu().numpy()[pick]),
+                                  np.ascontiguousarray(xl.cpu().numpy()[pick]))
+        ko = oracle.kmc_params(diam=s.diam, dt=s.dt, **kw)
+        vbd = oracle.kmc_effective_volume(ko)
+        d = oracle.directors(s.quat)
+        u = rng.random((pick.size, 4))
+        xi = rng.standard_normal((pick.size, 3))
+        t0 = time.perf_counter()
+        oracle.kmc_step(s.x, d, 1.0, s.box, ko, vbd, sub, u, xi)
+        el = time.perf_counter() - t0
+    finally:
+        oracle.use_build(prev)
+    return {"value": pick.size / el, "unit": "crosslinker updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one kinetics step of {pick.size} crosslinkers (500 per state) against all {s.n} filaments "
+                      f"(the oracle tests every filament), {el:.2f} s, -O3 -march=native",
+            "cpu_model": _cpu_model()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,7 +496,7 @@ def main() -> int:
     ap.add_argument("--profile-every", type=int, default=32, help="sample kernel events every k-th iteration (each sample costs a few us of launch overhead)")
     ap.add_argument("--cpu-iters", type=int, default=800, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["step", "precision", "batched", "adjoint"], default="step",
+    ap.add_argument("--form", choices=["step", "precision", "batched", "adjoint", "kmc"], default="step",
                     help="step: the FP64 whole-step benchmark (default); precision: FP32-mixed vs FP64; "
                          "batched: many systems in one batched solve; adjoint: gradient of a rollout")
     ap.add_argument("--rollout-steps", type=int, default=100, help="adjoint form: rollout length")
@@ -388,6 +505,8 @@ def main() -> int:
     ap.add_argument("--no-tape", action="store_true",
                     help="adjoint form: re-solve each step cold in the backward pass instead of replaying gamma")
     ap.add_argument("--phi", type=float, default=None, help="volume fraction override (precision form)")
+    ap.add_argument("--crosslinkers", type=int, default=400_000, help="kmc form: crosslinkers")
+    ap.add_argument("--kmc-populate", type=int, default=50, help="kmc form: untimed steps that populate the states")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 1 GiB device buffer once (reference for HBM counters)")
     args = ap.parse_args()
@@ -412,6 +531,9 @@ def main() -> int:
         return 0
     if args.form == "adjoint":
         print(json.dumps(form_adjoint(args, torch, rl, rodsynth)), flush=True)
+        return 0
+    if args.form == "kmc":
+        print(json.dumps(form_kmc(args, torch, rl, rodsynth)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     s = rodsynth.cfg_paper_scale(args.seed, n=args.rods)

@@ -211,7 +211,7 @@ enum Slot : int {
     kWsGenPsplit, kWsGenQsplit, kWsLinkLen, kWsLinkFlags, kWsInvPerm, kWsWallCnt, kWsWallOff,
     kWsCatPi, kWsCatPj, kWsCatE, kWsCatArm, kWsCatQ, kWsCatKind, kWsCatCmp, kWsCatLen, kWsStepUnc,
     kWsFtot, kWsWarmKeys, kWsWarmGam, kWsWarmKeysNew, kWsWarmGamNew, kWsStress,
-    kWsKmcCount, kWsKmcFlag, kWsKmcOff,
+    kWsKmcCount, kWsKmcFlag, kWsKmcOff, kWsKmcKey, kWsKmcKeyOut, kWsKmcPerm,
     kWsCount  // number of slots; must not exceed rl_ctx::kSlots
 };
 static_assert(kWsCount <= rl_ctx::kSlots, "workspace slot table too small");

@@ -221,15 +221,47 @@ __global__ void __launch_bounds__(kKmcBlock) k_kmc_check(KmcArgs A, int *__restr
     if (!ok) atomicOr(flag, 1);
 }
 
-__global__ void __launch_bounds__(kKmcBlock) k_kmc(KmcArgs A)
+// Processing order: crosslinkers with one head bound first, then unbound,
+// then doubly bound (the three cost very differently), each class by the
+// cell of its query point, so that the lanes of a wave scan the same cells
+// together and their loads of a filament's record coincide.
+__global__ void k_kmc_keys(KmcArgs A, int *__restrict__ key)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= A.m) return;
+    const int s = A.state[c];
+    int cls = 2;
+    double p[3] = {0.0, 0.0, 0.0};
+    if (s == RL_XL_SA || s == RL_XL_SB) {
+        const int hd = s == RL_XL_SA ? 0 : 1;
+        axis_point(A, A.rod[2 * c + hd], A.arc[2 * c + hd], p);
+        cls = 0;
+    } else if (s == RL_XL_U) {
+        for (int a = 0; a < 3; ++a) p[a] = wrap1(A.xl[3 * c + a], A.box[a]);
+        cls = 1;
+    }
+    int id = 0;
+    if (cls < 2) {
+        int k[3];
+        for (int a = 0; a < 3; ++a) {
+            int v = (int)floor(p[a] / A.cell[a]);
+            k[a] = v < 0 ? 0 : (v >= A.nc[a] ? A.nc[a] - 1 : v);
+        }
+        id = (k[0] * A.nc[1] + k[1]) * A.nc[2] + k[2];
+    }
+    key[c] = (cls << 26) | id;
+}
+
+__global__ void __launch_bounds__(kKmcBlock) k_kmc(KmcArgs A, const int *__restrict__ perm)
 {
     __shared__ KmcList S;
     __shared__ unsigned cnt[5];
     const int lane = threadIdx.x;
     if (lane < 5) cnt[lane] = 0;
     __syncthreads();
-    const int64_t c = blockIdx.x * (int64_t)kKmcBlock + lane;
-    if (c < A.m) {
+    const int64_t t = blockIdx.x * (int64_t)kKmcBlock + lane;
+    if (t < A.m) {
+        const int64_t c = perm[t];
         const rl_kmc_params &P = A.P;
         const double *uc = A.u + 4 * c, *xc = A.xi + 3 * c;
         int ev = RL_EV_NONE;
@@ -581,8 +613,16 @@ int rl_kmc_step(rl_handle h, int64_t n, const double *x, const double *dir, cons
     A.xs = cells.xs;
     A.ds = cells.ds;
     A.ls = cells.ls;
+    int *key = (int *)ws_get(h, kWsKmcKey, sizeof(int) * m, &werr);
+    int *key_out = (int *)ws_get(h, kWsKmcKeyOut, sizeof(int) * m, &werr);
+    int *perm = (int *)ws_get(h, kWsKmcPerm, sizeof(int) * m, &werr);
+    if (werr) return werr;
+    hipLaunchKernelGGL(k_kmc_keys, dim3(grid_of(m, 256)), dim3(256), 0, st, A, key);
+    RL_HIP(hipGetLastError());
+    rc = stable_sort_by_key(h, m, key, 28, key_out, perm);
+    if (rc) return rc;
     RL_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * 8, st));
-    hipLaunchKernelGGL(k_kmc, dim3(grid_of(m, kKmcBlock)), dim3(kKmcBlock), 0, st, A);
+    hipLaunchKernelGGL(k_kmc, dim3(grid_of(m, kKmcBlock)), dim3(kKmcBlock), 0, st, A, (const int *)perm);
     RL_HIP(hipGetLastError());
     RL_HIP(hipMemcpyAsync(h->host_scratch, cnt, sizeof(unsigned long long) * 5, hipMemcpyDeviceToHost, st));
     RL_HIP(hipStreamSynchronize(st));
