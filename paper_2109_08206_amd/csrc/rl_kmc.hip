@@ -3,14 +3,14 @@
 // "Kinetic Monte-Carlo", Table tab:supprates).
 //
 // Every crosslinker is independent of the others within a step (steric
-// interactions between motors are neglected), so the step is one lane per
-// crosslinker.  A lane finds the filaments near its query point (the
-// crosslinker, or its bound head) through a periodic cell list of filament
-// centres, accumulates the rate of each possible transition, decides with
-// its own uniform numbers, and for a binding walks the candidates in
-// filament-index order (inverse transform): their weights are kept in a
-// small per-lane list in LDS, sorted by index before the walk; a lane with
-// more candidates than the list holds walks by repeated search instead.
+// interactions between motors are neglected).  The crosslinkers are first
+// ordered by (state class, cell of the query point).  A crosslinker with at
+// most one head bound gets a wave: its lanes share the filaments of the 27
+// cells around the query point (the crosslinker, or its bound head), keep
+// those whose axis passes within the query radius, and sum the sites of the
+// kept ones; one lane then decides with the crosslinker's uniform numbers
+// and, for a binding, walks the kept filaments in index order (inverse
+// transform).  A doubly bound crosslinker needs only its two heads: one lane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,8 +24,7 @@
 
 namespace rl {
 
-constexpr int kKmcBlock = 64;   // crosslinkers per workgroup (one wave)
-constexpr int kKmcList = 32;    // candidates a lane keeps in LDS
+constexpr int kKmcBlock = 64;   // crosslinkers per workgroup of the check
 
 static inline unsigned grid_of(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -152,57 +151,6 @@ __device__ double site_sum(const KmcArgs &A, int64_t j, const double p[3], doubl
     return sum;
 }
 
-// the filaments whose centres lie in the cells around p (each once): f(j)
-template <class Fn>
-__device__ __forceinline__ void for_candidates(const KmcArgs &A, const double p[3], Fn f)
-{
-    int lo[3], cnt[3];
-    for (int a = 0; a < 3; ++a) {
-        int c = (int)floor(p[a] / A.cell[a]);
-        c = c < 0 ? 0 : (c >= A.nc[a] ? A.nc[a] - 1 : c);
-        if (A.nc[a] >= 3) {
-            lo[a] = c - 1;
-            cnt[a] = 3;
-        } else {
-            lo[a] = 0;
-            cnt[a] = A.nc[a];
-        }
-    }
-    for (int ix = 0; ix < cnt[0]; ++ix) {
-        const int wx = (lo[0] + ix + A.nc[0]) % A.nc[0];
-        for (int iy = 0; iy < cnt[1]; ++iy) {
-            const int wy = (lo[1] + iy + A.nc[1]) % A.nc[1];
-            for (int iz = 0; iz < cnt[2]; ++iz) {
-                const int wz = (lo[2] + iz + A.nc[2]) % A.nc[2];
-                const int w = (wx * A.nc[1] + wy) * A.nc[2] + wz;
-                for (int q = A.start[w]; q < A.start[w + 1]; ++q) f(q, A.order[q]);
-            }
-        }
-    }
-}
-
-// the lane's candidate list: index and weight, [slot][lane]
-struct KmcList {
-    int idx[kKmcList][kKmcBlock];
-    double w[kKmcList][kKmcBlock];
-};
-
-__device__ __forceinline__ void list_sort(KmcList &S, int lane, int K)
-{
-    for (int a = 1; a < K; ++a) {
-        const int ki = S.idx[a][lane];
-        const double kw = S.w[a][lane];
-        int b = a - 1;
-        while (b >= 0 && S.idx[b][lane] > ki) {
-            S.idx[b + 1][lane] = S.idx[b][lane];
-            S.w[b + 1][lane] = S.w[b][lane];
-            --b;
-        }
-        S.idx[b + 1][lane] = ki;
-        S.w[b + 1][lane] = kw;
-    }
-}
-
 __global__ void __launch_bounds__(kKmcBlock) k_kmc_check(KmcArgs A, int *__restrict__ flag)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -223,9 +171,8 @@ __global__ void __launch_bounds__(kKmcBlock) k_kmc_check(KmcArgs A, int *__restr
 
 // Processing order: crosslinkers with one head bound first, then unbound,
 // then doubly bound (the three cost very differently), each class by the
-// cell of its query point, so that the lanes of a wave scan the same cells
-// together and their loads of a filament's record coincide.
-__global__ void k_kmc_keys(KmcArgs A, int *__restrict__ key)
+// cell of its query point.  heavy[0] counts the first two classes.
+__global__ void k_kmc_keys(KmcArgs A, int *__restrict__ key, int *__restrict__ heavy)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= A.m) return;
@@ -248,218 +195,274 @@ __global__ void k_kmc_keys(KmcArgs A, int *__restrict__ key)
             k[a] = v < 0 ? 0 : (v >= A.nc[a] ? A.nc[a] - 1 : v);
         }
         id = (k[0] * A.nc[1] + k[1]) * A.nc[2] + k[2];
+        atomicAdd(heavy, 1);
     }
     key[c] = (cls << 26) | id;
 }
 
-__global__ void __launch_bounds__(kKmcBlock) k_kmc(KmcArgs A, const int *__restrict__ perm)
+__device__ __forceinline__ double wave_sum(double v)
 {
-    __shared__ KmcList S;
-    __shared__ unsigned cnt[5];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Crosslinkers without both heads bound: one wave each (a 64-thread
+// workgroup), its lanes sharing the candidate filaments of the 27 cells
+// around the query point.  A candidate is kept when its axis passes within
+// the query radius; the kept ones go to an LDS list, sorted by filament
+// index, over which the rate is summed and the binding walks, in the order
+// the method defines.  The S -> D weight of a kept filament is summed over
+// its sites by all lanes.
+constexpr int kNearCap = 128;
+
+__global__ void __launch_bounds__(64) k_kmc_heavy(KmcArgs A, const int *__restrict__ perm, int nheavy,
+                                                  int *__restrict__ err)
+{
+    __shared__ int cstart[27], cpre[28];
+    __shared__ int nnear;
+    __shared__ int nidx[kNearCap], sidx[kNearCap];
+    __shared__ double nw[kNearCap], sw[kNearCap];
     const int lane = threadIdx.x;
-    if (lane < 5) cnt[lane] = 0;
+    if ((int)blockIdx.x >= nheavy) return;
+    const int64_t c = perm[blockIdx.x];
+    const rl_kmc_params &P = A.P;
+    const double *uc = A.u + 4 * c, *xc = A.xi + 3 * c;
+    const int s = A.state[c];
+    const bool unb = s == RL_XL_U;
+    const int hd = s == RL_XL_SB ? 1 : 0, g = 1 - hd;
+    const int own = unb ? -1 : A.rod[2 * c + hd];
+    // query point: the diffused crosslinker, or the bound head
+    double p[3];
+    if (unb) {
+        const double hop = sqrt(2.0 * P.dU * A.dt);
+        for (int a = 0; a < 3; ++a) p[a] = wrap1(A.xl[3 * c + a] + hop * xc[a], A.box[a]);
+    } else {
+        axis_point(A, own, A.arc[2 * c + hd], p);
+    }
+    const double r = unb ? P.rcs : P.rcd;
+    // the distinct cells around p (fewer than 27 when a direction has < 3)
+    int lo[3], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        int v = (int)floor(p[a] / A.cell[a]);
+        v = v < 0 ? 0 : (v >= A.nc[a] ? A.nc[a] - 1 : v);
+        lo[a] = A.nc[a] >= 3 ? v - 1 : 0;
+        cnt[a] = A.nc[a] >= 3 ? 3 : A.nc[a];
+    }
+    const int ncl = cnt[0] * cnt[1] * cnt[2];
+    if (lane < ncl) {
+        const int ix = lane / (cnt[1] * cnt[2]), iy = (lane / cnt[2]) % cnt[1], iz = lane % cnt[2];
+        const int wx = (lo[0] + ix + A.nc[0]) % A.nc[0], wy = (lo[1] + iy + A.nc[1]) % A.nc[1],
+                  wz = (lo[2] + iz + A.nc[2]) % A.nc[2];
+        const int w = (wx * A.nc[1] + wy) * A.nc[2] + wz;
+        cstart[lane] = A.start[w];
+        cpre[lane + 1] = A.start[w + 1] - A.start[w];
+    }
+    if (lane == 0) nnear = 0;
     __syncthreads();
-    const int64_t t = blockIdx.x * (int64_t)kKmcBlock + lane;
-    if (t < A.m) {
-        const int64_t c = perm[t];
-        const rl_kmc_params &P = A.P;
-        const double *uc = A.u + 4 * c, *xc = A.xi + 3 * c;
-        int ev = RL_EV_NONE;
-        const int s = A.state[c];
-        if (s == RL_XL_U) {
-            const double hop = sqrt(2.0 * P.dU * A.dt);
-            double p[3];
-            for (int a = 0; a < 3; ++a) {
-                p[a] = wrap1(A.xl[3 * c + a] + hop * xc[a], A.box[a]);
-                A.xl[3 * c + a] = p[a];
-            }
-            double Lt = 0.0;
-            int K = 0;
-            for_candidates(A, p, [&](int q, int j) {
-                double lo, hi;
-                inside_interval(A.xs + 3 * (int64_t)q, A.ds + 3 * (int64_t)q, A.ls[q], A.box, p, P.rcs, lo, hi);
-                if (!(hi > lo)) return;
-                Lt += hi - lo;
-                if (K < kKmcList) {
-                    S.idx[K][lane] = j;
-                    S.w[K][lane] = hi - lo;
-                }
-                ++K;
-            });
-            const double cap = 3.0 * P.eps / (4.0 * 3.14159265358979323846 * P.rcs * P.rcs * P.rcs);
-            const double RA = P.koS[0] * P.Ka[0] * cap * Lt, RB = P.koS[1] * P.Ka[1] * cap * Lt;
-            const double R = RA + RB;
-            if (R > 0.0 && uc[0] < 1.0 - exp(-R * A.dt)) {
-                const int hd = uc[1] * R < RA ? 0 : 1;
-                const double t = uc[2] * Lt;
-                double cum = 0.0, before = 0.0;
-                int pick = -1;
-                if (K <= kKmcList) {
-                    list_sort(S, lane, K);
-                    for (int k = 0; k < K; ++k) {
-                        pick = S.idx[k][lane];
-                        before = cum;
-                        cum += S.w[k][lane];
-                        if (cum > t) break;
-                    }
-                } else {
-                    // more candidates than the list holds: take them in index
-                    // order by repeated search
-                    int cur = -1;
-                    for (;;) {
-                        int next = 0x7fffffff;
-                        double wn = 0.0;
-                        for_candidates(A, p, [&](int q, int j) {
-                            if (j <= cur || j >= next) return;
-                            double lo, hi;
-                            inside_interval(A.xs + 3 * (int64_t)q, A.ds + 3 * (int64_t)q, A.ls[q], A.box, p, P.rcs,
-                                            lo, hi);
-                            if (!(hi > lo)) return;
-                            next = j;
-                            wn = hi - lo;
-                        });
-                        if (next == 0x7fffffff) break;
-                        pick = next;
-                        before = cum;
-                        cum += wn;
-                        if (cum > t) break;
-                        cur = next;
-                    }
-                }
-                if (pick >= 0) {
-                    double lo, hi;
-                    inside_interval(A.x + 3 * (int64_t)pick, A.dir + 3 * (int64_t)pick, rlen(A, pick), A.box, p,
-                                    P.rcs, lo, hi);
-                    double sa = lo + (t - before);
-                    if (sa > hi) sa = hi;
-                    if (sa < lo) sa = lo;
-                    A.state[c] = hd == 0 ? RL_XL_SA : RL_XL_SB;
-                    A.rod[2 * c + hd] = pick;
-                    A.arc[2 * c + hd] = sa;
-                    double q[3];
-                    axis_point(A, pick, sa, q);
-                    for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = q[a];
-                    ev = RL_EV_BIND;
-                }
-            }
-        } else if (s == RL_XL_SA || s == RL_XL_SB) {
-            const int hd = s == RL_XL_SA ? 0 : 1, g = 1 - hd;
-            const int i = A.rod[2 * c + hd];
-            double p[3];
-            axis_point(A, i, A.arc[2 * c + hd], p);
-            double W = 0.0;
-            int K = 0;
-            for_candidates(A, p, [&](int, int j) {
-                if (j == i) return;
-                const double wj = site_sum(A, j, p, -1.0, nullptr);
-                if (!(wj > 0.0)) return;
-                W += wj;
-                if (K < kKmcList) {
-                    S.idx[K][lane] = j;
-                    S.w[K][lane] = wj;
-                }
-                ++K;
-            });
-            const double Ron = P.koD[g] * P.Ke[g] / A.vbd * W;
-            const double Roff = P.koS[hd];
-            const double R = Ron + Roff;
-            for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = p[a];
-            if (R > 0.0 && uc[0] < 1.0 - exp(-R * A.dt)) {
-                if (uc[1] * R < Roff) {
-                    const double nx = sqrt(xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2]);
-                    const double rad = P.rcs * cbrt(uc[3]);
-                    for (int a = 0; a < 3; ++a) {
-                        const double dn = nx > 0.0 ? xc[a] / nx : (a == 2 ? 1.0 : 0.0);
-                        A.xl[3 * c + a] = wrap1(p[a] + rad * dn, A.box[a]);
-                    }
-                    A.state[c] = RL_XL_U;
-                    A.rod[2 * c + hd] = -1;
-                    A.arc[2 * c + hd] = 0.0;
-                    ev = RL_EV_UNBIND;
-                } else {
-                    const double t = uc[2] * W;
-                    double cum = 0.0;
-                    int pick = -1;
-                    int64_t site = -1;
-                    bool found = false;
-                    if (K <= kKmcList) {
-                        list_sort(S, lane, K);
-                        for (int k = 0; k < K; ++k) {
-                            const int j = S.idx[k][lane];
-                            const double wj = S.w[k][lane];
-                            pick = j;
-                            if (cum + wj > t) {
-                                site_sum(A, j, p, t - cum, &site);
-                                found = true;
-                                break;
-                            }
-                            cum += wj;
-                        }
-                    } else {
-                        int cur = -1;
-                        for (;;) {
-                            int next = 0x7fffffff;
-                            for_candidates(A, p, [&](int, int j) {
-                                if (j == i || j <= cur || j >= next) return;
-                                if (site_sum(A, j, p, -1.0, nullptr) > 0.0) next = j;
-                            });
-                            if (next == 0x7fffffff) break;
-                            const double wj = site_sum(A, next, p, -1.0, nullptr);
-                            pick = next;
-                            if (cum + wj > t) {
-                                site_sum(A, next, p, t - cum, &site);
-                                found = true;
-                                break;
-                            }
-                            cum += wj;
-                            cur = next;
-                        }
-                    }
-                    // rounding left t at or past the total: the last site
-                    if (!found && pick >= 0) site_sum(A, pick, p, -1.0, &site);
-                    if (pick >= 0 && site >= 0) {
-                        const double L = rlen(A, pick);
-                        A.state[c] = RL_XL_D;
-                        A.rod[2 * c + g] = pick;
-                        A.arc[2 * c + g] = site_arc(L, sites_of(A, L), site);
-                        if (g == 0) {
-                            double q[3];
-                            axis_point(A, pick, A.arc[2 * c], q);
-                            for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = q[a];
-                        }
-                        ev = RL_EV_CROSS;
-                    }
-                }
-            }
-        } else if (s == RL_XL_D) {
-            double pa[3], pb[3];
-            axis_point(A, A.rod[2 * c], A.arc[2 * c], pa);
-            axis_point(A, A.rod[2 * c + 1], A.arc[2 * c + 1], pb);
-            double l2 = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                double d = pa[a] - pb[a];
-                d -= A.box[a] * floor(d / A.box[a] + 0.5);
-                l2 += d * d;
-            }
-            const double l = sqrt(l2);
-            const double RA = release_rate(A, P.koD[0], l), RB = release_rate(A, P.koD[1], l);
-            const double R = RA + RB;
-            for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = pa[a];
-            if (R > 0.0 && uc[0] < 1.0 - exp(-R * A.dt)) {
-                const int hd = uc[1] * R < RA ? 0 : 1;
-                A.state[c] = hd == 0 ? RL_XL_SB : RL_XL_SA;
-                A.rod[2 * c + hd] = -1;
-                A.arc[2 * c + hd] = 0.0;
-                if (hd == 0)
-                    for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = pb[a];
-                ev = RL_EV_RELEASE;
-            }
-        }
-        if (A.event) A.event[c] = ev;
-        atomicAdd(&cnt[ev], 1u);
+    if (lane == 0) {
+        cpre[0] = 0;
+        for (int k = 0; k < ncl; ++k) cpre[k + 1] += cpre[k];
     }
     __syncthreads();
-    if (lane < 5 && cnt[lane]) atomicAdd(A.counts + lane, (unsigned long long)cnt[lane]);
+    const int T = cpre[ncl];
+    // candidate pass: a cheap centre-distance test (nearest image, reach
+    // L/2 + r with a margin), then the exact captured interval
+    const double inv[3] = {1.0 / A.box[0], 1.0 / A.box[1], 1.0 / A.box[2]};
+    for (int t = lane; t < T; t += 64) {
+        int k = 0;
+        while (cpre[k + 1] <= t) ++k;
+        const int q = cstart[k] + (t - cpre[k]);
+        const double *xq = A.xs + 3 * (int64_t)q, *dq = A.ds + 3 * (int64_t)q;
+        const double Lq = A.ls[q];
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double d = xq[a] - p[a];
+            d -= A.box[a] * rint(d * inv[a]);
+            d2 += d * d;
+        }
+        const double reach = 0.5 * Lq + r;
+        if (d2 > reach * reach * (1.0 + 1e-9) + 1e-24) continue;
+        const int j = A.order[q];
+        if (j == own) continue;
+        double a0, a1;
+        inside_interval(xq, dq, Lq, A.box, p, unb ? r : r * (1.0 + 1e-9), a0, a1);
+        if (!(a1 > a0)) continue;
+        const int slot = atomicAdd(&nnear, 1);
+        if (slot < kNearCap) {
+            nidx[slot] = j;
+            nw[slot] = a1 - a0;
+        }
+    }
+    __syncthreads();
+    const int K = nnear;
+    if (K > kNearCap) {
+        if (lane == 0) atomicOr(err, 2);
+        return;
+    }
+    // sort the kept filaments by index (ranks; the indices are distinct)
+    for (int k = lane; k < K; k += 64) {
+        const int me = nidx[k];
+        int rank = 0;
+        for (int o = 0; o < K; ++o) rank += nidx[o] < me;
+        sidx[rank] = me;
+        sw[rank] = nw[k];
+    }
+    __syncthreads();
+    // S -> D weights of the kept filaments, sites spread over the lanes
+    if (!unb) {
+        for (int k = 0; k < K; ++k) {
+            const int j = sidx[k];
+            const double L = rlen(A, j);
+            const int64_t m = sites_of(A, L);
+            const double *xj = A.x + 3 * (int64_t)j, *dj = A.dir + 3 * (int64_t)j;
+            double a0, a1;
+            inside_interval(xj, dj, L, A.box, p, P.rcd * (1.0 + 1e-9), a0, a1);
+            const double step = L / m;
+            int64_t k0 = (int64_t)floor((a0 + 0.5 * L) / step - 0.5) - 1;
+            int64_t k1 = (int64_t)ceil((a1 + 0.5 * L) / step - 0.5) + 1;
+            if (k0 < 0) k0 = 0;
+            if (k1 > m - 1) k1 = m - 1;
+            double cc[3];
+            centre_rel(xj, A.box, p, cc);
+            double part = 0.0;
+            for (int64_t ks = k0 + lane; ks <= k1; ks += 64) {
+                const double sa = site_arc(L, m, ks);
+                const double v0 = cc[0] + sa * dj[0], v1 = cc[1] + sa * dj[1], v2 = cc[2] + sa * dj[2];
+                const double l = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+                if (l <= P.rcd) part += cross_weight(A, l);
+            }
+            const double wj = wave_sum(part);
+            if (lane == 0) sw[k] = wj;
+        }
+        __syncthreads();
+    }
+    if (lane != 0) return;
+    // the total over the kept filaments in index order
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) tot += sw[k];
+    int ev = RL_EV_NONE;
+    if (unb) {
+        for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = p[a];
+        const double cap = 3.0 * P.eps / (4.0 * 3.14159265358979323846 * P.rcs * P.rcs * P.rcs);
+        const double RA = P.koS[0] * P.Ka[0] * cap * tot, RB = P.koS[1] * P.Ka[1] * cap * tot;
+        const double R = RA + RB;
+        if (R > 0.0 && uc[0] < 1.0 - exp(-R * A.dt) && K > 0) {
+            const int h = uc[1] * R < RA ? 0 : 1;
+            const double t = uc[2] * tot;
+            double cum = 0.0, before = 0.0;
+            int pick = -1;
+            for (int k = 0; k < K; ++k) {
+                pick = sidx[k];
+                before = cum;
+                cum += sw[k];
+                if (cum > t) break;
+            }
+            double a0, a1;
+            inside_interval(A.x + 3 * (int64_t)pick, A.dir + 3 * (int64_t)pick, rlen(A, pick), A.box, p, P.rcs, a0,
+                            a1);
+            double sa = a0 + (t - before);
+            if (sa > a1) sa = a1;
+            if (sa < a0) sa = a0;
+            A.state[c] = h == 0 ? RL_XL_SA : RL_XL_SB;
+            A.rod[2 * c + h] = pick;
+            A.arc[2 * c + h] = sa;
+            double q[3];
+            axis_point(A, pick, sa, q);
+            for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = q[a];
+            ev = RL_EV_BIND;
+        }
+    } else {
+        const double Ron = P.koD[g] * P.Ke[g] / A.vbd * tot;
+        const double Roff = P.koS[hd];
+        const double R = Ron + Roff;
+        for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = p[a];
+        if (R > 0.0 && uc[0] < 1.0 - exp(-R * A.dt)) {
+            if (uc[1] * R < Roff) {
+                const double nx = sqrt(xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2]);
+                const double rad = P.rcs * cbrt(uc[3]);
+                for (int a = 0; a < 3; ++a) {
+                    const double dn = nx > 0.0 ? xc[a] / nx : (a == 2 ? 1.0 : 0.0);
+                    A.xl[3 * c + a] = wrap1(p[a] + rad * dn, A.box[a]);
+                }
+                A.state[c] = RL_XL_U;
+                A.rod[2 * c + hd] = -1;
+                A.arc[2 * c + hd] = 0.0;
+                ev = RL_EV_UNBIND;
+            } else if (K > 0) {
+                const double t = uc[2] * tot;
+                double cum = 0.0;
+                int pick = -1;
+                int64_t site = -1;
+                for (int k = 0; k < K; ++k) {
+                    if (!(sw[k] > 0.0)) continue;
+                    pick = sidx[k];
+                    if (cum + sw[k] > t) {
+                        site_sum(A, pick, p, t - cum, &site);
+                        break;
+                    }
+                    cum += sw[k];
+                }
+                // rounding left t at or past the total: the last site
+                if (pick >= 0 && site < 0) site_sum(A, pick, p, -1.0, &site);
+                if (pick >= 0 && site >= 0) {
+                    const double L = rlen(A, pick);
+                    A.state[c] = RL_XL_D;
+                    A.rod[2 * c + g] = pick;
+                    A.arc[2 * c + g] = site_arc(L, sites_of(A, L), site);
+                    if (g == 0) {
+                        double q[3];
+                        axis_point(A, pick, A.arc[2 * c], q);
+                        for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = q[a];
+                    }
+                    ev = RL_EV_CROSS;
+                }
+            }
+        }
+    }
+    if (A.event) A.event[c] = ev;
+    if (ev != RL_EV_NONE) atomicAdd(A.counts + ev, 1ull);
+}
+
+// Doubly bound crosslinkers: one lane each (two axis points, two rates).
+__global__ void __launch_bounds__(256) k_kmc_light(KmcArgs A, const int *__restrict__ perm, int nheavy)
+{
+    __shared__ unsigned nrel;
+    if (threadIdx.x == 0) nrel = 0;
+    __syncthreads();
+    const int64_t t = nheavy + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < A.m) {
+        const int64_t c = perm[t];
+        const double *uc = A.u + 4 * c;
+        const rl_kmc_params &P = A.P;
+        int ev = RL_EV_NONE;
+        double pa[3], pb[3];
+        axis_point(A, A.rod[2 * c], A.arc[2 * c], pa);
+        axis_point(A, A.rod[2 * c + 1], A.arc[2 * c + 1], pb);
+        double l2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double d = pa[a] - pb[a];
+            d -= A.box[a] * floor(d / A.box[a] + 0.5);
+            l2 += d * d;
+        }
+        const double l = sqrt(l2);
+        const double RA = release_rate(A, P.koD[0], l), RB = release_rate(A, P.koD[1], l);
+        const double R = RA + RB;
+        for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = pa[a];
+        if (R > 0.0 && uc[0] < 1.0 - exp(-R * A.dt)) {
+            const int hd = uc[1] * R < RA ? 0 : 1;
+            A.state[c] = hd == 0 ? RL_XL_SB : RL_XL_SA;
+            A.rod[2 * c + hd] = -1;
+            A.arc[2 * c + hd] = 0.0;
+            if (hd == 0)
+                for (int a = 0; a < 3; ++a) A.xl[3 * c + a] = pb[a];
+            ev = RL_EV_RELEASE;
+            atomicAdd(&nrel, 1u);
+        }
+        if (A.event) A.event[c] = ev;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && nrel) atomicAdd(A.counts + RL_EV_RELEASE, (unsigned long long)nrel);
 }
 
 // doubly bound crosslinkers: flags, then their links in crosslinker order
@@ -617,17 +620,37 @@ int rl_kmc_step(rl_handle h, int64_t n, const double *x, const double *dir, cons
     int *key_out = (int *)ws_get(h, kWsKmcKeyOut, sizeof(int) * m, &werr);
     int *perm = (int *)ws_get(h, kWsKmcPerm, sizeof(int) * m, &werr);
     if (werr) return werr;
-    hipLaunchKernelGGL(k_kmc_keys, dim3(grid_of(m, 256)), dim3(256), 0, st, A, key);
+    RL_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, st));
+    hipLaunchKernelGGL(k_kmc_keys, dim3(grid_of(m, 256)), dim3(256), 0, st, A, key, flag + 1);
     RL_HIP(hipGetLastError());
     rc = stable_sort_by_key(h, m, key, 28, key_out, perm);
     if (rc) return rc;
+    RL_HIP(hipMemcpyAsync(h->host_scratch + 4, flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    RL_HIP(hipStreamSynchronize(st));
+    const int nheavy = ((int *)(h->host_scratch + 4))[0];
     RL_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * 8, st));
-    hipLaunchKernelGGL(k_kmc, dim3(grid_of(m, kKmcBlock)), dim3(kKmcBlock), 0, st, A, (const int *)perm);
+    if (nheavy > 0)
+        hipLaunchKernelGGL(k_kmc_heavy, dim3((unsigned)nheavy), dim3(64), 0, st, A, (const int *)perm, nheavy, flag);
+    RL_HIP(hipGetLastError());
+    if (m > nheavy)
+        hipLaunchKernelGGL(k_kmc_light, dim3(grid_of(m - nheavy, 256)), dim3(256), 0, st, A, (const int *)perm,
+                           nheavy);
     RL_HIP(hipGetLastError());
     RL_HIP(hipMemcpyAsync(h->host_scratch, cnt, sizeof(unsigned long long) * 5, hipMemcpyDeviceToHost, st));
+    RL_HIP(hipMemcpyAsync(h->host_scratch + 5, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     RL_HIP(hipStreamSynchronize(st));
-    if (counts)
-        for (int k = 0; k < 5; ++k) counts[k] = h->host_scratch[k];
+    if (((int *)(h->host_scratch + 5))[0] & 2) {
+        set_error("rl_kmc_step: more than %d filaments pass within the query radius of one crosslinker", kNearCap);
+        return RL_ERR_ARG;
+    }
+    if (counts) {
+        int64_t ev = 0;
+        for (int k = 1; k < 5; ++k) {
+            counts[k] = h->host_scratch[k];
+            ev += counts[k];
+        }
+        counts[0] = m - ev;
+    }
     return RL_OK;
 }
 
