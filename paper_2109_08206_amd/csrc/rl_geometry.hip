@@ -277,6 +277,9 @@ __device__ __forceinline__ bool lex_positive(int a, int b, int c)
 constexpr int kPairBlock = 256;
 constexpr int kCellChunk = 256;  // rods of one cell staged at a time
 constexpr int kQueue = 4096;     // candidate (home, neighbour) pairs per flush
+#ifndef RL_PAIR_SPLIT
+#define RL_PAIR_SPLIT 9
+#endif
 
 // The staged copies are FP32, with the centres relative to the home cell's
 // corner (so they stay within a few cells of 0 and round finely): the cheap
@@ -345,7 +348,8 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
                                                       int32_t *__restrict__ pj, int32_t *__restrict__ img,
                                                       uint8_t *__restrict__ flags, unsigned long long *ecount,
                                                       unsigned long long *__restrict__ ekeys,
-                                                      uint8_t *__restrict__ eflags, int64_t ecap, int kshift)
+                                                      uint8_t *__restrict__ eflags, int64_t ecap, int kshift,
+                                                      int split)
 {
     constexpr bool FILL = PASS == kPairFill;
     __shared__ CellStage H, Nb;
@@ -354,7 +358,9 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
     __shared__ int qn;
     __shared__ int scan_lds[kPairBlock / 64 + 1];
     __shared__ unsigned long long ebase;
-    const int h = blockIdx.x;
+    // the emitting pass may split a home cell's stencil over `split`
+    // workgroups (each takes every split-th neighbour cell)
+    const int h = blockIdx.x / split, part = blockIdx.x % split;
     const int hz = h % g.nc[2], hy = (h / g.nc[2]) % g.nc[1], hx = h / (g.nc[2] * g.nc[1]);
     const int hb = cell_start[h], he = cell_start[h + 1];
     // FP32 margins.  Staged centres lie within S + 1 cells of the corner (S <=
@@ -375,7 +381,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
             if (PASS == kPairFill) hoff[u] = poff[INTERNAL ? a0 + u : sorted[a0 + u]];
         }
         __syncthreads();
-        for (int sc = 0; sc < NS; ++sc) {
+        for (int sc = part; sc < NS; sc += split) {
             const int ux = hx + sc / (NY * NZ) - g.S[0];
             const int uy = hy + (sc / NZ) % NY - g.S[1];
             const int uz = hz + sc % NZ - g.S[2];
@@ -658,6 +664,13 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     while ((1LL << ibits) < n) ++ibits;
     const bool emit = 2 * ibits + 12 <= 64;
     const dim3 pgrid((unsigned)ncell), pblock(kPairBlock);
+    // with few cells, one workgroup per home cell leaves the chip short of
+    // waves: the emitting pass splits each stencil over several workgroups,
+    // up to RL_PAIR_SPLIT of them, for about 4,096 workgroups in all
+    // (100k rods, 729 cells: 838 us with one per cell, 423 with three, 376
+    // with six)
+    const int split = (int)std::max<int64_t>(1, std::min<int64_t>(RL_PAIR_SPLIT, 4096 / ncell));
+    const dim3 egrid((unsigned)(ncell * split));
     auto *none_u64 = (unsigned long long *)nullptr;
     auto *none_u8 = (uint8_t *)nullptr;
     if (emit) {
@@ -669,13 +682,15 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
         RL_HIP(hipMemsetAsync(ecount, 0, sizeof(unsigned long long), st));
         const int kshift = ibits + 12;
         if (internal)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairEmit, true>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairEmit, true>), egrid, pblock, 0, st, g, p.diam, p.cutoff,
                                sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
-                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, ecount, ekeys, eflags, ecap, kshift);
+                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, ecount, ekeys, eflags, ecap, kshift,
+                               split);
         else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairEmit, false>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairEmit, false>), egrid, pblock, 0, st, g, p.diam, p.cutoff,
                                sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
-                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, ecount, ekeys, eflags, ecap, kshift);
+                               (int32_t *)nullptr, (int32_t *)nullptr, none_u8, ecount, ekeys, eflags, ecap, kshift,
+                               split);
         RL_HIP(hipGetLastError());
         RL_HIP(hipMemcpyAsync(h->host_scratch, ecount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     } else {
@@ -683,12 +698,12 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairCount, true>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
                                sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
                                (int32_t *)nullptr, (int32_t *)nullptr, none_u8, none_u64, none_u64, none_u8,
-                               (int64_t)0, 0);
+                               (int64_t)0, 0, 1);
         else
             hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairCount, false>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
                                sorted, xs, ds, ls, cell_start, pcnt, (const int *)nullptr, (int32_t *)nullptr,
                                (int32_t *)nullptr, (int32_t *)nullptr, none_u8, none_u64, none_u64, none_u8,
-                               (int64_t)0, 0);
+                               (int64_t)0, 0, 1);
         RL_HIP(hipGetLastError());
         const int rc = device_scan(h, pcnt, n, poff, tot);
         if (rc) return rc;
@@ -726,11 +741,11 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     if (internal)
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairFill, true>), pgrid, pblock, 0, st, g, p.diam, p.cutoff, sorted,
                            xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags, none_u64, none_u64,
-                           none_u8, (int64_t)0, 0);
+                           none_u8, (int64_t)0, 0, 1);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pairs<kPairFill, false>), pgrid, pblock, 0, st, g, p.diam, p.cutoff,
                            sorted, xs, ds, ls, cell_start, pcnt, (const int *)poff, pi, pj, img, flags, none_u64,
-                           none_u64, none_u8, (int64_t)0, 0);
+                           none_u64, none_u8, (int64_t)0, 0, 1);
     RL_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sort_pairs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)poff, pj, img, flags);
     RL_HIP(hipGetLastError());
