@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "BBPGD iters/sec and LCP solves/sec at 100k rods; HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bbpgd_rods100k.json")
+TRAFFIC_FILE_400K = os.path.join(ROOT, "profiles", "traffic_bbpgd_rods400k.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f)
                   for f in ("rl_solver.hip", "rl_device.hpp", "rl_internal.hpp")]
 
@@ -67,11 +68,11 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on other kernel sources."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(path))
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != source_hash():
@@ -209,7 +210,11 @@ def form_precision(args, torch, rl, rodsynth) -> dict:
                      "iters_per_solve": iters / args.steps, "fp64_refreshes_per_solve": refr / args.steps,
                      "max_residual_fp64": worst, "status": status, "constraints": npairs,
                      "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": ach, "peak": HBM_PEAK_GBS,
-                                  "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None},
+                                  "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                  "traffic": (measured_traffic(dom + ("" if prec == rl.FP64 else "32"),
+                                                               TRAFFIC_FILE_400K)
+                                              if (s.n, args.seed, phi) == (400_000, 0, 0.08) else None),
+                                  "alg_bytes_per_launch": kb[dom]},
                      "kernels": kern, "us_per_iteration": 1e3 * (avg["rod"] + avg["con"])}
         Us[name] = U.cpu()
     du = float(torch.linalg.norm(Us["fp32_mixed"] - Us["fp64"]) / torch.linalg.norm(Us["fp64"]))
