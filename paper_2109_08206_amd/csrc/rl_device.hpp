@@ -184,6 +184,26 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks)
     return (b % kXcd) * (nblocks / kXcd) + b / kXcd;
 }
 
+// Rounds of a constraint kernel (rw constraints each): XCD x owns the x-th
+// eighth of the constraint order and its workgroups sweep it together, band
+// after band (workgroup j of the XCD takes round j of each band), so that at
+// any moment an XCD works on one stretch of the order.  The partner entries
+// that neighbouring workgroups share (the gathered and scattered Q side) are
+// then touched while still in that XCD's L2, instead of once per workgroup
+// chunk at times far apart.  A workgroup's rounds start at `first`, step by
+// `stride` and end before `end`.
+struct ConBand {
+    int64_t first, stride, end;
+};
+
+__device__ __forceinline__ ConBand con_band(unsigned b, unsigned nblocks, int64_t nc, int64_t rw)
+{
+    constexpr unsigned kXcd = 8;
+    if (nblocks % kXcd != 0) return ConBand{(int64_t)b * rw, (int64_t)nblocks * rw, nc};
+    const int64_t px = (nc + kXcd - 1) / kXcd, x0 = (int64_t)(b % kXcd) * px;
+    return ConBand{x0 + (int64_t)(b / kXcd) * rw, (int64_t)(nblocks / kXcd) * rw, x0 + px < nc ? x0 + px : nc};
+}
+
 // ---------------------------------------------------------------------------
 // per-rod and per-constraint work of one product (shared by the single and
 // the batched solvers)

@@ -253,12 +253,13 @@ __global__ void __launch_bounds__(CB)
 {
     __shared__ double lds[CB / 64 + 1][4];
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    const unsigned tile = xcd_tile(blockIdx.x, nblk);
-    const int64_t per = (nc + nblk - 1) / nblk;
-    const int64_t lo = (int64_t)tile * per, hi = lo + per < nc ? lo + per : nc;
+    // rounds of CPL constraints per lane, swept band by band per XCD
+    const ConBand bd = con_band(blockIdx.x, nblk, nc, (int64_t)CPL * CB);
+    const int64_t hi = bd.end;
+    int64_t base = bd.first;
     // the first round goes out before the flags are read; nothing in this
     // launch writes the flags, so the early return is uniform
-    int64_t c0 = lo + threadIdx.x;
+    int64_t c0 = base + threadIdx.x;
     Con32Loads L[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u)
@@ -270,8 +271,9 @@ __global__ void __launch_bounds__(CB)
 #pragma unroll
         for (int u = 0; u < CPL; ++u)
             if (c0 + u * CB < hi) con32_update(a, c0 + u * CB, L[u], a32, p);
-        c0 += (int64_t)CPL * CB;
-        if (c0 >= hi) break;
+        base += bd.stride;
+        if (base >= hi) break;
+        c0 = base + threadIdx.x;
 #pragma unroll
         for (int u = 0; u < CPL; ++u)
             if (c0 + u * CB < hi) con32_load(qpos, uP32, s32, uQ32, c0 + u * CB, L[u]);

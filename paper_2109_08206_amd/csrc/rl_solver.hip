@@ -263,14 +263,13 @@ __global__ void __launch_bounds__(CB)
     __shared__ double lds[CB / 64 + 1][4];
     double p[4] = {0.0, 0.0, 0.0, 0.0};
     const ConIn in{qpos, uP, qv, st, uQ};
-    const unsigned tile = xcd_tile(blockIdx.x, nblk);
-    // each workgroup takes a contiguous chunk of constraints, CPL per lane per round
-    const int64_t per = (nc + nblk - 1) / nblk;
-    const int64_t lo = (int64_t)tile * per, hi = lo + per < nc ? lo + per : nc;
+    // rounds of CPL constraints per lane, swept band by band per XCD
+    const ConBand bd = con_band(blockIdx.x, nblk, nc, (int64_t)CPL * CB);
+    const int64_t hi = bd.end;
+    int64_t base = bd.first;
     // first round peeled: its records are in flight before the stop flag and
     // the step length are read (every thread reaches the test)
-    const int64_t step = (int64_t)CPL * CB;
-    int64_t c0 = lo + threadIdx.x;
+    int64_t c0 = base + threadIdx.x;
     ConLoadsU L[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u)
@@ -288,8 +287,9 @@ __global__ void __launch_bounds__(CB)
                 if (BIL) con_update_gen<MODE>(a, c0 + u * CB, L[u], alpha, p);
                 else con_update_u<MODE>(a, c0 + u * CB, L[u], alpha, p);
             }
-        c0 += step;
-        if (c0 >= hi) break;
+        base += bd.stride;
+        if (base >= hi) break;
+        c0 = base + threadIdx.x;
 #pragma unroll
         for (int u = 0; u < CPL; ++u)
             if (c0 + u * CB < hi) {
