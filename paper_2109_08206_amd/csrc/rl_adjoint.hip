@@ -128,12 +128,8 @@ __global__ void __launch_bounds__(kConBlock) k_cg_start(CgArgs g, const double *
         p[0] += b * b;
         p[2] += m;
     }
-    block_reduce4_all<kConBlock / 64>(p, lds);
-    if (threadIdx.x == 0) {
-        double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)a.gcon * 4 + 4 * blockIdx.x);
-        dst[0] = make_double2(p[0], p[1]);
-        dst[1] = make_double2(p[2], p[3]);
-    }
+    block_total4<kConBlock / 64>(p, lds);
+    if (threadIdx.x == 0) partial_put(a.partial + (int64_t)a.gcon * 4, a.gcon, blockIdx.x, p);
 }
 
 // One incidence record of the CG rod kernel: (r, s) and w of the constraint
@@ -226,7 +222,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     }
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
-    partials_first(part, a.gcon, pf);
+    partials_first_split(part, a.gcon, pf);
     // the recurrence's other inputs and the rod's direction and mobility do
     // not depend on the partials either
     const double bb0 = st->alpha0, tol = st->tol;
@@ -239,7 +235,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     rod_mob(a, rr, UNI, apar, aperp, rperp);
     if (st->done) return;
     double t[4];
-    sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
+    sum_partials_split_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
     double alpha = 0.0, beta = 0.0;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (k == 0) {
@@ -392,12 +388,8 @@ __global__ void __launch_bounds__(kConBlock)
         for (int u = 0; u < kConCpl; ++u)
             if (c0 + u * kConBlock < hi) cg_con_load(in, c0 + u * kConBlock, L[u]);
     }
-    block_reduce4_all<kConBlock / 64>(p, lds);
-    if (threadIdx.x == 0) {
-        double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)(k & 1) * a.gcon * 4 + 4 * blockIdx.x);
-        dst[0] = make_double2(p[0], p[1]);
-        dst[1] = make_double2(p[2], p[3]);
-    }
+    block_total4<kConBlock / 64>(p, lds);
+    if (threadIdx.x == 0) partial_put(a.partial + (int64_t)(k & 1) * a.gcon * 4, a.gcon, blockIdx.x, p);
 }
 
 // Per rod: G_c = D gamma and G_l = D lambda (force and torque), then

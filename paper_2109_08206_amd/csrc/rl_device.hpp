@@ -57,15 +57,136 @@ __device__ __forceinline__ void block_reduce4_all(double p[4], double (*lds)[4])
     __syncthreads();
 }
 
+// Wave total of a double by DPP lane moves, without the LDS crossbar: two
+// quad permutations, the half-row and the row mirror leave every lane of a
+// row of 16 holding that row's total (each step adds a lane's value to its
+// partner's, and both partners compute the same sum), and the four row totals
+// are then combined as (r0 + r1) + (r2 + r3).  Every lane returns the same
+// bits.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+template <bool MAX>
+__device__ __forceinline__ double wave_total(double v)
+{
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+    v = op(v, dpp_f64<0xb1>(v));   // quad_perm [1,0,3,2]
+    v = op(v, dpp_f64<0x4e>(v));   // quad_perm [2,3,0,1]
+    v = op(v, dpp_f64<0x141>(v));  // row_half_mirror
+    v = op(v, dpp_f64<0x140>(v));  // row_mirror
+    return op(op(lane_f64(v, 0), lane_f64(v, 16)), op(lane_f64(v, 32), lane_f64(v, 48)));
+}
+
+// Sums p[0..2] and takes the max of p[3] over the workgroup with one barrier:
+// wave totals by DPP, then every thread combines the NW wave totals in wave
+// order.  Every thread receives the same result; lds (NW x 4 doubles) is not
+// reused afterwards by the callers.
+template <int NW>
+__device__ __forceinline__ void block_total4(double p[4], double (*lds)[4])
+{
+    const int wid = threadIdx.x >> 6;
+    p[0] = wave_total<false>(p[0]);
+    p[1] = wave_total<false>(p[1]);
+    p[2] = wave_total<false>(p[2]);
+    p[3] = wave_total<true>(p[3]);
+    if ((threadIdx.x & 63) == 0) {
+        lds[wid][0] = p[0];
+        lds[wid][1] = p[1];
+        lds[wid][2] = p[2];
+        lds[wid][3] = p[3];
+    }
+    __syncthreads();
+    p[0] = lds[0][0];
+    p[1] = lds[0][1];
+    p[2] = lds[0][2];
+    p[3] = lds[0][3];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+        p[0] += lds[w][0];
+        p[1] += lds[w][1];
+        p[2] += lds[w][2];
+        p[3] = fmax(p[3], lds[w][3]);
+    }
+}
+
+// Workgroup partials of the single-system solvers: `count` slots, kept as two
+// arrays of double2, (s.s, s.y) of every slot and then (y.y, residual), so
+// that a wave's loads of consecutive slots read whole lines (half as many L2
+// requests as four doubles per slot; every rod workgroup reads them all).
+__device__ __forceinline__ void partial_put(double *P, int count, int b, const double p[4])
+{
+    double2 *Q = reinterpret_cast<double2 *>(P);
+    Q[b] = make_double2(p[0], p[1]);
+    Q[count + b] = make_double2(p[2], p[3]);
+}
+
+struct PartFirst {
+    double2 u, v;
+};
+
+// the thread's first slot (clamped: any count >= 1 gives an in-bounds address;
+// with count <= 0 nothing is read)
+__device__ __forceinline__ void partials_first_split(const double *__restrict__ P, int count, PartFirst &F)
+{
+    F.u = F.v = make_double2(0.0, 0.0);
+    if (count > 0) {
+        const double2 *Q = reinterpret_cast<const double2 *>(P);
+        const int b = min((int)threadIdx.x, count - 1);
+        F.u = Q[b];
+        F.v = Q[count + b];
+    }
+}
+
+// Totals of the `count` slots at `P` (split layout), identical in every
+// workgroup: each thread sums its slots in index order, then block_total4.
+template <int NW>
+__device__ __forceinline__ void sum_partials_split_from(const PartFirst &F, const double *__restrict__ P, int count,
+                                                        double p[4], double (*lds)[4])
+{
+    constexpr int NT = NW * 64;
+    const double2 *Q = reinterpret_cast<const double2 *>(P);
+    p[0] = p[1] = p[2] = p[3] = 0.0;
+    if ((int)threadIdx.x < count) {
+        p[0] += F.u.x;
+        p[1] += F.u.y;
+        p[2] += F.v.x;
+        p[3] = fmax(p[3], F.v.y);
+    }
+    for (int b = threadIdx.x + NT; b < count; b += NT) {
+        const double2 u = Q[b], v = Q[count + b];
+        p[0] += u.x;
+        p[1] += u.y;
+        p[2] += v.x;
+        p[3] = fmax(p[3], v.y);
+    }
+    block_total4<NW>(p, lds);
+}
+
+template <int NW>
+__device__ __forceinline__ void sum_partials_split(const double *__restrict__ P, int count, double p[4],
+                                                   double (*lds)[4])
+{
+    PartFirst F;
+    partials_first_split(P, count, F);
+    sum_partials_split_from<NW>(F, P, count, p, lds);
+}
+
 // Totals of the `count` workgroup partials at `P`, identical in every
 // workgroup.  Each thread sums its partials in index order: the first one
 // (partials_first, which a kernel may issue early, before it waits on
 // anything else), then the rest with kPartChunk loads in flight together.
 constexpr int kPartChunk = 2;
-
-struct PartFirst {
-    double2 u, v;
-};
 
 // the thread's first partial (clamped: any count >= 1 gives an in-bounds
 // address; with count <= 0 nothing is read)

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     // and the previous iteration's partials (read for nothing on a first iteration)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
-    partials_first(part, a.gcon, pf);
+    partials_first_split(part, a.gcon, pf);
     if (st->done || st->refresh) return;
     double alpha;
     if (first) {
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
         if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[k & 1] = alpha;
     } else {
         double t[4];
-        sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
+        sum_partials_split_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
         const double ss = t[0], sy = t[1], yy = t[2], res = t[3];
         int done = 0, refresh = 0, status = RL_OK;
         if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
@@ -278,12 +278,8 @@ __global__ void __launch_bounds__(CB)
         for (int u = 0; u < CPL; ++u)
             if (c0 + u * CB < hi) con32_load(qpos, uP32, s32, uQ32, c0 + u * CB, L[u]);
     }
-    block_reduce4_all<CB / 64>(p, lds);
-    if (threadIdx.x == 0) {
-        double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)(k & 1) * a.gcon * 4 + 4 * blockIdx.x);
-        dst[0] = make_double2(p[0], p[1]);
-        dst[1] = make_double2(p[2], p[3]);
-    }
+    block_total4<CB / 64>(p, lds);
+    if (threadIdx.x == 0) partial_put(a.partial + (int64_t)(k & 1) * a.gcon * 4, a.gcon, blockIdx.x, p);
 }
 
 // the leading arguments of k_rod32 and k_con32

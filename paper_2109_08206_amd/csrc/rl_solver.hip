@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     // so are the previous iteration's partials (read for nothing at k = 0)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
-    if (MODE == kModeLoop) partials_first(part, a.gcon, pf);
+    if (MODE == kModeLoop) partials_first_split(part, a.gcon, pf);
     // and the rod's direction and mobility and the inputs of the step rule,
     // which do not depend on the partials either
     const int64_t rr = active ? r : 0;
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
             }
         } else {
             double t[4];
-            sum_partials_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
+            sum_partials_split_from<kRodLoopBlock / 64>(pf, part, a.gcon, t, lds);
             const Decision d = decide_from(din, k, t);
             if (lead) {
                 report_progress(a.progress, k, d.stop);
@@ -298,12 +298,8 @@ __global__ void __launch_bounds__(CB)
             }
     }
     if (MODE == kModeApply) return;
-    block_reduce4_all<CB / 64>(p, lds);
-    if (threadIdx.x == 0) {
-        double2 *dst = reinterpret_cast<double2 *>(a.partial + (int64_t)(k & 1) * a.gcon * 4 + 4 * blockIdx.x);
-        dst[0] = make_double2(p[0], p[1]);
-        dst[1] = make_double2(p[2], p[3]);
-    }
+    block_total4<CB / 64>(p, lds);
+    if (threadIdx.x == 0) partial_put(a.partial + (int64_t)(k & 1) * a.gcon * 4, a.gcon, blockIdx.x, p);
 }
 
 // One workgroup: totals of the start phases (g0 and the Cauchy step).
@@ -314,7 +310,7 @@ __global__ void __launch_bounds__(kRodBlock) k_fin(SolveArgs a)
     SolverState *st = a.state;
     if (st->done && MODE != kModeRefresh) return;
     double t[4];
-    sum_partials<kRodBlock / 64>(a.partial, a.gcon, t, lds);
+    sum_partials_split<kRodBlock / 64>(a.partial, a.gcon, t, lds);
     if (threadIdx.x != 0) return;
     if (MODE == kModeRefresh) {
         st->res = t[3];
