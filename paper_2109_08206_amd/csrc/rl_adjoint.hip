@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     }
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
-    partials_first_split(part, a.gcon, pf);
+    partials_first_split<kRodLoopBlock>(part, a.gcon, pf);
     // the recurrence's other inputs and the rod's direction and mobility do
     // not depend on the partials either
     const double bb0 = st->alpha0, tol = st->tol;

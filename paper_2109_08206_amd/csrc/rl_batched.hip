@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(CB)
         if (c0 + CB < hi) con_load_u<MODE>(in, c0 + CB, B);
     }
     if (MODE == kModeApply) return;
-    block_reduce4_all<CB / 64>(p, lds);
+    block_total4<CB / 64>(p, lds);
     if (threadIdx.x == 0) {
         double2 *dst = reinterpret_cast<double2 *>(b.partial + ((int64_t)par * b.ncb + tc.w) * 4);
         dst[0] = make_double2(p[0], p[1]);

@@ -7,56 +7,6 @@
 
 namespace rl {
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Sums p[0..2] and takes the max of p[3] over the workgroup (fixed tree);
-// every thread receives the result.  lds holds NW x 4 doubles plus 4.
-template <int NW>
-__device__ __forceinline__ void block_reduce4_all(double p[4], double (*lds)[4])
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    p[0] = wave_sum(p[0]);
-    p[1] = wave_sum(p[1]);
-    p[2] = wave_sum(p[2]);
-    p[3] = wave_max(p[3]);
-    if (lane == 0) {
-        lds[wid][0] = p[0];
-        lds[wid][1] = p[1];
-        lds[wid][2] = p[2];
-        lds[wid][3] = p[3];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < NW; ++w) {
-            p[0] += lds[w][0];
-            p[1] += lds[w][1];
-            p[2] += lds[w][2];
-            p[3] = fmax(p[3], lds[w][3]);
-        }
-        lds[NW][0] = p[0];
-        lds[NW][1] = p[1];
-        lds[NW][2] = p[2];
-        lds[NW][3] = p[3];
-    }
-    __syncthreads();
-    p[0] = lds[NW][0];
-    p[1] = lds[NW][1];
-    p[2] = lds[NW][2];
-    p[3] = lds[NW][3];
-    __syncthreads();
-}
-
 // Wave total of a double by DPP lane moves, without the LDS crossbar: two
 // quad permutations, the half-row and the row mirror leave every lane of a
 // row of 16 holding that row's total (each step adds a lane's value to its
@@ -132,20 +82,22 @@ __device__ __forceinline__ void partial_put(double *P, int count, int b, const d
 }
 
 struct PartFirst {
-    double2 u, v;
+    double2 u, v, u2, v2;
 };
 
-// the thread's first slot (clamped: any count >= 1 gives an in-bounds address;
-// with count <= 0 nothing is read)
+// the thread's slots b and b + NT (clamped: count >= 1 gives in-bounds
+// addresses).  The loads are unconditional (see rod_rec_load), so a kernel
+// that issues them before its records can reduce them while the records are
+// still in flight.
+template <int NT>
 __device__ __forceinline__ void partials_first_split(const double *__restrict__ P, int count, PartFirst &F)
 {
-    F.u = F.v = make_double2(0.0, 0.0);
-    if (count > 0) {
-        const double2 *Q = reinterpret_cast<const double2 *>(P);
-        const int b = min((int)threadIdx.x, count - 1);
-        F.u = Q[b];
-        F.v = Q[count + b];
-    }
+    const double2 *Q = reinterpret_cast<const double2 *>(P);
+    const int b = min((int)threadIdx.x, count - 1), b2 = min((int)threadIdx.x + NT, count - 1);
+    F.u = Q[b];
+    F.v = Q[count + b];
+    F.u2 = Q[b2];
+    F.v2 = Q[count + b2];
 }
 
 // Totals of the `count` slots at `P` (split layout), identical in every
@@ -163,7 +115,13 @@ __device__ __forceinline__ void sum_partials_split_from(const PartFirst &F, cons
         p[2] += F.v.x;
         p[3] = fmax(p[3], F.v.y);
     }
-    for (int b = threadIdx.x + NT; b < count; b += NT) {
+    if ((int)threadIdx.x + NT < count) {
+        p[0] += F.u2.x;
+        p[1] += F.u2.y;
+        p[2] += F.v2.x;
+        p[3] = fmax(p[3], F.v2.y);
+    }
+    for (int b = threadIdx.x + 2 * NT; b < count; b += NT) {
         const double2 u = Q[b], v = Q[count + b];
         p[0] += u.x;
         p[1] += u.y;
@@ -178,7 +136,7 @@ __device__ __forceinline__ void sum_partials_split(const double *__restrict__ P,
                                                    double (*lds)[4])
 {
     PartFirst F;
-    partials_first_split(P, count, F);
+    partials_first_split<NW * 64>(P, count, F);
     sum_partials_split_from<NW>(F, P, count, p, lds);
 }
 
@@ -233,7 +191,7 @@ __device__ __forceinline__ void sum_partials_from(const PartFirst &F, const doub
             }
         }
     }
-    block_reduce4_all<NW>(p, lds);
+    block_total4<NW>(p, lds);
 }
 
 template <int NW>
@@ -373,16 +331,22 @@ struct RodLoads {
     RodRec p[kRodRounds], q[kRodRounds];  // the first rounds of the P and Q sides
 };
 
+// A lane past its rod's list reads a record of zeros instead of branching
+// around the loads: unconditional loads let the compiler's wait counts follow
+// each load, so work that needs only earlier loads does not wait for these.
+// The array is writable (and never written) so that the compiler cannot fold
+// the loads of its zeros into branches.
+static __device__ double kZeroRecord[4] = {0.0, 0.0, 0.0, 0.0};
+
 __device__ __forceinline__ void rod_rec_load(const double2 *st, const double *geo, int c, int end, RodRec &R)
 {
-    const double2 z = make_double2(0.0, 0.0);
-    R.s = R.g0 = R.g1 = z;
-    if (c < end) {
-        const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
-        R.s = st[c];
-        R.g0 = gd[0];
-        R.g1 = gd[1];
-    }
+    const bool ok = c < end;
+    const double2 *sp = ok ? st + c : reinterpret_cast<const double2 *>(kZeroRecord);
+    const double2 *gd = ok ? reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c)
+                           : reinterpret_cast<const double2 *>(kZeroRecord);
+    R.s = *sp;
+    R.g0 = gd[0];
+    R.g1 = gd[1];
 }
 
 // The arrays come as separate arguments so that a kernel can take them in
@@ -392,14 +356,14 @@ __device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qpt
                                          const double2 *stq, const double *geo, const double *qgeo, int64_t r,
                                          bool active, int sub, RodLoads &L)
 {
-    L.pb = L.pe = L.qb = L.qe = 0;
     L.ps = L.qs = 0x7fffffff;
-    if (active) {
-        L.pb = pptr[r] + sub;
-        L.pe = pptr[r + 1];
-        L.qb = qptr[r] + sub;
-        L.qe = qptr[r + 1];
-    }
+    // an inactive lane reads rod 0's offsets (n >= 1) and keeps an empty list
+    const int64_t rr = active ? r : 0;
+    const int pb = pptr[rr], pe = pptr[rr + 1], qb = qptr[rr], qe = qptr[rr + 1];
+    L.pb = active ? pb + sub : 0;
+    L.pe = active ? pe : 0;
+    L.qb = active ? qb + sub : 0;
+    L.qe = active ? qe : 0;
 #pragma unroll
     for (int i = 0; i < kRodRounds; ++i) {
         rod_rec_load(st, geo, L.pb + i * kRodLanes, L.pe, L.p[i]);

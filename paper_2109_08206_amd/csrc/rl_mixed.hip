@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     // and the previous iteration's partials (read for nothing on a first iteration)
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
-    partials_first_split(part, a.gcon, pf);
+    partials_first_split<kRodLoopBlock>(part, a.gcon, pf);
     if (st->done || st->refresh) return;
     double alpha;
     if (first) {

@@ -183,25 +183,30 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const unsigned tile = xcd_tile(blockIdx.x, nblk);
     const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < n;
-    // the incidence records depend neither on the step length nor on the stop
-    // flag: load them first (after the stop they are read for nothing)
+    // The previous iteration's partials, the inputs of the step rule and the
+    // stop flag go out first (the partials are read for nothing at k = 0),
+    // then the incidence records, which depend neither on the step length nor
+    // on the flag (after the stop they are read for nothing).  All loads are
+    // unconditional, so the step-length reduction waits only for the first
+    // group and runs while the records are in flight.
+    const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
+    PartFirst pf;
+    if (MODE == kModeLoop) partials_first_split<kRodLoopBlock>(part, a.gcon, pf);
+    DecideIn din{};
+    if (MODE == kModeLoop) din = decide_in(a.state, a.alpha_buf, k);
+    const int done = MODE != kModeApply ? a.state->done : 0;
+    // a compiler barrier keeps those loads ahead of the records'
+    __asm__ volatile("" ::: "memory");
     RodLoads L;
     rod_load(pptr, qptr, st, stq, geo, qgeo, r, active, sub, L);
     if (BIL) rod_load_split(a, r, active, L);
-    // so are the previous iteration's partials (read for nothing at k = 0)
-    const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
-    PartFirst pf;
-    if (MODE == kModeLoop) partials_first_split(part, a.gcon, pf);
-    // and the rod's direction and mobility and the inputs of the step rule,
-    // which do not depend on the partials either
+    // and the rod's direction and mobility, which the reduction does not need
     const int64_t rr = active ? r : 0;
     const double dx = a.dir[3 * rr], dy = a.dir[3 * rr + 1], dz = a.dir[3 * rr + 2];
     double apar, aperp, rperp;
     rod_mob(a, rr, UNI, apar, aperp, rperp);
-    DecideIn din{};
-    if (MODE == kModeLoop) din = decide_in(a.state, a.alpha_buf, k);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (MODE != kModeApply && a.state->done) {
+    if (MODE != kModeApply && done) {
         if (MODE == kModeLoop && lead) report_progress(a.progress, k, true);
         return;
     }
