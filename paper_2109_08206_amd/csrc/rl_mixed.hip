@@ -54,16 +54,20 @@ struct Rec32 {
     float4 s, g;
 };
 
+// unconditional, like the FP64 records: a lane past its list reads zeros
 __device__ __forceinline__ void rec32_load(const float4 *__restrict__ st, const float4 *__restrict__ geo, int c,
                                            int end, Rec32 &R)
 {
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    R.s = R.g = z;
-    if (c < end) {
-        R.s = st[c];
-        R.g = geo[c];
-    }
+    const bool ok = c < end;
+    const float4 *z = reinterpret_cast<const float4 *>(kZeroRecord);
+    R.s = *(ok ? st + c : z);
+    R.g = *(ok ? geo + c : z);
 }
+
+// records of each side held in registers across the step-length wait (the
+// FP32 records are half the size of the FP64 ones, so one more round fits;
+// at 12 constraints per rod no record is read after the wait or read twice)
+constexpr int kRounds32 = 3;
 
 __device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3], float m[3])
 {
@@ -77,15 +81,14 @@ __device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3]
 }
 
 __device__ __forceinline__ void side32(float sign, const float4 *__restrict__ st, const float4 *__restrict__ geo,
-                                       int b, int e, const Rec32 &r1, const Rec32 &r2, float a32, float f[3],
-                                       float m[3])
+                                       int b, int e, const Rec32 *rr, float a32, float f[3], float m[3])
 {
-    if (b >= e) return;
-    add32(sign, delta_prime(r1.s, a32), r1.g, f, m);
-    const int b2 = b + kRodLanes;
-    if (b2 >= e) return;
-    add32(sign, delta_prime(r2.s, a32), r2.g, f, m);
-    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
+#pragma unroll
+    for (int i = 0; i < kRounds32; ++i) {
+        if (b + i * kRodLanes >= e) return;
+        add32(sign, delta_prime(rr[i].s, a32), rr[i].g, f, m);
+    }
+    for (int c = b + kRounds32 * kRodLanes; c < e; c += kRodLanes) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
 }
 
 __device__ __forceinline__ float u32_along(float4 g, const float v[3], const float w[3])
@@ -94,14 +97,14 @@ __device__ __forceinline__ float u32_along(float4 g, const float v[3], const flo
 }
 
 __device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__restrict__ geo, int b, int e,
-                                       const Rec32 &r1, const Rec32 &r2, const float v[3], const float w[3])
+                                       const Rec32 *rr, const float v[3], const float w[3])
 {
-    if (b >= e) return;
-    u[b] = u32_along(r1.g, v, w);
-    const int b2 = b + kRodLanes;
-    if (b2 >= e) return;
-    u[b2] = u32_along(r2.g, v, w);
-    for (int c = b2 + kRodLanes; c < e; c += kRodLanes) u[c] = u32_along(geo[c], v, w);
+#pragma unroll
+    for (int i = 0; i < kRounds32; ++i) {
+        if (b + i * kRodLanes >= e) return;
+        u[b + i * kRodLanes] = u32_along(rr[i].g, v, w);
+    }
+    for (int c = b + kRounds32 * kRodLanes; c < e; c += kRodLanes) u[c] = u32_along(geo[c], v, w);
 }
 
 // Rod kernel of the inner FP32 iteration: the force of delta' on the rod,
@@ -121,27 +124,35 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const unsigned tile = xcd_tile(blockIdx.x, nblk);
     const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < n;
-    int pb = 0, pe = 0, qb = 0, qe = 0;
-    if (active) {
-        pb = pptr[r] + sub;
-        pe = pptr[r + 1];
-        qb = qptr[r] + sub;
-        qe = qptr[r + 1];
-    }
-    // two rounds of both sides in flight before the flags are read
-    Rec32 p1, q1, p2, q2;
-    rec32_load(s32, g32, pb, pe, p1);
-    rec32_load(sq32, gq32, qb, qe, q1);
-    rec32_load(s32, g32, pb + kRodLanes, pe, p2);
-    rec32_load(sq32, gq32, qb + kRodLanes, qe, q2);
-    // and the previous iteration's partials (read for nothing on a first iteration)
+    // the previous iteration's partials (read for nothing on a first
+    // iteration) and the flags first, then the offsets and the records, all
+    // unconditional, so that the step-length reduction waits only for the
+    // first group
     const double *part = a.partial + (int64_t)((k - 1) & 1) * a.gcon * 4;
     PartFirst pf;
     partials_first_split<kRodLoopBlock>(part, a.gcon, pf);
-    if (st->done || st->refresh) return;
+    const bool halt = st->done || st->refresh;
+    const double aprev = a.alpha_buf[(k - 1) & 1], inner_tol = st->inner_tol, amin = st->amin, amax = st->amax;
+    const long long max_iter = st->max_iter;
+    const double alpha_first = st->alpha;
+    __asm__ volatile("" ::: "memory");
+    const int64_t rr = active ? r : 0;
+    const int pb0 = pptr[rr], pe0 = pptr[rr + 1], qb0 = qptr[rr], qe0 = qptr[rr + 1];
+    const int pb = active ? pb0 + sub : 0, pe = active ? pe0 : 0;
+    const int qb = active ? qb0 + sub : 0, qe = active ? qe0 : 0;
+    // kRounds32 rounds of both sides in flight before the flags are read
+    Rec32 P[kRounds32], Q[kRounds32];
+#pragma unroll
+    for (int i = 0; i < kRounds32; ++i) {
+        rec32_load(s32, g32, pb + i * kRodLanes, pe, P[i]);
+        rec32_load(sq32, gq32, qb + i * kRodLanes, qe, Q[i]);
+    }
+    // keeps the loads ahead of the flag test (see k_rod)
+    __asm__ volatile("" ::: "memory");
+    if (halt) return;
     double alpha;
     if (first) {
-        alpha = st->alpha;
+        alpha = alpha_first;
         if (blockIdx.x == 0 && threadIdx.x == 0) a.alpha_buf[k & 1] = alpha;
     } else {
         double t[4];
@@ -151,16 +162,16 @@ __global__ void __launch_bounds__(kRodLoopBlock)
         if (!isfinite(ss) || !isfinite(sy) || !isfinite(yy) || !isfinite(res)) {
             done = 1;
             status = RL_ERR_NONFINITE;
-        } else if (k >= st->max_iter) {
+        } else if (k >= max_iter) {
             done = 1;
             status = RL_NOT_CONVERGED;
-        } else if (res <= st->inner_tol || ss == 0.0 || k - round_start >= kInnerRoundCap) {
+        } else if (res <= inner_tol || ss == 0.0 || k - round_start >= kInnerRoundCap) {
             refresh = 1;
         }
-        double al = a.alpha_buf[(k - 1) & 1];
+        double al = aprev;
         if (sy > 0.0) {
             al = ((k - 1) % 2 == 0) ? ss / sy : sy / yy;
-            al = al < st->amin ? st->amin : (al > st->amax ? st->amax : al);
+            al = al < amin ? amin : (al > amax ? amax : al);
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             if (done || refresh) {
@@ -182,8 +193,8 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     }
     const float a32 = (float)alpha;
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    side32(1.f, a.st32, a.geo32, pb, pe, p1, p2, a32, f, m);
-    side32(-1.f, a.stq32, a.qgeo32, qb, qe, q1, q2, a32, f, m);
+    side32(1.f, a.st32, a.geo32, pb, pe, P, a32, f, m);
+    side32(-1.f, a.stq32, a.qgeo32, qb, qe, Q, a32, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -208,8 +219,8 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const float md = dx * m[0] + dy * m[1] + dz * m[2];
     const float v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
     const float w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
-    emit32(a.uP32, a.geo32, pb, pe, p1, p2, v, w);
-    emit32(a.uQ32, a.qgeo32, qb, qe, q1, q2, v, w);
+    emit32(a.uP32, a.geo32, pb, pe, P, v, w);
+    emit32(a.uQ32, a.qgeo32, qb, qe, Q, v, w);
 }
 
 struct Con32Loads {

@@ -205,6 +205,9 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const double dx = a.dir[3 * rr], dy = a.dir[3 * rr + 1], dz = a.dir[3 * rr + 2];
     double apar, aperp, rperp;
     rod_mob(a, rr, UNI, apar, aperp, rperp);
+    // and a second barrier keeps all of them ahead of the stop test (the
+    // compiler would otherwise move them past it, behind the flag's latency)
+    __asm__ volatile("" ::: "memory");
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (MODE != kModeApply && done) {
         if (MODE == kModeLoop && lead) report_progress(a.progress, k, true);
