@@ -315,9 +315,12 @@ __device__ __forceinline__ double gamma_free(double gam, double g, double alpha)
 // sub + kRodLanes, ... of each side.  Its first kRodRounds records of both
 // sides are loaded into registers together, before the step-length wait;
 // longer lists continue in a loop.  The registers stay live for the
-// contact-velocity emission.
+// contact-velocity emission.  Three rounds (12 records a side) cover the
+// rods with more contacts than average, whose later records would otherwise
+// be read after the wait and read again for the emission, and which hold up
+// their workgroup; the cost is occupancy (4 waves per SIMD instead of 5).
 #ifndef RL_ROD_ROUNDS
-#define RL_ROD_ROUNDS 2
+#define RL_ROD_ROUNDS 3
 #endif
 constexpr int kRodRounds = RL_ROD_ROUNDS;
 
