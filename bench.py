@@ -460,6 +460,108 @@ def form_kmc(args, torch, rl, rodsynth) -> dict:
     return out
 
 
+def form_dynamics(args, torch, rl, rodsynth) -> dict:
+    """Whole coupled steps of a confined, crosslinked suspension: 100,000
+    rods of length 1 in a spherical shell at volume fraction 0.05 (the
+    setting of the paper's polarity sorting in a shell, scaled up), 400,000
+    kinesin-5 crosslinkers inside the shell, each step being the crosslinker
+    kinetics, the doubly bound crosslinkers as links, and the filament step
+    with contacts, links and the shell as one constraint set, Brownian
+    forces, a warm start from the previous step and the virial stress.  The
+    random numbers of every step are drawn before the timed region."""
+    import math
+    dev = torch.device("cuda:0")
+    n, m = args.rods, args.crosslinkers
+    v = math.pi * (0.5 * rodsynth.DIAM) ** 2 + 4.0 / 3.0 * math.pi * (0.5 * rodsynth.DIAM) ** 3
+    radius = (n * v / 0.05 * 3.0 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    s = rodsynth.confined_system(n, seed=args.seed, radius=radius)
+    wl = [rodsynth.shell_wall(s, radius)]
+    um3 = 602.214076
+    kT = 4.11e-3
+    kw = dict(eps=1625.0, Ka=90.9 / um3, koS=0.11, Ke=90.9 / um3, koD=0.11, kappa=300.0, rest=0.053, lam=0.258,
+              kT=kT, rcs=0.039, rcd=0.11, dU=1.0)
+    kp = rl.kmc_params(**kw)
+    x = torch.as_tensor(s.x, device=dev)
+    quat = torch.as_tensor(s.quat, device=dev)
+    F = torch.as_tensor(s.force, device=dev)
+    slv = rl.Solver(box=s.box, diam=s.diam, cutoff=s.cutoff, eta=s.eta, dt=s.dt, tol=1e-8, max_iter=200_000)
+    state = torch.zeros(m, dtype=torch.int32, device=dev)
+    rod = torch.full((m, 2), -1, dtype=torch.int32, device=dev)
+    arc = torch.zeros((m, 2), dtype=torch.float64, device=dev)
+    c = 0.5 * s.box
+    xl = torch.as_tensor(rodsynth.crosslinker_positions_ball(m, (c, c, c), radius, args.seed), device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    total = args.kmc_populate + args.warmup + args.steps
+    us = [torch.rand((m, 4), dtype=torch.float64, device=dev, generator=gen) for _ in range(total)]
+    xis = [torch.randn((m, 3), dtype=torch.float64, device=dev, generator=gen) for _ in range(total)]
+    noise = [torch.randn((n, 6), dtype=torch.float64, device=dev, generator=gen) for _ in range(args.warmup + args.steps)]
+    d = slv.directors(quat)
+    for k in range(args.kmc_populate):
+        slv.kmc_step(x, d, 1.0, kp, state, rod, arc, xl, us[k], xis[k])
+
+    def coupled(k):
+        dk = slv.directors(quat)
+        slv.kmc_step(x, dk, 1.0, kp, state, rod, arc, xl, us[args.kmc_populate + k], xis[args.kmc_populate + k])
+        p, q, arm, kap, rest, key = slv.kmc_links(kp, state, rod, arc, keys=True)
+        _, info, npairs = slv.step(x, quat, 1.0, F=F, links=(p, q, arm, kap, rest, None, key), walls=wl,
+                                   noise=noise[k], kT=kT, warm_start=True, stress=True)
+        return info, npairs, int(p.shape[0]), slv.last_wall_contacts
+
+    for k in range(args.warmup):
+        coupled(k)
+    slv.profile_enable(args.profile_every)
+    slv.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, status, res = [], 0, 0.0
+    counts = []
+    for k in range(args.warmup, args.warmup + args.steps):
+        info, npairs, nlinks, nwall = coupled(k)
+        iters.append(info.iterations)
+        status = max(status, info.status)
+        res = max(res, info.residual)
+        counts.append((npairs, nlinks, nwall))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = slv.profile_read()
+    slv.profile_enable(0)
+    stress = slv.last_stress
+    slv.close()
+    npairs, nlinks, nwall = counts[-1]
+    nc = npairs + nlinks + nwall
+    nq = npairs + nlinks
+    # general-mode loop kernels: the contact-only records plus per rod its two
+    # split indices (8 B) and per constraint the compliance (8 B); a wall
+    # constraint has no Q side
+    kb = {"rod": 40 * n + 56 * nc + 56 * nq, "con": 60 * nc + 24 * nq}
+    avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
+           "con": prof["con_ms"] / max(1, prof["con_launches"])}
+    names = {"rod": "k_rod<2,true,gen>", "con": con_kernel_name(nc)[:-1] + ",gen>"}
+    dom = max(avg, key=avg.get)
+    achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
+    return {
+        "metric": "dynamics form: coupled steps per second (crosslinker kinetics, then contacts, crosslinker links "
+                  "and the confining shell as one constraint set with Brownian forces, warm-started, with the "
+                  "virial stress)",
+        "value": args.steps / el, "unit": "coupled steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{n} rods L=1 d=0.025 in a spherical shell of radius {radius:.3f} (phi 0.05), "
+                               f"isotropic; {m} kinesin-5 crosslinkers in the shell; kT 4.11e-3 pN um; dt 1e-4 s",
+                   "rods": n, "crosslinkers": m, "radius": round(radius, 4), "seed": args.seed},
+        "bbpgd_iters_per_s": sum(iters) / el, "iterations_per_step": iters, "max_residual": res, "status": status,
+        "constraints_last_step": {"contacts": npairs, "links": nlinks, "wall": nwall},
+        "stress_trace_last_step": {"contacts": float(stress[0].trace()), "links": float(stress[1].trace())},
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": kb[dom], "avg_launch_us": 1e3 * avg[dom]},
+        "kernels": {names[k]: {"avg_us": 1e3 * avg[k], "alg_bytes": kb[k],
+                               "alg_gbps": kb[k] / (avg[k] * 1e-3) / 1e9 if avg[k] > 0 else 0.0,
+                               "samples": prof[f"{k}_launches"]} for k in ("rod", "con")},
+    }
+
+
 def kmc_cpu_baseline(s, kw, state, rod, arc, xl) -> dict:
     """The oracle's kinetics step (every crosslinker against every
     filament) on 2,000 crosslinkers sampled across the four states."""
@@ -501,9 +603,11 @@ def main() -> int:
     ap.add_argument("--profile-every", type=int, default=32, help="sample kernel events every k-th iteration (each sample costs a few us of launch overhead)")
     ap.add_argument("--cpu-iters", type=int, default=800, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["step", "precision", "batched", "adjoint", "kmc"], default="step",
+    ap.add_argument("--form", choices=["step", "precision", "batched", "adjoint", "kmc", "dynamics"], default="step",
                     help="step: the FP64 whole-step benchmark (default); precision: FP32-mixed vs FP64; "
-                         "batched: many systems in one batched solve; adjoint: gradient of a rollout")
+                         "batched: many systems in one batched solve; adjoint: gradient of a rollout; "
+                         "kmc: crosslinker kinetics; dynamics: coupled steps of a confined, crosslinked, "
+                         "Brownian suspension")
     ap.add_argument("--rollout-steps", type=int, default=100, help="adjoint form: rollout length")
     ap.add_argument("--checkpoint-every", type=int, default=10, help="adjoint form: checkpoint interval")
     ap.add_argument("--cg-tol", type=float, default=1e-10, help="adjoint form: CG relative residual")
@@ -539,6 +643,9 @@ def main() -> int:
         return 0
     if args.form == "kmc":
         print(json.dumps(form_kmc(args, torch, rl, rodsynth)), flush=True)
+        return 0
+    if args.form == "dynamics":
+        print(json.dumps(form_dynamics(args, torch, rl, rodsynth)), flush=True)
         return 0
     dev = torch.device("cuda:0")
     s = rodsynth.cfg_paper_scale(args.seed, n=args.rods)

@@ -198,6 +198,8 @@ typedef struct {
     const double *kappa;    /* [n_links] stiffness (device) */
     const double *rest;     /* [n_links] rest length (device) */
     const double *anchor;   /* [n_links][3] fixed points (device; may be NULL if no q < 0) */
+    const int64_t *key;     /* [n_links] warm-start keys, distinct, 0 <= key < 2^62 (device; may be NULL:
+                               a link's key is its index) */
 } rl_links;
 
 /* Link geometry and rows: writes length[n_links], e[n_links][3], q[n_links]
@@ -330,7 +332,8 @@ int rl_solve_lcp_noalloc(rl_handle h, int64_t n, const double *dir, const double
  *                      step on this handle that also had warm_start set,
  *                      matched by constraint (a contact by its two rods and
  *                      periodic shift in the caller's numbering, a link by
- *                      its index; wall contacts start at 0), and keep this
+ *                      its key, rl_links.key, or by its index when that is
+ *                      NULL; wall contacts start at 0), and keep this
  *                      step's forces for the next one.  The result is the
  *                      same problem's solution; only the start differs.
  *   stress[18]         host out: the virial of the constraint forces between
@@ -535,12 +538,14 @@ int rl_kmc_step(rl_handle h, int64_t n, const double *x, const double *dir, cons
 /* The doubly bound crosslinkers as bilateral links (rl_links) for the
  * filament step: p = head A's filament, q = head B's, arm = their
  * arclengths, kappa = kp->kappa, rest = kp->rest + diam (the tether's rest
- * length between the axes, eq. Ucl), in crosslinker order; each array has
- * room for capacity links.  *n_links (host) gets the count; if it exceeds
- * capacity nothing is written and RL_ERR_CAPACITY is returned.
- * Synchronises. */
+ * length between the axes, eq. Ucl), in crosslinker order; key (may be
+ * NULL) = the crosslinker's index, a warm-start key (rl_links.key) that
+ * stays with the crosslinker while it is bound, whatever binds or unbinds
+ * elsewhere.  Each array has room for capacity links.  *n_links (host) gets
+ * the count; if it exceeds capacity nothing is written and RL_ERR_CAPACITY
+ * is returned.  Synchronises. */
 int rl_kmc_links(rl_handle h, const rl_kmc_params *kp, const rl_crosslinkers *xl, int64_t capacity, int32_t *p,
-                 int32_t *q, double *arm, double *kappa, double *rest, int64_t *n_links);
+                 int32_t *q, double *arm, double *kappa, double *rest, int64_t *key, int64_t *n_links);
 
 /* Kernel timing with HIP events on the handle's stream, for measurement.
  * With every > 0, every every-th BBPGD iteration of later solves records

@@ -47,7 +47,7 @@ class SolveInfo(C.Structure):
 
 class RLLinks(C.Structure):
     _fields_ = [("n_links", C.c_int64), ("p", C.c_void_p), ("q", C.c_void_p), ("arm", C.c_void_p),
-                ("kappa", C.c_void_p), ("rest", C.c_void_p), ("anchor", C.c_void_p)]
+                ("kappa", C.c_void_p), ("rest", C.c_void_p), ("anchor", C.c_void_p), ("key", C.c_void_p)]
 
 
 class RLWall(C.Structure):
@@ -158,7 +158,7 @@ def load(path: Optional[str] = None) -> C.CDLL:
             "rl_kmc_effective_volume": ([H, C.POINTER(KmcParams), C.POINTER(C.c_double)], C.c_int),
             "rl_kmc_step": ([H, I64, P, P, P, D, C.POINTER(KmcParams), C.POINTER(RLCrosslinkers), P, P, P,
                              C.POINTER(C.c_int64)], C.c_int),
-            "rl_kmc_links": ([H, C.POINTER(KmcParams), C.POINTER(RLCrosslinkers), I64, P, P, P, P, P,
+            "rl_kmc_links": ([H, C.POINTER(KmcParams), C.POINTER(RLCrosslinkers), I64, P, P, P, P, P, P,
                               C.POINTER(C.c_int64)], C.c_int),
         }
         for name, (args, res) in sig.items():
@@ -392,14 +392,15 @@ class Solver:
         return gamma, U, _result(info)
 
     @staticmethod
-    def links_struct(p, q, arm, kappa, rest, anchor=None):
-        """An rl_links over device tensors (kept alive by the caller)."""
+    def links_struct(p, q, arm, kappa, rest, anchor=None, key=None):
+        """An rl_links over device tensors (kept alive by the caller); key:
+        optional int64 warm-start keys."""
         torch = _torch()
         nl = p.shape[0]
         return RLLinks(nl, _ptr(p, torch.int32, (nl,), "p"), _ptr(q, torch.int32, (nl,), "q"),
                        _ptr(arm, torch.float64, (nl, 2), "arm"), _ptr(kappa, torch.float64, (nl,), "kappa"),
                        _ptr(rest, torch.float64, (nl,), "rest"),
-                       _ptr(anchor, torch.float64, (nl, 3), "anchor"))
+                       _ptr(anchor, torch.float64, (nl, 3), "anchor"), _ptr(key, torch.int64, (nl,), "key"))
 
     def assemble_links(self, x, dir_, length, p, q, arm, kappa, rest, anchor=None, F=None):
         """Link geometry: returns (length, e, q, cmp, flags)."""
@@ -470,8 +471,10 @@ class Solver:
             _ptr(event, torch.int32, (m,), "event"), counts), "rl_kmc_step")
         return [int(v) for v in counts]
 
-    def kmc_links(self, kp: KmcParams, state, rod, arc, capacity=None):
-        """The doubly bound crosslinkers as links: (p, q, arm, kappa, rest)."""
+    def kmc_links(self, kp: KmcParams, state, rod, arc, capacity=None, keys=False):
+        """The doubly bound crosslinkers as links: (p, q, arm, kappa, rest),
+        and with keys=True also their warm-start keys (the crosslinker
+        indices)."""
         torch = _torch()
         m = state.shape[0]
         cap = int(capacity) if capacity is not None else m
@@ -481,13 +484,16 @@ class Solver:
         arm = torch.empty((max(cap, 1), 2), dtype=torch.float64, device=dev)
         kap = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
         rest = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        key = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if keys else None
         X = RLCrosslinkers(m, _ptr(state, torch.int32, (m,), "state"), _ptr(rod, torch.int32, (m, 2), "rod"),
                            _ptr(arc, torch.float64, (m, 2), "arc"), None)
         cnt = C.c_int64(0)
         self._stream()
         self._check(self.lib.rl_kmc_links(self._h, C.byref(kp), C.byref(X), cap, _ptr(p), _ptr(q), _ptr(arm),
-                                          _ptr(kap), _ptr(rest), C.byref(cnt)), "rl_kmc_links")
+                                          _ptr(kap), _ptr(rest), _ptr(key), C.byref(cnt)), "rl_kmc_links")
         k = int(cnt.value)
+        if keys:
+            return p[:k], q[:k], arm[:k], kap[:k], rest[:k], key[:k]
         return p[:k], q[:k], arm[:k], kap[:k], rest[:k]
 
     def solve_general(self, dir_, length, pi, pj, e, arm, q, kind, cmp, F=None, gamma=None, U=None):
@@ -549,8 +555,9 @@ class Solver:
         tape: float64 device tensor for the step's constraint forces
         (TAPE_RECORD writes them, TAPE_REPLAY starts from them).
         x_unwrapped: [n, 3] centres without wrapping, advanced in place.
-        links: (p, q, arm, kappa, rest, anchor) device tensors (anchor may be
-        None), solved with the contacts; gamma_links receives their forces.
+        links: (p, q, arm, kappa, rest, anchor[, key]) device tensors (anchor may be
+        None; key: warm-start keys), solved with the contacts; gamma_links
+        receives their forces.
         walls: [(kind, p, a, r), ...].  The step's wall constraint count is
         left in self.last_wall_contacts.
         noise: [n, 6] N(0,1) draws with kT > 0: Brownian force.

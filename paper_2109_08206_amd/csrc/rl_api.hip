@@ -254,7 +254,8 @@ static int step_general(rl_ctx *h, int64_t n, double *x, double *quat, const dou
         RL_HIP(hipMemsetAsync(cpj + np + nl, 0xff, sizeof(int32_t) * nw, st));  // -1: no Q side
         RL_HIP(hipMemsetAsync(ckind + np + nl, 0, (size_t)nw, st));
     }
-    const StepList L{n, np, nl, nc, perm, cpi, cpj, (const int32_t *)h->buf[kWsStepImg], ds, ce, carm, phi, llen};
+    const StepList L{n, np, nl, nc, perm, cpi, cpj, (const int32_t *)h->buf[kWsStepImg], ds, ce, carm, phi, llen,
+                     lk ? lk->key : nullptr};
     if (ex->warm_start) {
         rc = warm_lookup(h, L, cgam);
         if (rc) return rc;
@@ -600,7 +601,7 @@ int rl_step(rl_handle h, int64_t n, double *x, double *quat, const double *len, 
     const int32_t *img = (const int32_t *)h->buf[kWsStepImg];
     rc = assemble_impl(h, n, xs, ds, lsv, len0, np, pi, pj, img, Fs, phi, e, arm, q);
     if (rc) return rc;
-    const StepList L{n, np, 0, np, perm, pi, pj, img, ds, e, arm, phi, nullptr};
+    const StepList L{n, np, 0, np, perm, pi, pj, img, ds, e, arm, phi, nullptr, nullptr};
     if (tape_mode == RL_TAPE_REPLAY && np > 0) {
         RL_HIP(hipMemcpyAsync(gamma, gamma_tape, sizeof(double) * np, hipMemcpyDeviceToDevice, h->stream));
     } else if (warm) {

@@ -354,7 +354,7 @@ hipError_t launch_brownian(hipStream_t st, int64_t n, const double *dir, const d
 
 // Key of input constraint c in the caller's numbering: a contact by its two
 // rods (smaller caller index first, the shift negated when they swap) and
-// shift, a link by its index; wall contacts have no key (0).
+// shift, a link by its key (or index); wall contacts have no key (0).
 __device__ __forceinline__ unsigned long long step_key(const StepList &L, int64_t c)
 {
     if (c < L.np) {
@@ -369,7 +369,10 @@ __device__ __forceinline__ unsigned long long step_key(const StepList &L, int64_
         }
         return (1ull << 62) | (a << 37) | (b << 12) | (unsigned long long)img;
     }
-    if (c < L.np + L.nl) return (2ull << 62) | (unsigned long long)(c - L.np);
+    if (c < L.np + L.nl) {
+        const int64_t k = c - L.np;
+        return (2ull << 62) | ((unsigned long long)(L.link_key ? L.link_key[k] : k) & ((1ull << 62) - 1ull));
+    }
     return 0ull;
 }
 

@@ -337,6 +337,7 @@ struct StepList {
     const double *dir;                 // solver order
     const double *e, *arm, *phi;       // input order (phi: contacts)
     const double *link_len;            // [nl]
+    const int64_t *link_key;           // [nl] warm-start keys (null: the index)
 };
 // Brownian force: Ftot = F + sqrt(2 kT/h) M^(-1/2) noise (caller order)
 hipError_t launch_brownian(hipStream_t st, int64_t n, const double *dir, const double *len, double len0, double diam,

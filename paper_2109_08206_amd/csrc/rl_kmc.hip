@@ -475,7 +475,7 @@ __global__ void k_kmc_dflag(int64_t m, const int32_t *__restrict__ state, int *_
 __global__ void k_kmc_links(int64_t m, const int32_t *__restrict__ state, const int32_t *__restrict__ rod,
                             const double *__restrict__ arc, const int *__restrict__ off, double kappa, double rest,
                             int32_t *__restrict__ p, int32_t *__restrict__ q, double *__restrict__ arm,
-                            double *__restrict__ kap, double *__restrict__ rst)
+                            double *__restrict__ kap, double *__restrict__ rst, int64_t *__restrict__ key)
 {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= m || state[c] != RL_XL_D) return;
@@ -486,6 +486,7 @@ __global__ void k_kmc_links(int64_t m, const int32_t *__restrict__ state, const 
     arm[2 * k + 1] = arc[2 * c + 1];
     kap[k] = kappa;
     rst[k] = rest;
+    if (key) key[k] = c;
 }
 
 // V_bd by Gauss-Legendre quadrature (8 nodes per panel, 256 panels; the
@@ -655,7 +656,7 @@ int rl_kmc_step(rl_handle h, int64_t n, const double *x, const double *dir, cons
 }
 
 int rl_kmc_links(rl_handle h, const rl_kmc_params *kp, const rl_crosslinkers *xl, int64_t capacity, int32_t *p,
-                 int32_t *q, double *arm, double *kappa, double *rest, int64_t *n_links)
+                 int32_t *q, double *arm, double *kappa, double *rest, int64_t *key, int64_t *n_links)
 {
     if (!h) {
         set_error("handle is NULL");
@@ -693,7 +694,7 @@ int rl_kmc_links(rl_handle h, const rl_kmc_params *kp, const rl_crosslinkers *xl
     if (nl == 0) return RL_OK;
     hipLaunchKernelGGL(k_kmc_links, dim3(grid_of(m, 256)), dim3(256), 0, st, m, (const int32_t *)xl->state,
                        (const int32_t *)xl->rod, (const double *)xl->arc, (const int *)off, kp->kappa,
-                       kp->rest + h->prm.diam, p, q, arm, kappa, rest);
+                       kp->rest + h->prm.diam, p, q, arm, kappa, rest, key);
     RL_HIP(hipGetLastError());
     RL_HIP(hipStreamSynchronize(st));
     return RL_OK;

@@ -397,6 +397,21 @@ def crosslinker_positions(m: int, box: float, seed: int = 0) -> np.ndarray:
     return np.ascontiguousarray(np.where(x >= box, 0.0, x))
 
 
+def crosslinker_positions_ball(m: int, centre, radius: float, seed: int = 0) -> np.ndarray:
+    """m unbound crosslinkers uniform in a ball (a confined suspension's
+    shell), by rejection from its bounding cube, from PCG64([seed, 14])."""
+    rng = np.random.Generator(np.random.PCG64([seed, 14]))
+    c = np.asarray(centre, dtype=np.float64)
+    out = np.empty((m, 3))
+    k = 0
+    while k < m:
+        y = c + radius * (rng.random((2 * (m - k) + 16, 3)) * 2.0 - 1.0)
+        y = y[np.linalg.norm(y - c, axis=1) <= radius][: m - k]
+        out[k:k + len(y)] = y
+        k += len(y)
+    return np.ascontiguousarray(out)
+
+
 def kmc_draws(m: int, seed: int, step: int):
     """The random numbers of one kinetics step: u[m][4] uniform in [0, 1) and
     xi[m][3] standard normal, from PCG64([seed, 13, step])."""

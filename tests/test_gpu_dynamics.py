@@ -5,8 +5,9 @@ force, warm starts and the virial stress.
   velocities with F_nc = F + sqrt(2 kT/h) M^(-1/2) xi.
 * Warm start: a step repeated on the same state starts at its own solution
   (0 iterations): the keys (two rods and shift in the caller's numbering,
-  link index) find every constraint again although the pairs are built in
-  the solver's own rod order.  A short warm-started run with fresh random
+  link key or index) find every constraint again although the pairs are
+  built in the solver's own rod order, and links handed in another order
+  with the same keys find theirs.  A short warm-started run with fresh random
   loads follows the oracle's cold-started run step by step (U is unique, so
   the start does not change it).
 * Stress: the contact and link virials against the oracle's, on systems
@@ -75,6 +76,77 @@ def test_warm_start_finds_every_constraint_again(gpu_lib):
     assert n2 == n1 and i2.status == gpu_lib.OK
     assert i2.iterations == 0 and i2.residual <= 1e-8
     assert torch.allclose(U1, U2, rtol=0, atol=1e-12 * float(U1.abs().max()))
+
+
+def test_warm_start_follows_links_by_key(gpu_lib):
+    """Links handed in another order with the same keys (as the crosslinker
+    kinetics does, whose link list shifts whenever a crosslinker binds or
+    unbinds) still find their previous forces: the repeated step starts at
+    its solution.  Without keys (matched by index) the permuted links start
+    from the wrong forces."""
+    s = rodsynth.relaxed_system(2000, seed=5, phi=0.05)
+    rng = np.random.default_rng(9)
+    nl = 600
+    a = rng.integers(0, s.n, nl)
+    b = (a + 1 + rng.integers(0, s.n - 1, nl)) % s.n
+    arm = rng.uniform(-0.5, 0.5, (nl, 2))
+    d = oracle.directors(s.quat)
+    pa = s.x[a] + arm[:, :1] * d[a]
+    pb = s.x[b] + arm[:, 1:] * d[b]
+    sep = pb - pa
+    sep -= s.box * np.round(sep / s.box)
+    rest = np.linalg.norm(sep, axis=1) * rng.uniform(0.8, 1.2, nl)
+    kap = np.full(nl, 300.0)
+    keys = rng.permutation(10 * nl)[:nl].astype(np.int64)
+    perm = rng.permutation(nl)
+    x0, q0, F = _t(s.x), _t(s.quat), _t(s.force)
+
+    def links(order, with_keys):
+        out = (_t(a[order], torch.int32), _t(b[order], torch.int32), _t(arm[order]), _t(kap[order]),
+               _t(rest[order]), None)
+        return out + (_t(keys[order], torch.int64),) if with_keys else out
+
+    with _solver(gpu_lib, s) as slv:
+        ident = np.arange(nl)
+        g1 = torch.empty(nl, dtype=torch.float64, device="cuda")
+        U1, i1, _ = slv.step(x0.clone(), q0.clone(), 1.0, F=F, links=links(ident, True), gamma_links=g1,
+                             warm_start=True)
+        assert i1.status == gpu_lib.OK and i1.iterations > 0
+        g2 = torch.empty(nl, dtype=torch.float64, device="cuda")
+        U2, i2, _ = slv.step(x0.clone(), q0.clone(), 1.0, F=F, links=links(perm, True), gamma_links=g2,
+                             warm_start=True)
+        assert i2.status == gpu_lib.OK and i2.iterations == 0
+        assert torch.allclose(U1, U2, rtol=0, atol=1e-12 * float(U1.abs().max()))
+        assert torch.allclose(g1[torch.as_tensor(perm, device="cuda")], g2, rtol=0,
+                              atol=1e-12 * float(g1.abs().max()))
+        # matched by index instead: the permuted links start from other links' forces
+        slv.step(x0.clone(), q0.clone(), 1.0, F=F, links=links(ident, False), warm_start=True)
+        _, i3, _ = slv.step(x0.clone(), q0.clone(), 1.0, F=F, links=links(perm, False), warm_start=True)
+        assert i3.status == gpu_lib.OK and i3.iterations > 0
+
+
+def test_kmc_link_keys_are_crosslinker_indices(gpu_lib):
+    s = rodsynth.cfg_small(2)
+    d = oracle.directors(s.quat)
+    um3 = oracle.AVOGADRO_UM3_PER_UM
+    kw = dict(eps=1625.0, Ka=[90.9 / um3] * 2, koS=[33.0] * 2, Ke=[90.9 / um3] * 2, koD=[33.0] * 2, kappa=300.0,
+              rest=0.053, lam=0.258, kT=oracle.KT_300K, rcs=0.039, rcd=0.11, dU=1.0)
+    ko = oracle.kmc_params(diam=s.diam, dt=s.dt, **kw)
+    vbd = oracle.kmc_effective_volume(ko)
+    m = 2000
+    xl = oracle.Crosslinkers(np.zeros(m, np.int32), np.full((m, 2), -1, np.int32), np.zeros((m, 2)),
+                             rodsynth.crosslinker_positions(m, s.box, 4))
+    for k in range(6):
+        u, xi = rodsynth.kmc_draws(m, 4, k)
+        oracle.kmc_step(s.x, d, 1.0, s.box, ko, vbd, xl, u, xi)
+    with _solver(gpu_lib, s) as slv:
+        kp = gpu_lib.kmc_params(**kw)
+        p, q, arm, kap, rest, key = slv.kmc_links(kp, _t(xl.state, torch.int32), _t(xl.rod, torch.int32),
+                                                  _t(xl.arc), keys=True)
+    dd = np.flatnonzero(xl.state == oracle.KMC_D)
+    assert dd.size > 10
+    assert np.array_equal(key.cpu().numpy(), dd)
+    assert np.array_equal(p.cpu().numpy(), xl.rod[dd, 0]) and np.array_equal(q.cpu().numpy(), xl.rod[dd, 1])
 
 
 def test_warm_started_run_follows_the_oracle(gpu_lib):
