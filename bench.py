@@ -505,7 +505,7 @@ def form_dynamics(args, torch, rl, rodsynth) -> dict:
         slv.kmc_step(x, dk, 1.0, kp, state, rod, arc, xl, us[args.kmc_populate + k], xis[args.kmc_populate + k])
         p, q, arm, kap, rest, key = slv.kmc_links(kp, state, rod, arc, keys=True)
         _, info, npairs = slv.step(x, quat, 1.0, F=F, links=(p, q, arm, kap, rest, None, key), walls=wl,
-                                   noise=noise[k], kT=kT, warm_start=True, stress=True)
+                                   noise=noise[k], kT=kT, warm_start=not args.cold_start, stress=True)
         return info, npairs, int(p.shape[0]), slv.last_wall_contacts
 
     for k in range(args.warmup):
@@ -549,7 +549,8 @@ def form_dynamics(args, torch, rl, rodsynth) -> dict:
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{n} rods L=1 d=0.025 in a spherical shell of radius {radius:.3f} (phi 0.05), "
                                f"isotropic; {m} kinesin-5 crosslinkers in the shell; kT 4.11e-3 pN um; dt 1e-4 s",
-                   "rods": n, "crosslinkers": m, "radius": round(radius, 4), "seed": args.seed},
+                   "rods": n, "crosslinkers": m, "radius": round(radius, 4), "seed": args.seed,
+                   "warm_start": not args.cold_start},
         "bbpgd_iters_per_s": sum(iters) / el, "iterations_per_step": iters, "max_residual": res, "status": status,
         "constraints_last_step": {"contacts": npairs, "links": nlinks, "wall": nwall},
         "stress_trace_last_step": {"contacts": float(stress[0].trace()), "links": float(stress[1].trace())},
@@ -616,6 +617,7 @@ def main() -> int:
     ap.add_argument("--phi", type=float, default=None, help="volume fraction override (precision form)")
     ap.add_argument("--crosslinkers", type=int, default=400_000, help="kmc form: crosslinkers")
     ap.add_argument("--kmc-populate", type=int, default=50, help="kmc form: untimed steps that populate the states")
+    ap.add_argument("--cold-start", action="store_true", help="dynamics form: every solve from zero forces")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy a 1 GiB device buffer once (reference for HBM counters)")
     args = ap.parse_args()
