@@ -462,18 +462,17 @@ def form_kmc(args, torch, rl, rodsynth) -> dict:
 
 def form_dynamics(args, torch, rl, rodsynth) -> dict:
     """Whole coupled steps of a confined, crosslinked suspension: 100,000
-    rods of length 1 in a spherical shell at volume fraction 0.05 (the
-    setting of the paper's polarity sorting in a shell, scaled up), 400,000
-    kinesin-5 crosslinkers inside the shell, each step being the crosslinker
+    rods of length 1 in a spherical shell at the density of the paper's
+    confined suspension (3,200 rods in a shell of radius 3 um, so radius
+    3 (n/3200)^(1/3)), 400,000 kinesin-5 crosslinkers inside the shell,
+    each step being the crosslinker
     kinetics, the doubly bound crosslinkers as links, and the filament step
     with contacts, links and the shell as one constraint set, Brownian
     forces, a warm start from the previous step and the virial stress.  The
     random numbers of every step are drawn before the timed region."""
-    import math
     dev = torch.device("cuda:0")
     n, m = args.rods, args.crosslinkers
-    v = math.pi * (0.5 * rodsynth.DIAM) ** 2 + 4.0 / 3.0 * math.pi * (0.5 * rodsynth.DIAM) ** 3
-    radius = (n * v / 0.05 * 3.0 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    radius = 3.0 * (n / 3200.0) ** (1.0 / 3.0)
     s = rodsynth.confined_system(n, seed=args.seed, radius=radius)
     wl = [rodsynth.shell_wall(s, radius)]
     um3 = 602.214076
@@ -547,7 +546,8 @@ def form_dynamics(args, torch, rl, rodsynth) -> dict:
         "value": args.steps / el, "unit": "coupled steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{n} rods L=1 d=0.025 in a spherical shell of radius {radius:.3f} (phi 0.05), "
+        "config": {"workload": f"{n} rods L=1 d=0.025 in a spherical shell of radius {radius:.3f} (the density of "
+                               f"the paper's 3,200 rods in radius 3), "
                                f"isotropic; {m} kinesin-5 crosslinkers in the shell; kT 4.11e-3 pN um; dt 1e-4 s",
                    "rods": n, "crosslinkers": m, "radius": round(radius, 4), "seed": args.seed,
                    "warm_start": not args.cold_start},
