@@ -199,7 +199,9 @@ typedef struct {
     const double *rest;     /* [n_links] rest length (device) */
     const double *anchor;   /* [n_links][3] fixed points (device; may be NULL if no q < 0) */
     const int64_t *key;     /* [n_links] warm-start keys, distinct, 0 <= key < 2^62 (device; may be NULL:
-                               a link's key is its index) */
+                               a link's key is its index).  Keys are not checked: a repeated key or one
+                               outside the range only gives a link another link's start (the solution is
+                               the same) */
 } rl_links;
 
 /* Link geometry and rows: writes length[n_links], e[n_links][3], q[n_links]
