@@ -531,7 +531,10 @@ int rl_kmc_effective_volume(rl_handle h, const rl_kmc_params *kp, double *vbd);
  * dir, len as for rl_build_pairs; not changed).  u, xi: the step's random
  * numbers (device).  event[m] (device, may be NULL): RL_EV_* per crosslinker.
  * counts[5] (host, may be NULL): crosslinkers per event.  RL_ERR_ARG on bad
- * parameters, a bad state or head, or a box below the reach.
+ * parameters, a bad state or head, or a box below the reach (nothing is
+ * changed then), and when the axes of more than 128 filaments pass within
+ * the query radius of one crosslinker (a few pass at the paper's densities):
+ * that crosslinker is left unchanged while the others have stepped.
  * Synchronises. */
 int rl_kmc_step(rl_handle h, int64_t n, const double *x, const double *dir, const double *len, double len0,
                 const rl_kmc_params *kp, const rl_crosslinkers *xl, const double *u, const double *xi,
