@@ -309,8 +309,9 @@ __device__ __forceinline__ void stage_cell(CellStage &S, int q0, int m, V3 shift
 }
 
 // Pass modes: count pairs per rod, fill the per-rod slots, or emit every
-// pair once as a sort key (pi, pj, shift) with its flags at a slot reserved
-// per flush (the list is put in canonical order by a radix sort afterwards).
+// pair once as a key (pi, pj, shift) with its flags at a slot reserved per
+// flush (the list is put in canonical order afterwards: bucketed by pi, then
+// sorted per rod).
 enum PairPass : int { kPairCount = 0, kPairFill = 1, kPairEmit = 2 };
 
 // exclusive prefix of v over the workgroup; tot = the sum (lds: 5 ints)
@@ -493,6 +494,33 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(GridDev g, double diam, do
     }
 }
 
+// Emitted pair keys (pi, pj, shift) into the canonical order: bucketed by
+// pi (a histogram, its scan, a scatter), then each rod's short list sorted
+// by (pj, shift).  The keys are distinct, so the result is the order of the
+// keys whatever order the scatter's atomics took.
+__global__ void k_pair_hist(int64_t m, const unsigned long long *__restrict__ keys, int shift, int *__restrict__ cnt)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    atomicAdd(cnt + (int)(keys[t] >> shift), 1);
+}
+
+__global__ void k_pair_scatter(int64_t m, const unsigned long long *__restrict__ keys,
+                               const uint8_t *__restrict__ kflags, int ibits, const int *__restrict__ off,
+                               int *__restrict__ cur, int32_t *__restrict__ pi, int32_t *__restrict__ pj,
+                               int32_t *__restrict__ img, uint8_t *__restrict__ flags)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const unsigned long long k = keys[t];
+    const int a = (int)(k >> (ibits + 12));
+    const int slot = off[a] + atomicAdd(cur + a, 1);
+    pi[slot] = a;
+    pj[slot] = (int32_t)((k >> 12) & ((1ull << ibits) - 1ull));
+    img[slot] = (int32_t)(k & 0xfffull);
+    flags[slot] = kflags[t];
+}
+
 // copies of centres, directors, lengths (and forces) in cell order
 __global__ void k_gather_rods(int64_t n, const int *__restrict__ perm, const double *__restrict__ x,
                               const double *__restrict__ dir, const double *__restrict__ len, double len0,
@@ -657,9 +685,9 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
                            cell_start, cell_cur, sorted, xs, ds, ls);
     }
     RL_HIP(hipGetLastError());
-    // one pass emitting sort keys (pi, pj, shift), then a radix sort into the
-    // canonical order; rod counts above 2^26 do not fit the 64-bit key and
-    // take the counting and filling passes with a per-rod sort instead
+    // one pass emitting keys (pi, pj, shift), then buckets by pi and a per-rod
+    // sort into the canonical order; rod counts above 2^26 do not fit the
+    // 64-bit key and take the counting and filling passes instead
     int ibits = 1;
     while ((1LL << ibits) < n) ++ibits;
     const bool emit = 2 * ibits + 12 <= 64;
@@ -734,8 +762,19 @@ static int pairs_core(rl_ctx *h, int64_t n, const double *x, const double *dir, 
     if (emit) {
         auto *ekeys = (unsigned long long *)h->buf[kWsEmitKeys];
         auto *eflags = (uint8_t *)h->buf[kWsEmitFlags];
-        const int rc = sort_pair_keys(h, total, 2 * ibits + 12, ekeys, eflags, ibits, pi, pj, img, flags);
+        RL_HIP(hipMemsetAsync(pcnt, 0, sizeof(int) * n, st));
+        hipLaunchKernelGGL(k_pair_hist, dim3(grid_of(total)), dim3(kBlock), 0, st, total,
+                           (const unsigned long long *)ekeys, ibits + 12, pcnt);
+        RL_HIP(hipGetLastError());
+        const int rc = device_scan(h, pcnt, n, poff, nullptr);
         if (rc) return rc;
+        RL_HIP(hipMemsetAsync(pcnt, 0, sizeof(int) * n, st));
+        hipLaunchKernelGGL(k_pair_scatter, dim3(grid_of(total)), dim3(kBlock), 0, st, total,
+                           (const unsigned long long *)ekeys, (const uint8_t *)eflags, ibits, (const int *)poff, pcnt,
+                           pi, pj, img, flags);
+        RL_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_sort_pairs, dim3(grid_of(n)), dim3(kBlock), 0, st, n, (const int *)poff, pj, img, flags);
+        RL_HIP(hipGetLastError());
         return RL_OK;
     }
     if (internal)

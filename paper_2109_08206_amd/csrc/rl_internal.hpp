@@ -204,7 +204,7 @@ enum Slot : int {
     kWsStepU, kWsScan, kWsLenMax, kWsPP, kWsGeo, kWsSt, kWsAlpha, kWsQpos, kWsQgeo, kWsStq, kWsSortIdx, kWsSortTmp, kWsCellKey, kWsFs,
     kWsSt32, kWsStq32, kWsGeo32, kWsUP32, kWsQgeo32, kWsUQ32,
     kWsBatchTab, kWsBatchOff, kWsBatchState, kWsBatchAlpha, kWsBatchCtr, kWsBatchPartial,
-    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags, kWsEmitKeys2, kWsEmitFlags2,
+    kWsBatchPartial2, kWsBatchDone, kWsBatchMap, kWsGeo2, kWsPairCache, kWsScanTmp, kWsEmitCount, kWsEmitKeys, kWsEmitFlags,
     kWsAdjG, kWsAdjUbar, kWsAdjQbd, kWsAdjCs, kWsAdjCr, kWsAdjCq, kWsAdjSc, kWsAdjPQ, kWsAdjDmob,
     kWsAdjEbar, kWsAdjArmbar, kWsAdjQbar, kWsAdjDbar, kWsAdjGbar, kWsAdjFs, kWsQv, kWsUP, kWsUQ,
     kWsGenKey, kWsGenKeyOut, kWsGenOrd, kWsGenPi, kWsGenPj, kWsGenE, kWsGenArm, kWsGenQ, kWsGenCmp, kWsGenGamma,
@@ -249,12 +249,9 @@ int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total, v
 int scan_tmp_bytes(int64_t m, size_t *bytes);
 // bytes of the allocation-free scratch array on each device
 constexpr size_t kScratchBytes = (size_t)RL_NOALLOC_SCRATCH_BYTES;
-// sorts m pair keys ((pi << (ibits + 12)) | (pj << 12) | shift, `bits` wide)
-// with their flags and writes the canonical pi, pj, img, flags lists
+// sorts m (key, value) pairs by key (the warm start's constraint keys)
 int sort_key_values(rl_ctx *h, int64_t m, const unsigned long long *keys, const double *vals,
                     unsigned long long *keys_out, double *vals_out);
-int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *keys, const uint8_t *kflags, int ibits,
-                   int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags);
 // Pair list in the solver's own rod order (cell order).  On return *perm
 // (device, n) maps solver rod -> caller rod and xs/ds/ls hold the rods'
 // centres, directors and lengths in solver order (handle workspace).

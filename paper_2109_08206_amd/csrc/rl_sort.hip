@@ -61,38 +61,6 @@ int device_scan(rl_ctx *h, const int *in, int64_t m, int *out, int64_t *total, v
     return RL_OK;
 }
 
-__global__ void k_decode_pairs(int64_t m, const unsigned long long *__restrict__ keys,
-                               const uint8_t *__restrict__ kflags, int ibits, int32_t *__restrict__ pi,
-                               int32_t *__restrict__ pj, int32_t *__restrict__ img, uint8_t *__restrict__ flags)
-{
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= m) return;
-    const unsigned long long k = keys[t];
-    pi[t] = (int32_t)(k >> (ibits + 12));
-    pj[t] = (int32_t)((k >> 12) & ((1ull << ibits) - 1ull));
-    img[t] = (int32_t)(k & 0xfffull);
-    flags[t] = kflags[t];
-}
-
-int sort_pair_keys(rl_ctx *h, int64_t m, int bits, const unsigned long long *keys, const uint8_t *kflags, int ibits,
-                   int32_t *pi, int32_t *pj, int32_t *img, uint8_t *flags)
-{
-    hipStream_t st = h->stream;
-    int werr = 0;
-    auto *k2 = (unsigned long long *)ws_get(h, kWsEmitKeys2, sizeof(unsigned long long) * m, &werr);
-    auto *f2 = (uint8_t *)ws_get(h, kWsEmitFlags2, (size_t)m, &werr);
-    if (werr) return werr;
-    size_t tmp_bytes = 0;
-    RL_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, k2, kflags, f2, (int)m, 0, bits, st));
-    void *tmp = ws_get(h, kWsSortTmp, tmp_bytes, &werr);
-    if (werr) return werr;
-    RL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, k2, kflags, f2, (int)m, 0, bits, st));
-    hipLaunchKernelGGL(k_decode_pairs, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, m,
-                       (const unsigned long long *)k2, (const uint8_t *)f2, ibits, pi, pj, img, flags);
-    RL_HIP(hipGetLastError());
-    return RL_OK;
-}
-
 // sorts m (key, value) pairs by key into keys_out / vals_out
 int sort_key_values(rl_ctx *h, int64_t m, const unsigned long long *keys, const double *vals,
                     unsigned long long *keys_out, double *vals_out)
