@@ -682,6 +682,18 @@ static hipError_t record_sample(rl_ctx *h, int v, long long it, const SolveArgs 
     return hipGetLastError();
 }
 
+// U = M (D gamma + F) in the caller's order (perm may be null)
+static hipError_t launch_velocity(hipStream_t st, const SolveArgs &a, bool uni, const double *F, const int *perm,
+                                  double *U)
+{
+    const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
+    if (uni)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<true>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<false>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
+    return hipGetLastError();
+}
+
 int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamma_out, rl_solve_info *info,
                const int *perm)
 {
@@ -691,6 +703,7 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, st, h->state, p.tol, (long long)p.max_iter);
     RL_HIP(hipGetLastError());
     long long iters = 0, refreshes = 0;
+    bool vel_queued = false;
     if (a.nc > 0 && p.precision == RL_FP32_MIXED) {
         int rc = prepare_mixed(h, a);
         if (rc) return rc;
@@ -800,29 +813,28 @@ int solve_impl(rl_ctx *h, SolveArgs &a, const double *F, double *U, double *gamm
                 __builtin_ia32_pause();
             }
         }
+        // the state copy, the forces and the velocities are queued together
+        // and waited for once
         RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+        if (gamma_out) {
+            hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
+                               (const double2 *)a.st, gamma_out);
+            RL_HIP(hipGetLastError());
+        }
+        if (U && a.n > 0) {
+            RL_HIP(launch_velocity(st, a, uni, F, perm, U));
+            vel_queued = true;
+        }
         RL_HIP(hipStreamSynchronize(st));
         {
             const int rc = drain(true, h->state_host->iter);
             if (rc) return rc;
         }
         iters = h->state_host->iter;
-        if (gamma_out) {
-            hipLaunchKernelGGL(k_unpack_gamma, dim3(grid_of(a.nc)), dim3(kBlock), 0, st, a.nc,
-                               (const double2 *)a.st, gamma_out);
-            RL_HIP(hipGetLastError());
-        }
     } else {
         RL_HIP(hipMemcpyAsync(h->state_host, h->state, sizeof(SolverState), hipMemcpyDeviceToHost, st));
     }
-    if (U && a.n > 0) {
-        const dim3 grid(grid_of(a.n, kRodBlock / kRodLanes));
-        if (uni)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<true>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
-        else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_velocity<false>), grid, dim3(kRodBlock), 0, st, a, F, perm, U);
-        RL_HIP(hipGetLastError());
-    }
+    if (U && a.n > 0 && !vel_queued) RL_HIP(launch_velocity(st, a, uni, F, perm, U));
     RL_HIP(hipStreamSynchronize(st));
     const SolverState &s = *h->state_host;
     const int status = a.nc > 0 ? s.status : RL_OK;
