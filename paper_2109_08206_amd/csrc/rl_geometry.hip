@@ -534,13 +534,45 @@ __global__ void k_gather_rods(int64_t n, const int *__restrict__ perm, const dou
     ls[t] = len ? len[i] : len0;
 }
 
-// order each rod's pairs by (pj, img): short insertion sort per rod
+// order each rod's pairs by (pj, img).  Up to 16 pairs (nearly every rod)
+// are sorted in registers by an odd-even transposition network over keys
+// (pj, img, flags) packed into 64 bits, so the loads go out together and the
+// stores once; longer lists take an insertion sort in memory.
+constexpr int kSortRegs = 16;
+
 __global__ void k_sort_pairs(int64_t n, const int *__restrict__ poff, int32_t *__restrict__ pj,
                              int32_t *__restrict__ img, uint8_t *__restrict__ flags)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int b = poff[i], e = poff[i + 1];
+    const int cnt = e - b;
+    if (cnt <= 1) return;
+    if (cnt <= kSortRegs) {
+        unsigned long long key[kSortRegs];
+#pragma unroll
+        for (int k = 0; k < kSortRegs; ++k)
+            key[k] = k < cnt ? ((unsigned long long)(unsigned)pj[b + k] << 16) |
+                                   ((unsigned long long)(unsigned)img[b + k] << 4) | (unsigned long long)flags[b + k]
+                             : ~0ull;
+#pragma unroll
+        for (int r = 0; r < kSortRegs; ++r)
+#pragma unroll
+            for (int k = r & 1; k + 1 < kSortRegs; k += 2) {
+                const unsigned long long lo = key[k] < key[k + 1] ? key[k] : key[k + 1];
+                const unsigned long long hi = key[k] < key[k + 1] ? key[k + 1] : key[k];
+                key[k] = lo;
+                key[k + 1] = hi;
+            }
+#pragma unroll
+        for (int k = 0; k < kSortRegs; ++k)
+            if (k < cnt) {
+                pj[b + k] = (int32_t)(key[k] >> 16);
+                img[b + k] = (int32_t)((key[k] >> 4) & 0xfffull);
+                flags[b + k] = (uint8_t)(key[k] & 15ull);
+            }
+        return;
+    }
     for (int k = b + 1; k < e; ++k) {
         const int32_t kj = pj[k], ki = img[k];
         const uint8_t kf = flags[k];
