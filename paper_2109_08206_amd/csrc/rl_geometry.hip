@@ -534,14 +534,16 @@ __global__ void k_gather_rods(int64_t n, const int *__restrict__ perm, const dou
     ls[t] = len ? len[i] : len0;
 }
 
-// order each rod's pairs by (pj, img).  Up to 16 pairs (nearly every rod)
+// order each rod's pairs by (pj, img).  Up to 32 pairs (every rod at the paper's densities)
 // are sorted in registers by an odd-even transposition network over keys
 // (pj, img, flags) packed into 64 bits, so the loads go out together and the
 // stores once; longer lists take an insertion sort in memory.
-constexpr int kSortRegs = 16;
+constexpr int kSortRegs = 32;
 
-__global__ void k_sort_pairs(int64_t n, const int *__restrict__ poff, int32_t *__restrict__ pj,
-                             int32_t *__restrict__ img, uint8_t *__restrict__ flags)
+// (256-thread groups, so that the 32 keys stay in registers)
+__global__ void __launch_bounds__(256)
+    k_sort_pairs(int64_t n, const int *__restrict__ poff, int32_t *__restrict__ pj, int32_t *__restrict__ img,
+                 uint8_t *__restrict__ flags)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
