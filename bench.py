@@ -61,6 +61,12 @@ def con_kernel_name(nc: int, fp32: bool = False) -> str:
     return "k_con<2,256,8>" if wide else "k_con<2,512,4>"
 
 
+def rod_rounds(n: int, nc: int) -> int:
+    """Rounds of incidence records the loop's rod kernel holds in registers:
+    five above 8 constraints per rod (contact-only sets), else three."""
+    return 5 if nc > 8 * n else 3
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -201,8 +207,9 @@ def form_precision(args, torch, rl, rodsynth) -> dict:
         prof = slv.profile_read()
         slv.close()
         kb = (kernel_bytes if prec == rl.FP64 else kernel_bytes32)(s.n, npairs)
-        names = {"rod": "k_rod<2,false>", "con": con_kernel_name(npairs)} if prec == rl.FP64 else \
-            {"rod": "k_rod32<false>", "con": con_kernel_name(npairs, fp32=True)}
+        rr = rod_rounds(s.n, npairs)
+        names = {"rod": f"k_rod<2,false,{rr}>", "con": con_kernel_name(npairs)} if prec == rl.FP64 else \
+            {"rod": f"k_rod32<false,{rr}>", "con": con_kernel_name(npairs, fp32=True)}
         avg, kern = _kernel_summary(prof, kb, names)
         dom = max(avg, key=avg.get)
         ach = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
@@ -536,7 +543,7 @@ def form_dynamics(args, torch, rl, rodsynth) -> dict:
     kb = {"rod": 40 * n + 56 * nc + 56 * nq, "con": 60 * nc + 24 * nq}
     avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
            "con": prof["con_ms"] / max(1, prof["con_launches"])}
-    names = {"rod": "k_rod<2,true,gen>", "con": con_kernel_name(nc)[:-1] + ",gen>"}
+    names = {"rod": "k_rod<2,true,gen,3>", "con": con_kernel_name(nc)[:-1] + ",gen>"}
     dom = max(avg, key=avg.get)
     achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     return {
@@ -684,7 +691,7 @@ def main() -> int:
     kb = kernel_bytes(s.n, npairs)
     avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
            "con": prof["con_ms"] / max(1, prof["con_launches"])}
-    names = {"rod": "k_rod<2,true>", "con": con_kernel_name(npairs)}
+    names = {"rod": f"k_rod<2,true,{rod_rounds(s.n, npairs)}>", "con": con_kernel_name(npairs)}
     dom = max(avg, key=avg.get)
     achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     traffic = measured_traffic(dom)

@@ -77,7 +77,7 @@ __device__ __forceinline__ void latch(const BatchArgs &b, int s, long long k, co
 
 // The tile table and the arrays of the first loads lead the argument list
 // (14 dwords, preloaded into registers).
-template <int MODE, bool UNI, int RB>
+template <int MODE, bool UNI, int RB, int R>
 __global__ void __launch_bounds__(RB)
     k_rod_b(const int4 *__restrict__ rt, const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr,
             const double2 *sg, const double2 *sgq, const double *__restrict__ geo, const double *__restrict__ qgeo,
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(RB)
     const int64_t r = (int64_t)t0.x + threadIdx.x / kRodLanes;
     const bool active = r < t0.y;
     // records first: they depend neither on the system's state nor on its step
-    RodLoads L;
+    RodLoads<R> L;
     rod_load(pptr, qptr, sg, sgq, geo, qgeo, r, active, sub, L);
     // the counter and the system's partials are read before the stop flag,
     // so that the three loads are in flight together.  The counter base is
@@ -324,17 +324,32 @@ static inline unsigned xcd_tile_host(unsigned b, unsigned nblocks)
     return (b % 8) * (nblocks / 8) + b / 8;
 }
 
+template <int MODE, int RB, int R>
+static void launch_rod_b_r(hipStream_t st, const BatchArgs &b, bool uni, int i)
+{
+    const SolveArgs &a = b.a;
+    if (uni)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, true, RB, R>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b.rt,
+                           a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, false, RB, R>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b.rt,
+                           a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
+}
+
+// As in the single solve, the loop kernel holds five rounds of records when
+// the batch as a whole is dense, in 256-thread groups (1,024-thread groups
+// leave 128 registers a lane, too few for five rounds).
 template <int MODE, int RB>
 static hipError_t launch_rod_b(hipStream_t st, const BatchArgs &b, bool uni, int i)
 {
     if (b.nrb == 0) return hipSuccess;
-    const SolveArgs &a = b.a;
-    if (uni)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, true, RB>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b.rt,
-                           a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod_b<MODE, false, RB>), dim3(pad8(b.nrb)), dim3(RB), 0, st, b.rt,
-                           a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
+    if constexpr (MODE == kModeLoop && RB == 256) {
+        if (rod_rounds_for(b.a.n, b.a.nc) == kRodRoundsDense) {
+            launch_rod_b_r<MODE, RB, kRodRoundsDense>(st, b, uni, i);
+            return hipGetLastError();
+        }
+    }
+    launch_rod_b_r<MODE, RB, kRodRounds>(st, b, uni, i);
     return hipGetLastError();
 }
 

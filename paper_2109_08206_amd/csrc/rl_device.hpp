@@ -312,26 +312,33 @@ __device__ __forceinline__ double gamma_free(double gam, double g, double alpha)
 // Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
 // rod r, split over the kRodLanes lanes of the rod and combined by a fixed
 // tree.  The torque on the rod is dir x m.  A lane takes the records sub,
-// sub + kRodLanes, ... of each side.  Its first kRodRounds records of both
-// sides are loaded into registers together, before the step-length wait;
-// longer lists continue in a loop.  The registers stay live for the
-// contact-velocity emission.  Three rounds (12 records a side) cover the
-// rods with more contacts than average, whose later records would otherwise
-// be read after the wait and read again for the emission, and which hold up
-// their workgroup; the cost is occupancy (4 waves per SIMD instead of 5).
-#ifndef RL_ROD_ROUNDS
-#define RL_ROD_ROUNDS 3
-#endif
-constexpr int kRodRounds = RL_ROD_ROUNDS;
+// sub + kRodLanes, ... of each side.  Its first R records of both sides
+// (R rounds) are loaded into registers together, before the step-length
+// wait; longer lists continue in a loop.  The registers stay live for the
+// contact-velocity emission.  Records beyond the rounds are read after the
+// wait, read again for the emission (by then often evicted from the L2) and
+// hold up their workgroup, so the rounds should cover the rods with more
+// contacts than average; each round costs registers and so occupancy.
+// Three rounds (12 records a side, 4 waves per SIMD) for systems with a few
+// constraints per rod (the nematic suspension: 4.7 a side on average);
+// kRodRoundsDense = 5 (20 a side, 3 waves per SIMD) where the lists are
+// longer (isotropic phi 0.08 with lengths up to 1.5: 12 a side on average,
+// where three rounds re-read 22% of the records).
+constexpr int kRodRounds = 3;
+constexpr int kRodRoundsDense = 5;
+// the rounds for a system of n rods and nc constraints: the dense count
+// above 8 constraints per rod
+inline int rod_rounds_for(int64_t n, int64_t nc) { return nc > 8 * n ? kRodRoundsDense : kRodRounds; }
 
 struct RodRec {
     double2 s, g0, g1;  // (gamma, g), (ex, ey), (ez, s)
 };
 
+template <int R = kRodRounds>
 struct RodLoads {
     int pb, pe, qb, qe;
     int ps, qs;  // general constraint sets: first bilateral record of each side
-    RodRec p[kRodRounds], q[kRodRounds];  // the first rounds of the P and Q sides
+    RodRec p[R], q[R];  // the first rounds of the P and Q sides
 };
 
 // A lane past its rod's list reads a record of zeros instead of branching
@@ -355,9 +362,10 @@ __device__ __forceinline__ void rod_rec_load(const double2 *st, const double *ge
 // The arrays come as separate arguments so that a kernel can take them in
 // preloaded registers (leading kernel arguments) instead of from the
 // argument block.
+template <int R>
 __device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qptr, const double2 *st,
                                          const double2 *stq, const double *geo, const double *qgeo, int64_t r,
-                                         bool active, int sub, RodLoads &L)
+                                         bool active, int sub, RodLoads<R> &L)
 {
     L.ps = L.qs = 0x7fffffff;
     // an inactive lane reads rod 0's offsets (n >= 1) and keeps an empty list
@@ -368,20 +376,22 @@ __device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qpt
     L.qb = active ? qb + sub : 0;
     L.qe = active ? qe : 0;
 #pragma unroll
-    for (int i = 0; i < kRodRounds; ++i) {
+    for (int i = 0; i < R; ++i) {
         rod_rec_load(st, geo, L.pb + i * kRodLanes, L.pe, L.p[i]);
         rod_rec_load(stq, qgeo, L.qb + i * kRodLanes, L.qe, L.q[i]);
     }
 }
 
-__device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads &L)
+template <int R>
+__device__ __forceinline__ void rod_load(const SolveArgs &a, int64_t r, bool active, int sub, RodLoads<R> &L)
 {
     rod_load(a.pptr, a.qptr, a.st, a.stq, a.geo, a.qgeo, r, active, sub, L);
 }
 
 // general constraint sets: a rod's records are unilateral before ps (P side,
 // constraint index) and qs (Q side, list position), bilateral from there on
-__device__ __forceinline__ void rod_load_split(const SolveArgs &a, int64_t r, bool active, RodLoads &L)
+template <int R>
+__device__ __forceinline__ void rod_load_split(const SolveArgs &a, int64_t r, bool active, RodLoads<R> &L)
 {
     if (active) {
         L.ps = a.psplit[r];
@@ -408,30 +418,30 @@ __device__ __forceinline__ double gamma_of(double gam, double g, double alpha, i
     return gamma_prime<MODE>(gam, g, alpha);
 }
 
-template <int MODE, bool BIL = false>
+template <int MODE, bool BIL, int R>
 __device__ __forceinline__ void rod_side(double sign, const double2 *st, const double *geo, int b, int e, int split,
                                          const RodRec *rr, double alpha, double f[3], double m[3])
 {
 #pragma unroll
-    for (int i = 0; i < kRodRounds; ++i) {
+    for (int i = 0; i < R; ++i) {
         const int c = b + i * kRodLanes;
         if (c >= e) return;
         rod_add(sign, gamma_of<MODE, BIL>(rr[i].s.x, rr[i].s.y, alpha, c, split), rr[i].g0, rr[i].g1, f, m);
     }
-    for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
+    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) {
         const double2 sg = st[c];
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
         rod_add(sign, gamma_of<MODE, BIL>(sg.x, sg.y, alpha, c, split), gd[0], gd[1], f, m);
     }
 }
 
-template <int MODE, bool BIL = false>
-__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads &L, double alpha, double f[3],
+template <int MODE, bool BIL = false, int R>
+__device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads<R> &L, double alpha, double f[3],
                                                double m[3])
 {
     f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    rod_side<MODE, BIL>(1.0, a.st, a.geo, L.pb, L.pe, L.ps, L.p, alpha, f, m);
-    rod_side<MODE, BIL>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.qs, L.q, alpha, f, m);
+    rod_side<MODE, BIL, R>(1.0, a.st, a.geo, L.pb, L.pe, L.ps, L.p, alpha, f, m);
+    rod_side<MODE, BIL, R>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.qs, L.q, alpha, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -553,24 +563,27 @@ __device__ __forceinline__ double u_along(double2 g0, double2 g1, const double v
 // The lane's incidences in the same order as rod_accumulate: the first
 // rounds are still in registers, later ones are read again (moments after
 // the same lane read them).
+template <int R>
 __device__ __forceinline__ void emit_side(double *u, const double *geo, int b, int e, const RodRec *rr,
                                           const double v[3], const double w[3])
 {
 #pragma unroll
-    for (int i = 0; i < kRodRounds; ++i) {
+    for (int i = 0; i < R; ++i) {
         if (b + i * kRodLanes >= e) return;
         u[b + i * kRodLanes] = u_along(rr[i].g0, rr[i].g1, v, w);
     }
-    for (int c = b + kRodRounds * kRodLanes; c < e; c += kRodLanes) {
+    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) {
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
         u[c] = u_along(gd[0], gd[1], v, w);
     }
 }
 
-__device__ __forceinline__ void rod_emit_u(const SolveArgs &a, const RodLoads &L, const double v[3], const double w[3])
+template <int R>
+__device__ __forceinline__ void rod_emit_u(const SolveArgs &a, const RodLoads<R> &L, const double v[3],
+                                           const double w[3])
 {
-    emit_side(a.uP, a.geo, L.pb, L.pe, L.p, v, w);
-    emit_side(a.uQ, a.qgeo, L.qb, L.qe, L.q, v, w);
+    emit_side<R>(a.uP, a.geo, L.pb, L.pe, L.p, v, w);
+    emit_side<R>(a.uQ, a.qgeo, L.qb, L.qe, L.q, v, w);
 }
 
 struct ConLoadsU {

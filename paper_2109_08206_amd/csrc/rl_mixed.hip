@@ -64,10 +64,10 @@ __device__ __forceinline__ void rec32_load(const float4 *__restrict__ st, const 
     R.g = *(ok ? geo + c : z);
 }
 
-// records of each side held in registers across the step-length wait (the
-// FP32 records are half the size of the FP64 ones, so one more round fits;
-// at 12 constraints per rod no record is read after the wait or read twice)
-constexpr int kRounds32 = 3;
+// Records of each side held in registers across the step-length wait: as
+// in the FP64 rod kernel, three rounds where rods have a few constraints
+// and five on dense systems (rod_rounds_for); the FP32 records are half the
+// size of the FP64 ones, so five rounds keep 4 waves per SIMD.
 
 __device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3], float m[3])
 {
@@ -80,15 +80,16 @@ __device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3]
     m[2] += ds * g.z;
 }
 
+template <int R>
 __device__ __forceinline__ void side32(float sign, const float4 *__restrict__ st, const float4 *__restrict__ geo,
                                        int b, int e, const Rec32 *rr, float a32, float f[3], float m[3])
 {
 #pragma unroll
-    for (int i = 0; i < kRounds32; ++i) {
+    for (int i = 0; i < R; ++i) {
         if (b + i * kRodLanes >= e) return;
         add32(sign, delta_prime(rr[i].s, a32), rr[i].g, f, m);
     }
-    for (int c = b + kRounds32 * kRodLanes; c < e; c += kRodLanes) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
+    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
 }
 
 __device__ __forceinline__ float u32_along(float4 g, const float v[3], const float w[3])
@@ -96,15 +97,16 @@ __device__ __forceinline__ float u32_along(float4 g, const float v[3], const flo
     return g.x * (v[0] + g.w * w[0]) + g.y * (v[1] + g.w * w[1]) + g.z * (v[2] + g.w * w[2]);
 }
 
+template <int R>
 __device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__restrict__ geo, int b, int e,
                                        const Rec32 *rr, const float v[3], const float w[3])
 {
 #pragma unroll
-    for (int i = 0; i < kRounds32; ++i) {
+    for (int i = 0; i < R; ++i) {
         if (b + i * kRodLanes >= e) return;
         u[b + i * kRodLanes] = u32_along(rr[i].g, v, w);
     }
-    for (int c = b + kRounds32 * kRodLanes; c < e; c += kRodLanes) u[c] = u32_along(geo[c], v, w);
+    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) u[c] = u32_along(geo[c], v, w);
 }
 
 // Rod kernel of the inner FP32 iteration: the force of delta' on the rod,
@@ -112,7 +114,7 @@ __device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__re
 // form, as in the FP64 rod kernel).
 // The arrays of the first loads, the grid size and n lead the argument list
 // (14 dwords), so that they arrive in preloaded registers.
-template <bool UNI>
+template <bool UNI, int R>
 __global__ void __launch_bounds__(kRodLoopBlock)
     k_rod32(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const float4 *s32, const float4 *sq32,
             const float4 *__restrict__ g32, const float4 *__restrict__ gq32, unsigned nblk, int n, SolveArgs a,
@@ -140,10 +142,10 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const int pb0 = pptr[rr], pe0 = pptr[rr + 1], qb0 = qptr[rr], qe0 = qptr[rr + 1];
     const int pb = active ? pb0 + sub : 0, pe = active ? pe0 : 0;
     const int qb = active ? qb0 + sub : 0, qe = active ? qe0 : 0;
-    // kRounds32 rounds of both sides in flight before the flags are read
-    Rec32 P[kRounds32], Q[kRounds32];
+    // R rounds of both sides in flight before the flags are read
+    Rec32 P[R], Q[R];
 #pragma unroll
-    for (int i = 0; i < kRounds32; ++i) {
+    for (int i = 0; i < R; ++i) {
         rec32_load(s32, g32, pb + i * kRodLanes, pe, P[i]);
         rec32_load(sq32, gq32, qb + i * kRodLanes, qe, Q[i]);
     }
@@ -193,8 +195,8 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     }
     const float a32 = (float)alpha;
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    side32(1.f, a.st32, a.geo32, pb, pe, P, a32, f, m);
-    side32(-1.f, a.stq32, a.qgeo32, qb, qe, Q, a32, f, m);
+    side32<R>(1.f, a.st32, a.geo32, pb, pe, P, a32, f, m);
+    side32<R>(-1.f, a.stq32, a.qgeo32, qb, qe, Q, a32, f, m);
 #pragma unroll
     for (int o = 1; o < kRodLanes; o <<= 1) {
 #pragma unroll
@@ -219,8 +221,8 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const float md = dx * m[0] + dy * m[1] + dz * m[2];
     const float v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
     const float w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
-    emit32(a.uP32, a.geo32, pb, pe, P, v, w);
-    emit32(a.uQ32, a.qgeo32, qb, qe, Q, v, w);
+    emit32<R>(a.uP32, a.geo32, pb, pe, P, v, w);
+    emit32<R>(a.uQ32, a.qgeo32, qb, qe, Q, v, w);
 }
 
 struct Con32Loads {
@@ -305,6 +307,36 @@ __global__ void __launch_bounds__(CB)
 // 512 threads with 2 each
 static inline bool con32_wide(const SolveArgs &a) { return (a.nc + a.gcon - 1) / a.gcon > 2048; }
 
+// the FP32 rod kernel with R rounds of records, with dispatch-stamped events
+// when e0 is set
+template <int R>
+static void launch_rod32(hipStream_t st, const SolveArgs &a, bool uni, const dim3 &g, long long k, int fl,
+                         long long round_start, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0) {
+        if (uni)
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true, R>), g, dim3(kRodLoopBlock), 0, st, e0, e1, 0,
+                                  RL_ROD32_HOT(a, g), a, k, fl, round_start);
+        else
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false, R>), g, dim3(kRodLoopBlock), 0, st, e0, e1, 0,
+                                  RL_ROD32_HOT(a, g), a, k, fl, round_start);
+    } else {
+        if (uni)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true, R>), g, dim3(kRodLoopBlock), 0, st, RL_ROD32_HOT(a, g),
+                               a, k, fl, round_start);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false, R>), g, dim3(kRodLoopBlock), 0, st,
+                               RL_ROD32_HOT(a, g), a, k, fl, round_start);
+    }
+}
+
+static void launch_rod32_r(hipStream_t st, const SolveArgs &a, bool uni, bool dense, const dim3 &g, long long k,
+                           int fl, long long round_start, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    if (dense) launch_rod32<kRodRoundsDense>(st, a, uni, g, k, fl, round_start, e0, e1);
+    else launch_rod32<kRodRounds>(st, a, uni, g, k, fl, round_start, e0, e1);
+}
+
 int prepare_mixed(rl_ctx *h, SolveArgs &a)
 {
     int werr = 0;
@@ -348,6 +380,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
     bool first = true;
     const dim3 rgrid(rod_grid32(a.n));
     const bool wide = con32_wide(a);
+    const bool dense = rod_rounds_for(a.n, a.nc) == kRodRoundsDense;
     while (!h->state_host->done) {
         if (launched > p.max_iter + 4 * every + 64) {
             set_error("rl_solve_lcp: mixed-precision loop did not stop");
@@ -364,14 +397,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                 for (int e = 0; e < 4; ++e)
                     if (!h->ev[nev][e]) RL_HIP(hipEventCreateWithFlags(&h->ev[nev][e], hipEventDisableSystemFence));
                 h->ev_iter[nev] = k;
-                if (uni)
-                    hipExtLaunchKernelGGL(k_rod32<true>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
-                                          h->ev[nev][1], 0, RL_ROD32_HOT(a, rgrid), a, (long long)k, fl,
-                                          (long long)round_start);
-                else
-                    hipExtLaunchKernelGGL(k_rod32<false>, rgrid, dim3(kRodLoopBlock), 0, st, h->ev[nev][0],
-                                          h->ev[nev][1], 0, RL_ROD32_HOT(a, rgrid), a, (long long)k, fl,
-                                          (long long)round_start);
+                launch_rod32_r(st, a, uni, dense, rgrid, k, fl, round_start, h->ev[nev][0], h->ev[nev][1]);
                 if (wide)
                     hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
                                           h->ev[nev][2], h->ev[nev][3], 0, RL_CON32_HOT(a), a, (long long)k);
@@ -380,12 +406,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                                           h->ev[nev][2], h->ev[nev][3], 0, RL_CON32_HOT(a), a, (long long)k);
                 ++nev;
             } else {
-                if (uni)
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true>), rgrid, dim3(kRodLoopBlock), 0, st,
-                                       RL_ROD32_HOT(a, rgrid), a, k, fl, round_start);
-                else
-                    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false>), rgrid, dim3(kRodLoopBlock), 0, st,
-                                       RL_ROD32_HOT(a, rgrid), a, k, fl, round_start);
+                launch_rod32_r(st, a, uni, dense, rgrid, k, fl, round_start);
                 if (wide)
                     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
                                        RL_CON32_HOT(a), a, k);

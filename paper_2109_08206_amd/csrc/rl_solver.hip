@@ -171,7 +171,7 @@ __device__ __forceinline__ void report_progress(unsigned long long *w, long long
 // (pptr, qptr, st, stq, geo, qgeo, grid size, n: 14 dwords, what the
 // hardware can preload into registers besides the argument block's address),
 // so that the first loads do not wait for the argument block.
-template <int MODE, bool UNI, bool BIL>
+template <int MODE, bool UNI, bool BIL, int R>
 __global__ void __launch_bounds__(kRodLoopBlock)
     k_rod(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const double2 *st, const double2 *stq,
           const double *__restrict__ geo, const double *__restrict__ qgeo, unsigned nblk, int n, SolveArgs a,
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const int done = MODE != kModeApply ? a.state->done : 0;
     // a compiler barrier keeps those loads ahead of the records'
     __asm__ volatile("" ::: "memory");
-    RodLoads L;
+    RodLoads<R> L;
     rod_load(pptr, qptr, st, stq, geo, qgeo, r, active, sub, L);
     if (BIL) rod_load_split(a, r, active, L);
     // and the rod's direction and mobility, which the reduction does not need
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kRodBlock) k_velocity(SolveArgs a, const doubl
     const int sub = threadIdx.x & (kRodLanes - 1);
     const int64_t r = (int64_t)blockIdx.x * (kRodBlock / kRodLanes) + (threadIdx.x / kRodLanes);
     const bool active = r < a.n;
-    RodLoads L;
+    RodLoads<> L;
     rod_load(a, r, active, sub, L);
     double f[3], m[3];
     rod_accumulate<kModeApply>(a, L, 0.0, f, m);
@@ -587,16 +587,43 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
 // rod kernel grid: a multiple of 8 so that each XCD gets a contiguous range of rods
 static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
 
-template <int MODE, bool BIL>
-static void launch_rod_t(hipStream_t st, const SolveArgs &a, bool uni, long long k)
+// the rod kernel with R rounds of records, with dispatch-stamped events when
+// e0 is set
+template <int MODE, bool BIL, int R>
+static void launch_rod_r(hipStream_t st, const SolveArgs &a, bool uni, long long k, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid(rod_grid(a.n));
-    if (uni)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL>), grid, dim3(kRodLoopBlock), 0, st,
-                           RL_ROD_HOT(a, grid), a, k);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL>), grid, dim3(kRodLoopBlock), 0, st,
-                           RL_ROD_HOT(a, grid), a, k);
+    if (e0) {
+        if (uni)
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL, R>), grid, dim3(kRodLoopBlock), 0, st, e0, e1,
+                                  0, RL_ROD_HOT(a, grid), a, k);
+        else
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL, R>), grid, dim3(kRodLoopBlock), 0, st, e0,
+                                  e1, 0, RL_ROD_HOT(a, grid), a, k);
+    } else {
+        if (uni)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL, R>), grid, dim3(kRodLoopBlock), 0, st,
+                               RL_ROD_HOT(a, grid), a, k);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL, R>), grid, dim3(kRodLoopBlock), 0, st,
+                               RL_ROD_HOT(a, grid), a, k);
+    }
+}
+
+// the loop kernel holds five rounds of records on dense contact systems
+// (the phases that run once per solve keep three, and so do general sets,
+// whose extra registers would leave two waves per SIMD at five rounds)
+template <int MODE, bool BIL>
+static void launch_rod_t(hipStream_t st, const SolveArgs &a, bool uni, long long k, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr)
+{
+    if constexpr (MODE == kModeLoop && !BIL) {
+        if (rod_rounds_for(a.n, a.nc) == kRodRoundsDense) {
+            launch_rod_r<MODE, BIL, kRodRoundsDense>(st, a, uni, k, e0, e1);
+            return;
+        }
+    }
+    launch_rod_r<MODE, BIL, kRodRounds>(st, a, uni, k, e0, e1);
 }
 
 template <int MODE>
@@ -650,15 +677,7 @@ template <bool BIL>
 static void record_sample_t(rl_ctx *h, int v, long long it, const SolveArgs &a, bool uni)
 {
     hipStream_t st = h->stream;
-    if (a.n > 0) {
-        const dim3 grid(rod_grid(a.n));
-        if (uni)
-            hipExtLaunchKernelGGL(k_rod<kModeLoop, true, BIL>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
-                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
-        else
-            hipExtLaunchKernelGGL(k_rod<kModeLoop, false, BIL>, grid, dim3(kRodLoopBlock), 0, st, h->ev[v][0],
-                                  h->ev[v][1], 0, RL_ROD_HOT(a, grid), a, (long long)it);
-    }
+    if (a.n > 0) launch_rod_t<kModeLoop, BIL>(st, a, uni, it, h->ev[v][0], h->ev[v][1]);
     if (con_wide(a))
         hipExtLaunchKernelGGL(k_con<kModeLoop, 256, 8, BIL>, dim3(a.gcon), dim3(256), 0, st, h->ev[v][2],
                               h->ev[v][3], 0, RL_CON_HOT(a), a, (long long)it);
