@@ -51,14 +51,14 @@ def con_kernel_name(nc: int, fp32: bool = False) -> str:
     """The constraint kernel's instantiation for nc constraints: the library
     sizes its grid at about 2,048 constraints per workgroup (at least one, at
     most 512, a multiple of 8) and takes 256 threads with 8 constraints each
-    once a workgroup's share exceeds 2,048, else 512 threads with 4 (FP64) or
-    2 (FP32)."""
+    (FP32) or 512 threads with 8 (FP64) once a workgroup's share exceeds
+    2,048, else 512 threads with 4 (FP64) or 2 (FP32)."""
     g = min(max((nc + 2047) // 2048, 1), 512)
     g = (g + 7) // 8 * 8
     wide = (nc + g - 1) // g > 2048
     if fp32:
         return "k_con32<256,8>" if wide else "k_con32<512,2>"
-    return "k_con<2,256,8>" if wide else "k_con<2,512,4>"
+    return "k_con<2,512,8>" if wide else "k_con<2,512,4>"
 
 
 def rod_rounds(n: int, nc: int) -> int:

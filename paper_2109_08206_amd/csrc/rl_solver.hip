@@ -636,9 +636,11 @@ static hipError_t launch_rod(hipStream_t st, const SolveArgs &a, bool uni, long 
 }
 
 // Constraint kernel shape: while a workgroup's share fits one round of four
-// per lane in 512 threads, that; beyond it, eight per lane in 256 threads
-// (measured: at 100k rods, 2,048 per group, 9.4 against 9.7 us; at 400k
-// rods, 3,637 per group, 48 against 40 us).
+// per lane in 512 threads, that; beyond it, eight per lane in 512 threads
+// (rounds of 4,096).  Measured on the band sweep: nematic 400k rods (3,673
+// per group) 31.8 -> 28.5 us and isotropic phi 0.08 (9,439 per group)
+// 95.6 -> 92.1 us against eight per lane in 256 threads; rounds of 3,072
+// (six per lane) were slower than either.
 static inline bool con_wide(const SolveArgs &a)
 {
     const int64_t per = (a.nc + a.gcon - 1) / a.gcon;
@@ -649,7 +651,7 @@ template <int MODE, bool BIL>
 static void launch_con_t(hipStream_t st, const SolveArgs &a, long long k)
 {
     if (con_wide(a))
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 256, 8, BIL>), dim3(a.gcon), dim3(256), 0, st, RL_CON_HOT(a),
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 512, 8, BIL>), dim3(a.gcon), dim3(512), 0, st, RL_CON_HOT(a),
                            a, k);
     else
         hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con<MODE, 512, 4, BIL>), dim3(a.gcon), dim3(512), 0, st, RL_CON_HOT(a),
@@ -679,7 +681,7 @@ static void record_sample_t(rl_ctx *h, int v, long long it, const SolveArgs &a, 
     hipStream_t st = h->stream;
     if (a.n > 0) launch_rod_t<kModeLoop, BIL>(st, a, uni, it, h->ev[v][0], h->ev[v][1]);
     if (con_wide(a))
-        hipExtLaunchKernelGGL(k_con<kModeLoop, 256, 8, BIL>, dim3(a.gcon), dim3(256), 0, st, h->ev[v][2],
+        hipExtLaunchKernelGGL(k_con<kModeLoop, 512, 8, BIL>, dim3(a.gcon), dim3(512), 0, st, h->ev[v][2],
                               h->ev[v][3], 0, RL_CON_HOT(a), a, (long long)it);
     else
         hipExtLaunchKernelGGL(k_con<kModeLoop, 512, 4, BIL>, dim3(a.gcon), dim3(512), 0, st, h->ev[v][2],
