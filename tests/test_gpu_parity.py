@@ -277,13 +277,28 @@ def _gpu_solve(gpu_lib, s, d, pr, cs, **kw):
     return g.cpu().numpy(), U.cpu().numpy(), info
 
 
-@pytest.mark.parametrize("which", ["small0", "small1", "lengths", "dense10k", "hub"])
+def _assert_dense(s, pr):
+    """The system takes the rod kernels' five rounds of records (above 8
+    constraints per rod), and some rods have more than the 20 records a side
+    that the rounds hold, so the loop past them runs too."""
+    assert pr.n > 8 * s.n
+    assert np.bincount(pr.pi, minlength=s.n).max() > 20 and np.bincount(pr.pj, minlength=s.n).max() > 20
+
+
+def _phi08():
+    # relaxed isotropic suspension at the precision workload's density
+    return rodsynth.relaxed_system(1500, seed=3, phi=0.08, length=(0.5, 1.5))
+
+
+@pytest.mark.parametrize("which", ["small0", "small1", "lengths", "dense10k", "hub", "phi08"])
 def test_solve_matches_oracle(gpu_lib, which):
     s = {"small0": lambda: rodsynth.cfg_small(0), "small1": lambda: rodsynth.cfg_small(1),
          "hub": lambda: rodsynth.cfg_hub(1),
          "lengths": lambda: rodsynth.make_system(1000, seed=1, phi=0.04, length=(0.5, 1.5)),
-         "dense10k": lambda: rodsynth.cfg_paper_scale(0, n=10_000)}[which]()
+         "dense10k": lambda: rodsynth.cfg_paper_scale(0, n=10_000), "phi08": _phi08}[which]()
     d, pr, cs = _oracle_setup(s)
+    if which == "phi08":
+        _assert_dense(s, pr)
     ref = oracle.bbpgd(d, _length(s), s.diam, s.eta, pr, cs, tol=1e-8)
     Uref = oracle.velocity(d, _length(s), s.diam, s.eta, pr, cs, ref.gamma, s.force)
     g, U, info = _gpu_solve(gpu_lib, s, d, pr, cs)
@@ -390,14 +405,17 @@ def test_solve_bitwise_repeatable(gpu_lib):
     assert np.array_equal(g1, g2) and np.array_equal(U1, U2)
 
 
-@pytest.mark.parametrize("which", ["small", "lengths", "hub"])
+@pytest.mark.parametrize("which", ["small", "lengths", "hub", "phi08"])
 def test_step_matches_oracle(gpu_lib, which):
     """"hub": one rod 4 long in a box of 10 (two cells per side) with 18
-    contacts on each side of its incidence lists."""
+    contacts on each side of its incidence lists; "phi08": 12 constraints
+    per rod."""
     s = {"small": lambda: rodsynth.cfg_small(5),
          "lengths": lambda: rodsynth.make_system(800, seed=6, phi=0.06, length=(0.5, 1.5)),
-         "hub": lambda: rodsynth.cfg_hub(1)}[which]()
+         "hub": lambda: rodsynth.cfg_hub(1), "phi08": _phi08}[which]()
     r = oracle.step_solve(s)
+    if which == "phi08":
+        _assert_dense(s, r.pairs)
     xo, qo = s.x.copy(), s.quat.copy()
     oracle.integrate(s.box, s.dt, r.U, xo, qo)
     x, quat = _t(s.x), _t(s.quat)
