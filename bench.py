@@ -50,10 +50,11 @@ def kernel_bytes(n: int, nc: int) -> dict:
 def con_kernel_name(nc: int, fp32: bool = False) -> str:
     """The constraint kernel's instantiation for nc constraints: the library
     sizes its grid at about 2,048 constraints per workgroup (at least one, at
-    most 512, a multiple of 8) and takes 256 threads with 8 constraints each
+    most 512, or 256 in the mixed-precision solve, a multiple of 8) and takes
+    256 threads with 8 constraints each
     (FP32) or 512 threads with 8 (FP64) once a workgroup's share exceeds
     2,048, else 512 threads with 4 (FP64) or 2 (FP32)."""
-    g = min(max((nc + 2047) // 2048, 1), 512)
+    g = min(max((nc + 2047) // 2048, 1), 256 if fp32 else 512)
     g = (g + 7) // 8 * 8
     wide = (nc + g - 1) // g > 2048
     if fp32:

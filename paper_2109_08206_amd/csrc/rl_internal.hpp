@@ -82,6 +82,7 @@ constexpr int kRodLoopBlock = RL_ROD_LOOP_BLOCK;  // workgroup of the single-sol
 #endif
 constexpr int kConBlock = RL_CON_BLOCK;     // constraint kernel workgroup
 constexpr int kConGridMax = RL_CON_GRIDMAX; // constraint kernel grid cap (grid-stride beyond)
+constexpr int kConGridMixed = 256;  // the same cap for the mixed-precision solve
 #ifndef RL_CON_PER_GROUP
 #define RL_CON_PER_GROUP 2048
 #endif

@@ -231,13 +231,36 @@ struct Con32Loads {
     int qp;
 };
 
-__device__ __forceinline__ void con32_load(const int32_t *qpos, const float *uP32, const float4 *st32,
-                                           const float *uQ32, int64_t c, Con32Loads &L)
+// One round of CPL constraints per lane: the list positions first, then the
+// records, then the gathers of u_Q.  Lanes past the end read constraint
+// `last` instead (their values go unused), so that no load sits behind a
+// branch: with a branch around each constraint's loads the compiler keeps
+// them in program order, and each gather of u_Q, which needs its list
+// position, waits for every load issued before it (the memory counter
+// completes in order), one memory round trip per constraint of the lane.
+// At 400k rods, phi 0.08: 88 -> 84 us per launch.
+template <int CB, int CPL>
+__device__ __forceinline__ void con32_load_round(const int32_t *qpos, const float *uP32, const float4 *st32,
+                                                 const float *uQ32, int64_t c0, int64_t last, Con32Loads (&L)[CPL])
 {
-    L.qp = qpos[c];
-    L.up = uP32[c];
-    L.s = st32[c];
-    L.uq = uQ32[L.qp];
+    int64_t cc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        const int64_t c = c0 + (int64_t)u * CB;
+        cc[u] = c < last ? c : last;
+        L[u].qp = qpos[cc[u]];
+    }
+    // compiler barriers keep the three groups in this order (the scheduler
+    // would otherwise wait for the first position right after its load)
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        L[u].up = uP32[cc[u]];
+        L[u].s = st32[cc[u]];
+    }
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) L[u].uq = uQ32[L[u].qp];
 }
 
 __device__ __forceinline__ void con32_update(const SolveArgs &a, int64_t c, const Con32Loads &L, float a32,
@@ -270,15 +293,18 @@ __global__ void __launch_bounds__(CB)
     const ConBand bd = con_band(blockIdx.x, nblk, nc, (int64_t)CPL * CB);
     const int64_t hi = bd.end;
     int64_t base = bd.first;
-    // the first round goes out before the flags are read; nothing in this
-    // launch writes the flags, so the early return is uniform
+    // the step length and the flags are read first (scalar loads), then the
+    // first round goes out before the flags are tested; nothing in this
+    // launch writes the flags, so the early return is uniform (a workgroup
+    // without constraints loads nothing; nc >= 1 whenever it has some)
+    const double a64 = alpha_buf[k & 1];
+    const int halt = a.state->done | a.state->refresh;  // both read, no branch
+    const int64_t last = (int64_t)nc - 1;
     int64_t c0 = base + threadIdx.x;
     Con32Loads L[CPL];
-#pragma unroll
-    for (int u = 0; u < CPL; ++u)
-        if (c0 + u * CB < hi) con32_load(qpos, uP32, s32, uQ32, c0 + u * CB, L[u]);
-    const double a64 = alpha_buf[k & 1];  // read with the flags (for nothing after a stop)
-    if (a.state->done || a.state->refresh) return;
+    if (base < hi) con32_load_round<CB, CPL>(qpos, uP32, s32, uQ32, c0, last, L);
+    __asm__ volatile("" ::: "memory");
+    if (halt) return;
     const float a32 = (float)a64;
     for (;;) {
 #pragma unroll
@@ -287,9 +313,7 @@ __global__ void __launch_bounds__(CB)
         base += bd.stride;
         if (base >= hi) break;
         c0 = base + threadIdx.x;
-#pragma unroll
-        for (int u = 0; u < CPL; ++u)
-            if (c0 + u * CB < hi) con32_load(qpos, uP32, s32, uQ32, c0 + u * CB, L[u]);
+        con32_load_round<CB, CPL>(qpos, uP32, s32, uQ32, c0, last, L);
     }
     block_total4<CB / 64>(p, lds);
     if (threadIdx.x == 0) partial_put(a.partial + (int64_t)(k & 1) * a.gcon * 4, a.gcon, blockIdx.x, p);

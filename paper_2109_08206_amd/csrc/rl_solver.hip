@@ -496,6 +496,11 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     // workgroup, so fewer and fuller groups make that sum cheaper), at most
     // kConGridMax, a multiple of 8 (XCDs)
     int64_t gc = std::min<int64_t>(std::max<int64_t>(grid_of(nc, kConPerGroup), 1), kConGridMax);
+    // The mixed-precision loop's constraint kernel runs best at one
+    // workgroup per CU: at 400k rods, phi 0.08, 68 us per launch from 256
+    // workgroups against 84 us from 512 (its FP64 refreshes take the same
+    // grid, and the rod kernel sums half the partials)
+    if (p.precision == RL_FP32_MIXED) gc = std::min<int64_t>(gc, kConGridMixed);
     s.gcon = (int)((gc + 7) / 8 * 8);
     const int64_t nb = nc > 0 ? nc : 1, rb = n > 0 ? n : 1;
     int32_t *pptr = (int32_t *)ws_get(h, kWsPptr, sizeof(int32_t) * (n + 1), &werr);
