@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bbpgd_rods100k.json")
 TRAFFIC_FILE_400K = os.path.join(ROOT, "profiles", "traffic_bbpgd_rods400k.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2109_08206_amd", "csrc", f)
-                  for f in ("rl_solver.hip", "rl_device.hpp", "rl_internal.hpp")]
+                  for f in ("rl_solver.hip", "rl_mixed.hip", "rl_device.hpp", "rl_internal.hpp")]
 
 
 def kernel_bytes(n: int, nc: int) -> dict:
