@@ -62,10 +62,10 @@ def con_kernel_name(nc: int, fp32: bool = False) -> str:
     return "k_con<2,512,8>" if wide else "k_con<2,512,4>"
 
 
-def rod_rounds(n: int, nc: int) -> int:
-    """Rounds of incidence records the loop's rod kernel holds in registers:
-    five above 8 constraints per rod (contact-only sets), else three."""
-    return 5 if nc > 8 * n else 3
+def rod_lanes(n: int, nc: int) -> int:
+    """Lanes per rod of the loop's rod kernel (three rounds of records each):
+    eight above 8 constraints per rod (contact-only sets), else four."""
+    return 8 if nc > 8 * n else 4
 
 
 def source_hash() -> str:
@@ -208,9 +208,9 @@ def form_precision(args, torch, rl, rodsynth) -> dict:
         prof = slv.profile_read()
         slv.close()
         kb = (kernel_bytes if prec == rl.FP64 else kernel_bytes32)(s.n, npairs)
-        rr = rod_rounds(s.n, npairs)
-        names = {"rod": f"k_rod<2,false,{rr}>", "con": con_kernel_name(npairs)} if prec == rl.FP64 else \
-            {"rod": f"k_rod32<false,{rr}>", "con": con_kernel_name(npairs, fp32=True)}
+        ln = rod_lanes(s.n, npairs)
+        names = {"rod": f"k_rod<2,false,3,{ln}>", "con": con_kernel_name(npairs)} if prec == rl.FP64 else \
+            {"rod": f"k_rod32<false,3,{ln}>", "con": con_kernel_name(npairs, fp32=True)}
         avg, kern = _kernel_summary(prof, kb, names)
         dom = max(avg, key=avg.get)
         ach = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
@@ -544,7 +544,7 @@ def form_dynamics(args, torch, rl, rodsynth) -> dict:
     kb = {"rod": 40 * n + 56 * nc + 56 * nq, "con": 60 * nc + 24 * nq}
     avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
            "con": prof["con_ms"] / max(1, prof["con_launches"])}
-    names = {"rod": "k_rod<2,true,gen,3>", "con": con_kernel_name(nc)[:-1] + ",gen>"}
+    names = {"rod": "k_rod<2,true,gen,3,4>", "con": con_kernel_name(nc)[:-1] + ",gen>"}
     dom = max(avg, key=avg.get)
     achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     return {
@@ -692,7 +692,7 @@ def main() -> int:
     kb = kernel_bytes(s.n, npairs)
     avg = {"rod": prof["rod_ms"] / max(1, prof["rod_launches"]),
            "con": prof["con_ms"] / max(1, prof["con_launches"])}
-    names = {"rod": f"k_rod<2,true,{rod_rounds(s.n, npairs)}>", "con": con_kernel_name(npairs)}
+    names = {"rod": f"k_rod<2,true,3,{rod_lanes(s.n, npairs)}>", "con": con_kernel_name(npairs)}
     dom = max(avg, key=avg.get)
     achieved = kb[dom] / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
     traffic = measured_traffic(dom)

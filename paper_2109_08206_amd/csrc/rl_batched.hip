@@ -336,15 +336,16 @@ static void launch_rod_b_r(hipStream_t st, const BatchArgs &b, bool uni, int i)
                            a.pptr, a.qptr, (const double2 *)a.st, (const double2 *)a.stq, a.geo, a.qgeo, b, i);
 }
 
-// As in the single solve, the loop kernel holds five rounds of records when
-// the batch as a whole is dense, in 256-thread groups (1,024-thread groups
-// leave 128 registers a lane, too few for five rounds).
+// The loop kernel holds five rounds of records when the batch as a whole is
+// dense (four lanes per rod, which the tile tables assume), in 256-thread
+// groups (1,024-thread groups leave 128 registers a lane, too few for five
+// rounds).
 template <int MODE, int RB>
 static hipError_t launch_rod_b(hipStream_t st, const BatchArgs &b, bool uni, int i)
 {
     if (b.nrb == 0) return hipSuccess;
     if constexpr (MODE == kModeLoop && RB == 256) {
-        if (rod_rounds_for(b.a.n, b.a.nc) == kRodRoundsDense) {
+        if (rod_dense(b.a.n, b.a.nc)) {
             launch_rod_b_r<MODE, RB, kRodRoundsDense>(st, b, uni, i);
             return hipGetLastError();
         }

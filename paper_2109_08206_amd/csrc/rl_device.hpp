@@ -310,25 +310,28 @@ __device__ __forceinline__ double gamma_free(double gam, double g, double alpha)
 }
 
 // Contact force f = sum +-gamma' e and moment arm sum m = sum +-gamma' s e of
-// rod r, split over the kRodLanes lanes of the rod and combined by a fixed
-// tree.  The torque on the rod is dir x m.  A lane takes the records sub,
-// sub + kRodLanes, ... of each side.  Its first R records of both sides
-// (R rounds) are loaded into registers together, before the step-length
-// wait; longer lists continue in a loop.  The registers stay live for the
+// rod r, split over the LN lanes of the rod and combined by a fixed tree.
+// The torque on the rod is dir x m.  A lane takes the records sub,
+// sub + LN, ... of each side.  Its first R records of both sides (R rounds)
+// are loaded into registers together, before the step-length wait; longer
+// lists continue in a loop.  The registers stay live for the
 // contact-velocity emission.  Records beyond the rounds are read after the
 // wait, read again for the emission (by then often evicted from the L2) and
 // hold up their workgroup, so the rounds should cover the rods with more
 // contacts than average; each round costs registers and so occupancy.
-// Three rounds (12 records a side, 4 waves per SIMD) for systems with a few
-// constraints per rod (the nematic suspension: 4.7 a side on average);
-// kRodRoundsDense = 5 (20 a side, 3 waves per SIMD) where the lists are
-// longer (isotropic phi 0.08 with lengths up to 1.5: 12 a side on average,
-// where three rounds re-read 22% of the records).
+// Four lanes and three rounds (12 records a side, 4 waves per SIMD) for
+// systems with a few constraints per rod (the nematic suspension: 4.7 a side
+// on average).  Where the lists are longer (isotropic phi 0.08 with lengths
+// up to 1.5: 12 a side on average, where 12 a lane-group re-read 22% of the
+// records) the single solves take eight lanes and three rounds (24 a side,
+// shorter chains per lane: rod kernel 150.5 -> 127.5 us at 400k rods, FP32
+// 94.3 -> 76.6 us), and the batched solve, whose tile tables assume four
+// lanes, five rounds (20 a side, 3 waves per SIMD).
 constexpr int kRodRounds = 3;
 constexpr int kRodRoundsDense = 5;
-// the rounds for a system of n rods and nc constraints: the dense count
-// above 8 constraints per rod
-inline int rod_rounds_for(int64_t n, int64_t nc) { return nc > 8 * n ? kRodRoundsDense : kRodRounds; }
+constexpr int kRodLanesDense = 8;
+// dense systems: above 8 constraints per rod
+inline bool rod_dense(int64_t n, int64_t nc) { return nc > 8 * n; }
 
 struct RodRec {
     double2 s, g0, g1;  // (gamma, g), (ex, ey), (ez, s)
@@ -362,7 +365,7 @@ __device__ __forceinline__ void rod_rec_load(const double2 *st, const double *ge
 // The arrays come as separate arguments so that a kernel can take them in
 // preloaded registers (leading kernel arguments) instead of from the
 // argument block.
-template <int R>
+template <int LN = kRodLanes, int R>
 __device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qptr, const double2 *st,
                                          const double2 *stq, const double *geo, const double *qgeo, int64_t r,
                                          bool active, int sub, RodLoads<R> &L)
@@ -377,8 +380,8 @@ __device__ __forceinline__ void rod_load(const int32_t *pptr, const int32_t *qpt
     L.qe = active ? qe : 0;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        rod_rec_load(st, geo, L.pb + i * kRodLanes, L.pe, L.p[i]);
-        rod_rec_load(stq, qgeo, L.qb + i * kRodLanes, L.qe, L.q[i]);
+        rod_rec_load(st, geo, L.pb + i * LN, L.pe, L.p[i]);
+        rod_rec_load(stq, qgeo, L.qb + i * LN, L.qe, L.q[i]);
     }
 }
 
@@ -418,32 +421,32 @@ __device__ __forceinline__ double gamma_of(double gam, double g, double alpha, i
     return gamma_prime<MODE>(gam, g, alpha);
 }
 
-template <int MODE, bool BIL, int R>
+template <int MODE, bool BIL, int R, int LN>
 __device__ __forceinline__ void rod_side(double sign, const double2 *st, const double *geo, int b, int e, int split,
                                          const RodRec *rr, double alpha, double f[3], double m[3])
 {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const int c = b + i * kRodLanes;
+        const int c = b + i * LN;
         if (c >= e) return;
         rod_add(sign, gamma_of<MODE, BIL>(rr[i].s.x, rr[i].s.y, alpha, c, split), rr[i].g0, rr[i].g1, f, m);
     }
-    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) {
+    for (int c = b + R * LN; c < e; c += LN) {
         const double2 sg = st[c];
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
         rod_add(sign, gamma_of<MODE, BIL>(sg.x, sg.y, alpha, c, split), gd[0], gd[1], f, m);
     }
 }
 
-template <int MODE, bool BIL = false, int R>
+template <int MODE, bool BIL = false, int LN = kRodLanes, int R>
 __device__ __forceinline__ void rod_accumulate(const SolveArgs &a, const RodLoads<R> &L, double alpha, double f[3],
                                                double m[3])
 {
     f[0] = f[1] = f[2] = m[0] = m[1] = m[2] = 0.0;
-    rod_side<MODE, BIL, R>(1.0, a.st, a.geo, L.pb, L.pe, L.ps, L.p, alpha, f, m);
-    rod_side<MODE, BIL, R>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.qs, L.q, alpha, f, m);
+    rod_side<MODE, BIL, R, LN>(1.0, a.st, a.geo, L.pb, L.pe, L.ps, L.p, alpha, f, m);
+    rod_side<MODE, BIL, R, LN>(-1.0, a.stq, a.qgeo, L.qb, L.qe, L.qs, L.q, alpha, f, m);
 #pragma unroll
-    for (int o = 1; o < kRodLanes; o <<= 1) {
+    for (int o = 1; o < LN; o <<= 1) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             f[d] += __shfl_xor(f[d], o, 64);
@@ -563,27 +566,27 @@ __device__ __forceinline__ double u_along(double2 g0, double2 g1, const double v
 // The lane's incidences in the same order as rod_accumulate: the first
 // rounds are still in registers, later ones are read again (moments after
 // the same lane read them).
-template <int R>
+template <int R, int LN>
 __device__ __forceinline__ void emit_side(double *u, const double *geo, int b, int e, const RodRec *rr,
                                           const double v[3], const double w[3])
 {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        if (b + i * kRodLanes >= e) return;
-        u[b + i * kRodLanes] = u_along(rr[i].g0, rr[i].g1, v, w);
+        if (b + i * LN >= e) return;
+        u[b + i * LN] = u_along(rr[i].g0, rr[i].g1, v, w);
     }
-    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) {
+    for (int c = b + R * LN; c < e; c += LN) {
         const double2 *gd = reinterpret_cast<const double2 *>(geo + 4 * (int64_t)c);
         u[c] = u_along(gd[0], gd[1], v, w);
     }
 }
 
-template <int R>
+template <int LN = kRodLanes, int R>
 __device__ __forceinline__ void rod_emit_u(const SolveArgs &a, const RodLoads<R> &L, const double v[3],
                                            const double w[3])
 {
-    emit_side<R>(a.uP, a.geo, L.pb, L.pe, L.p, v, w);
-    emit_side<R>(a.uQ, a.qgeo, L.qb, L.qe, L.q, v, w);
+    emit_side<R, LN>(a.uP, a.geo, L.pb, L.pe, L.p, v, w);
+    emit_side<R, LN>(a.uQ, a.qgeo, L.qb, L.qe, L.q, v, w);
 }
 
 struct ConLoadsU {

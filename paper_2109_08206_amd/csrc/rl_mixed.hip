@@ -27,7 +27,7 @@
 namespace rl {
 
 static inline unsigned grid_of(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
-static inline unsigned rod_grid32(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
+static inline unsigned rod_grid32(int64_t n, int ln) { return (grid_of(n, kRodLoopBlock / ln) + 7) / 8 * 8; }
 
 constexpr long long kInnerRoundCap = 4000;  // inner iterations before a forced refresh
 
@@ -65,9 +65,8 @@ __device__ __forceinline__ void rec32_load(const float4 *__restrict__ st, const 
 }
 
 // Records of each side held in registers across the step-length wait: as
-// in the FP64 rod kernel, three rounds where rods have a few constraints
-// and five on dense systems (rod_rounds_for); the FP32 records are half the
-// size of the FP64 ones, so five rounds keep 4 waves per SIMD.
+// in the FP64 rod kernel, three rounds over four lanes per rod where rods
+// have a few constraints and over eight lanes on dense systems (rod_dense).
 
 __device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3], float m[3])
 {
@@ -80,16 +79,16 @@ __device__ __forceinline__ void add32(float sign, float dp, float4 g, float f[3]
     m[2] += ds * g.z;
 }
 
-template <int R>
+template <int R, int LN>
 __device__ __forceinline__ void side32(float sign, const float4 *__restrict__ st, const float4 *__restrict__ geo,
                                        int b, int e, const Rec32 *rr, float a32, float f[3], float m[3])
 {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        if (b + i * kRodLanes >= e) return;
+        if (b + i * LN >= e) return;
         add32(sign, delta_prime(rr[i].s, a32), rr[i].g, f, m);
     }
-    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
+    for (int c = b + R * LN; c < e; c += LN) add32(sign, delta_prime(st[c], a32), geo[c], f, m);
 }
 
 __device__ __forceinline__ float u32_along(float4 g, const float v[3], const float w[3])
@@ -97,16 +96,16 @@ __device__ __forceinline__ float u32_along(float4 g, const float v[3], const flo
     return g.x * (v[0] + g.w * w[0]) + g.y * (v[1] + g.w * w[1]) + g.z * (v[2] + g.w * w[2]);
 }
 
-template <int R>
+template <int R, int LN>
 __device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__restrict__ geo, int b, int e,
                                        const Rec32 *rr, const float v[3], const float w[3])
 {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        if (b + i * kRodLanes >= e) return;
-        u[b + i * kRodLanes] = u32_along(rr[i].g, v, w);
+        if (b + i * LN >= e) return;
+        u[b + i * LN] = u32_along(rr[i].g, v, w);
     }
-    for (int c = b + R * kRodLanes; c < e; c += kRodLanes) u[c] = u32_along(geo[c], v, w);
+    for (int c = b + R * LN; c < e; c += LN) u[c] = u32_along(geo[c], v, w);
 }
 
 // Rod kernel of the inner FP32 iteration: the force of delta' on the rod,
@@ -114,7 +113,7 @@ __device__ __forceinline__ void emit32(float *__restrict__ u, const float4 *__re
 // form, as in the FP64 rod kernel).
 // The arrays of the first loads, the grid size and n lead the argument list
 // (14 dwords), so that they arrive in preloaded registers.
-template <bool UNI, int R>
+template <bool UNI, int R, int LN>
 __global__ void __launch_bounds__(kRodLoopBlock)
     k_rod32(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const float4 *s32, const float4 *sq32,
             const float4 *__restrict__ g32, const float4 *__restrict__ gq32, unsigned nblk, int n, SolveArgs a,
@@ -122,9 +121,9 @@ __global__ void __launch_bounds__(kRodLoopBlock)
 {
     __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     SolverState *st = a.state;
-    const int sub = threadIdx.x & (kRodLanes - 1);
+    const int sub = threadIdx.x & (LN - 1);
     const unsigned tile = xcd_tile(blockIdx.x, nblk);
-    const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const int64_t r = (int64_t)tile * (kRodLoopBlock / LN) + (threadIdx.x / LN);
     const bool active = r < n;
     // the previous iteration's partials (read for nothing on a first
     // iteration) and the flags first, then the offsets and the records, all
@@ -146,8 +145,8 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     Rec32 P[R], Q[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        rec32_load(s32, g32, pb + i * kRodLanes, pe, P[i]);
-        rec32_load(sq32, gq32, qb + i * kRodLanes, qe, Q[i]);
+        rec32_load(s32, g32, pb + i * LN, pe, P[i]);
+        rec32_load(sq32, gq32, qb + i * LN, qe, Q[i]);
     }
     // keeps the loads ahead of the flag test (see k_rod)
     __asm__ volatile("" ::: "memory");
@@ -195,10 +194,10 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     }
     const float a32 = (float)alpha;
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    side32<R>(1.f, a.st32, a.geo32, pb, pe, P, a32, f, m);
-    side32<R>(-1.f, a.stq32, a.qgeo32, qb, qe, Q, a32, f, m);
+    side32<R, LN>(1.f, a.st32, a.geo32, pb, pe, P, a32, f, m);
+    side32<R, LN>(-1.f, a.stq32, a.qgeo32, qb, qe, Q, a32, f, m);
 #pragma unroll
-    for (int o = 1; o < kRodLanes; o <<= 1) {
+    for (int o = 1; o < LN; o <<= 1) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             f[d] += __shfl_xor(f[d], o, 64);
@@ -221,8 +220,8 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const float md = dx * m[0] + dy * m[1] + dz * m[2];
     const float v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
     const float w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
-    emit32<R>(a.uP32, a.geo32, pb, pe, P, v, w);
-    emit32<R>(a.uQ32, a.qgeo32, qb, qe, Q, v, w);
+    emit32<R, LN>(a.uP32, a.geo32, pb, pe, P, v, w);
+    emit32<R, LN>(a.uQ32, a.qgeo32, qb, qe, Q, v, w);
 }
 
 struct Con32Loads {
@@ -331,34 +330,35 @@ __global__ void __launch_bounds__(CB)
 // 512 threads with 2 each
 static inline bool con32_wide(const SolveArgs &a) { return (a.nc + a.gcon - 1) / a.gcon > 2048; }
 
-// the FP32 rod kernel with R rounds of records, with dispatch-stamped events
-// when e0 is set
-template <int R>
-static void launch_rod32(hipStream_t st, const SolveArgs &a, bool uni, const dim3 &g, long long k, int fl,
-                         long long round_start, hipEvent_t e0, hipEvent_t e1)
+// the FP32 rod kernel with LN lanes per rod and R rounds of records, with
+// dispatch-stamped events when e0 is set
+template <int R, int LN>
+static void launch_rod32(hipStream_t st, const SolveArgs &a, bool uni, long long k, int fl, long long round_start,
+                         hipEvent_t e0, hipEvent_t e1)
 {
+    const dim3 g(rod_grid32(a.n, LN));
     if (e0) {
         if (uni)
-            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true, R>), g, dim3(kRodLoopBlock), 0, st, e0, e1, 0,
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true, R, LN>), g, dim3(kRodLoopBlock), 0, st, e0, e1, 0,
                                   RL_ROD32_HOT(a, g), a, k, fl, round_start);
         else
-            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false, R>), g, dim3(kRodLoopBlock), 0, st, e0, e1, 0,
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false, R, LN>), g, dim3(kRodLoopBlock), 0, st, e0, e1, 0,
                                   RL_ROD32_HOT(a, g), a, k, fl, round_start);
     } else {
         if (uni)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true, R>), g, dim3(kRodLoopBlock), 0, st, RL_ROD32_HOT(a, g),
-                               a, k, fl, round_start);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<true, R, LN>), g, dim3(kRodLoopBlock), 0, st,
+                               RL_ROD32_HOT(a, g), a, k, fl, round_start);
         else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false, R>), g, dim3(kRodLoopBlock), 0, st,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod32<false, R, LN>), g, dim3(kRodLoopBlock), 0, st,
                                RL_ROD32_HOT(a, g), a, k, fl, round_start);
     }
 }
 
-static void launch_rod32_r(hipStream_t st, const SolveArgs &a, bool uni, bool dense, const dim3 &g, long long k,
-                           int fl, long long round_start, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+static void launch_rod32_r(hipStream_t st, const SolveArgs &a, bool uni, bool dense, long long k, int fl,
+                           long long round_start, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
-    if (dense) launch_rod32<kRodRoundsDense>(st, a, uni, g, k, fl, round_start, e0, e1);
-    else launch_rod32<kRodRounds>(st, a, uni, g, k, fl, round_start, e0, e1);
+    if (dense) launch_rod32<kRodRounds, kRodLanesDense>(st, a, uni, k, fl, round_start, e0, e1);
+    else launch_rod32<kRodRounds, kRodLanes>(st, a, uni, k, fl, round_start, e0, e1);
 }
 
 int prepare_mixed(rl_ctx *h, SolveArgs &a)
@@ -402,9 +402,8 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
     const int every = p.check_every > 0 ? p.check_every : 32;
     long long k = 0, round_start = 0, launched = 0;
     bool first = true;
-    const dim3 rgrid(rod_grid32(a.n));
     const bool wide = con32_wide(a);
-    const bool dense = rod_rounds_for(a.n, a.nc) == kRodRoundsDense;
+    const bool dense = rod_dense(a.n, a.nc);
     while (!h->state_host->done) {
         if (launched > p.max_iter + 4 * every + 64) {
             set_error("rl_solve_lcp: mixed-precision loop did not stop");
@@ -421,7 +420,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                 for (int e = 0; e < 4; ++e)
                     if (!h->ev[nev][e]) RL_HIP(hipEventCreateWithFlags(&h->ev[nev][e], hipEventDisableSystemFence));
                 h->ev_iter[nev] = k;
-                launch_rod32_r(st, a, uni, dense, rgrid, k, fl, round_start, h->ev[nev][0], h->ev[nev][1]);
+                launch_rod32_r(st, a, uni, dense, k, fl, round_start, h->ev[nev][0], h->ev[nev][1]);
                 if (wide)
                     hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
                                           h->ev[nev][2], h->ev[nev][3], 0, RL_CON32_HOT(a), a, (long long)k);
@@ -430,7 +429,7 @@ int solve_mixed_impl(rl_ctx *h, SolveArgs &a, long long *refreshes)
                                           h->ev[nev][2], h->ev[nev][3], 0, RL_CON32_HOT(a), a, (long long)k);
                 ++nev;
             } else {
-                launch_rod32_r(st, a, uni, dense, rgrid, k, fl, round_start);
+                launch_rod32_r(st, a, uni, dense, k, fl, round_start);
                 if (wide)
                     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_con32<256, 8>), dim3(a.gcon), dim3(256), 0, st,
                                        RL_CON32_HOT(a), a, k);

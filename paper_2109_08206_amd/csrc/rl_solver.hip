@@ -171,7 +171,7 @@ __device__ __forceinline__ void report_progress(unsigned long long *w, long long
 // (pptr, qptr, st, stq, geo, qgeo, grid size, n: 14 dwords, what the
 // hardware can preload into registers besides the argument block's address),
 // so that the first loads do not wait for the argument block.
-template <int MODE, bool UNI, bool BIL, int R>
+template <int MODE, bool UNI, bool BIL, int R, int LN>
 __global__ void __launch_bounds__(kRodLoopBlock)
     k_rod(const int32_t *__restrict__ pptr, const int32_t *__restrict__ qptr, const double2 *st, const double2 *stq,
           const double *__restrict__ geo, const double *__restrict__ qgeo, unsigned nblk, int n, SolveArgs a,
@@ -179,9 +179,9 @@ __global__ void __launch_bounds__(kRodLoopBlock)
 {
     __shared__ double lds[kRodLoopBlock / 64 + 1][4];
     double alpha = 0.0;
-    const int sub = threadIdx.x & (kRodLanes - 1);
+    const int sub = threadIdx.x & (LN - 1);
     const unsigned tile = xcd_tile(blockIdx.x, nblk);
-    const int64_t r = (int64_t)tile * (kRodLoopBlock / kRodLanes) + (threadIdx.x / kRodLanes);
+    const int64_t r = (int64_t)tile * (kRodLoopBlock / LN) + (threadIdx.x / LN);
     const bool active = r < n;
     // The previous iteration's partials, the inputs of the step rule and the
     // stop flag go out first (the partials are read for nothing at k = 0),
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     // a compiler barrier keeps those loads ahead of the records'
     __asm__ volatile("" ::: "memory");
     RodLoads<R> L;
-    rod_load(pptr, qptr, st, stq, geo, qgeo, r, active, sub, L);
+    rod_load<LN>(pptr, qptr, st, stq, geo, qgeo, r, active, sub, L);
     if (BIL) rod_load_split(a, r, active, L);
     // and the rod's direction and mobility, which the reduction does not need
     const int64_t rr = active ? r : 0;
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
         }
     }
     double f[3], m[3];
-    rod_accumulate<MODE, BIL>(a, L, alpha, f, m);
+    rod_accumulate<MODE, BIL, LN>(a, L, alpha, f, m);
     if (!active) return;
     // translation a_perp f + (a_par - a_perp)(d.f) d; rotation Omega =
     // r_perp dir x m (normal to the axis) and Omega x dir = r_perp (m - (d.m) d)
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(kRodLoopBlock)
     const double md = dx * m[0] + dy * m[1] + dz * m[2];
     const double v[3] = {aperp * f[0] + fd * dx, aperp * f[1] + fd * dy, aperp * f[2] + fd * dz};
     const double w[3] = {rperp * (m[0] - md * dx), rperp * (m[1] - md * dy), rperp * (m[2] - md * dz)};
-    rod_emit_u(a, L, v, w);
+    rod_emit_u<LN>(a, L, v, w);
 }
 
 
@@ -589,46 +589,49 @@ int prepare_solve(rl_ctx *h, int64_t n, const double *dir, const double *len, do
     (const int32_t *)(a).qpos, (const double *)(a).uP, (const double *)(a).qv, (const double2 *)(a).st, \
         (const double *)(a).uQ, (int)(a).nc, (unsigned)(a).gcon, (const double *)(a).alpha_buf
 
-// rod kernel grid: a multiple of 8 so that each XCD gets a contiguous range of rods
-static inline unsigned rod_grid(int64_t n) { return (grid_of(n, kRodLoopBlock / kRodLanes) + 7) / 8 * 8; }
+// rod kernel grid for LN lanes per rod: a multiple of 8 so that each XCD gets a
+// contiguous range of rods
+static inline unsigned rod_grid(int64_t n, int ln = kRodLanes)
+{
+    return (grid_of(n, kRodLoopBlock / ln) + 7) / 8 * 8;
+}
 
-// the rod kernel with R rounds of records, with dispatch-stamped events when
-// e0 is set
-template <int MODE, bool BIL, int R>
+// the rod kernel with LN lanes per rod and R rounds of records, with
+// dispatch-stamped events when e0 is set
+template <int MODE, bool BIL, int R, int LN>
 static void launch_rod_r(hipStream_t st, const SolveArgs &a, bool uni, long long k, hipEvent_t e0, hipEvent_t e1)
 {
-    const dim3 grid(rod_grid(a.n));
+    const dim3 grid(rod_grid(a.n, LN));
     if (e0) {
         if (uni)
-            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL, R>), grid, dim3(kRodLoopBlock), 0, st, e0, e1,
-                                  0, RL_ROD_HOT(a, grid), a, k);
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL, R, LN>), grid, dim3(kRodLoopBlock), 0, st,
+                                  e0, e1, 0, RL_ROD_HOT(a, grid), a, k);
         else
-            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL, R>), grid, dim3(kRodLoopBlock), 0, st, e0,
-                                  e1, 0, RL_ROD_HOT(a, grid), a, k);
+            hipExtLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL, R, LN>), grid, dim3(kRodLoopBlock), 0, st,
+                                  e0, e1, 0, RL_ROD_HOT(a, grid), a, k);
     } else {
         if (uni)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL, R>), grid, dim3(kRodLoopBlock), 0, st,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, true, BIL, R, LN>), grid, dim3(kRodLoopBlock), 0, st,
                                RL_ROD_HOT(a, grid), a, k);
         else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL, R>), grid, dim3(kRodLoopBlock), 0, st,
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rod<MODE, false, BIL, R, LN>), grid, dim3(kRodLoopBlock), 0, st,
                                RL_ROD_HOT(a, grid), a, k);
     }
 }
 
-// the loop kernel holds five rounds of records on dense contact systems
-// (the phases that run once per solve keep three, and so do general sets,
-// whose extra registers would leave two waves per SIMD at five rounds)
+// the loop kernel takes eight lanes per rod on dense contact systems (the
+// phases that run once per solve keep four, and so do general sets)
 template <int MODE, bool BIL>
 static void launch_rod_t(hipStream_t st, const SolveArgs &a, bool uni, long long k, hipEvent_t e0 = nullptr,
                          hipEvent_t e1 = nullptr)
 {
     if constexpr (MODE == kModeLoop && !BIL) {
-        if (rod_rounds_for(a.n, a.nc) == kRodRoundsDense) {
-            launch_rod_r<MODE, BIL, kRodRoundsDense>(st, a, uni, k, e0, e1);
+        if (rod_dense(a.n, a.nc)) {
+            launch_rod_r<MODE, BIL, kRodRounds, kRodLanesDense>(st, a, uni, k, e0, e1);
             return;
         }
     }
-    launch_rod_r<MODE, BIL, kRodRounds>(st, a, uni, k, e0, e1);
+    launch_rod_r<MODE, BIL, kRodRounds, kRodLanes>(st, a, uni, k, e0, e1);
 }
 
 template <int MODE>

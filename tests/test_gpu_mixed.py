@@ -43,15 +43,16 @@ def _solve(rl, s, d, pr, cs, precision, **kw):
 @pytest.mark.parametrize("which", ["small", "lengths", "dense10k", "hub", "phi08"])
 def test_mixed_matches_oracle(gpu_lib, which):
     """"phi08": a relaxed isotropic suspension at 12 constraints per rod
-    (five rounds of records in the FP32 rod kernel, and rods with more than
-    the 20 records a side that they hold)."""
+    (the FP32 rod kernel's dense form, eight lanes per rod with three rounds
+    of records each, and rods with more than the 24 records a side that
+    they hold)."""
     s = {"small": lambda: rodsynth.cfg_small(0), "hub": lambda: rodsynth.cfg_hub(1),
          "lengths": lambda: rodsynth.make_system(1000, seed=1, phi=0.04, length=(0.5, 1.5)),
          "dense10k": lambda: rodsynth.cfg_paper_scale(0, n=10_000),
          "phi08": lambda: rodsynth.relaxed_system(1500, seed=3, phi=0.08, length=(0.5, 1.5))}[which]()
     d, pr, cs = _setup(s)
     if which == "phi08":
-        assert pr.n > 8 * s.n and np.bincount(pr.pi, minlength=s.n).max() > 20
+        assert pr.n > 8 * s.n and np.bincount(pr.pi, minlength=s.n).max() > 24
     ref = oracle.bbpgd(d, _length(s), s.diam, s.eta, pr, cs, tol=1e-8)
     Uref = oracle.velocity(d, _length(s), s.diam, s.eta, pr, cs, ref.gamma, s.force)
     g, U, info = _solve(gpu_lib, s, d, pr, cs, gpu_lib.FP32_MIXED)

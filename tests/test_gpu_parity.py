@@ -278,11 +278,12 @@ def _gpu_solve(gpu_lib, s, d, pr, cs, **kw):
 
 
 def _assert_dense(s, pr):
-    """The system takes the rod kernels' five rounds of records (above 8
-    constraints per rod), and some rods have more than the 20 records a side
-    that the rounds hold, so the loop past them runs too."""
+    """The system takes the rod kernels' dense form (above 8 constraints per
+    rod: eight lanes per rod, three rounds of records each), and some rods
+    have more than the 24 records a side that the rounds hold, so the loop
+    past them runs too."""
     assert pr.n > 8 * s.n
-    assert np.bincount(pr.pi, minlength=s.n).max() > 20 and np.bincount(pr.pj, minlength=s.n).max() > 20
+    assert np.bincount(pr.pi, minlength=s.n).max() > 24 and np.bincount(pr.pj, minlength=s.n).max() > 24
 
 
 def _phi08():
